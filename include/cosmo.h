@@ -1,0 +1,134 @@
+/*
+ * cosmo.h -- C ABI of libcosmo.so: batched, differentiable LambdaCDM+radiation
+ * distances on MI355X (gfx950), after Karchev, "Analytic auto-differentiable
+ * LambdaCDM cosmography" (arXiv:2212.01937).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array arguments are DEVICE pointers owned by the caller.  The library keeps
+ *    no per-call state, never frees caller memory and is safe to call from several
+ *    host threads.  The only library-owned device memory is a constant table of
+ *    quadrature nodes, written once at first use.
+ *  - Calls enqueue asynchronously on `stream` (a hipStream_t passed as void*;
+ *    NULL is the default stream) and return a cosmo_status.  Argument errors
+ *    (NULL pointers, negative sizes, unknown kind/dtype, workspace too small) are
+ *    detected synchronously on the host and nothing is enqueued.  Launch failures
+ *    return COSMO_E_HIP.  Per-cosmology domain problems never fail the call: they
+ *    write NaN to the affected outputs and set bits in the optional `info` array.
+ *  - Cosmological parameters are FP64 rows (H0 [km/s/Mpc], Om0, OL0, Or0); the
+ *    curvature follows from the closure Ok0 = 1 - Om0 - OL0 - Or0 (sec. 2.1).
+ *    E^2(z) = Or0 (1+z)^4 + Om0 (1+z)^3 + Ok0 (1+z)^2 + OL0 (eq. 2.2).
+ *  - Redshifts z (> -1; all outputs are for the interval from 0 to z) and the
+ *    outputs use the dtype argument: COSMO_F32 (float) or COSMO_F64 (double).
+ *    Whatever the dtype, the per-cosmology root finding, the root Jacobian and
+ *    the parameter-gradient reductions run in FP64.
+ *  - Units: distances in Mpc, time in Gyr, distance modulus in magnitudes
+ *    (c = 299792.458 km/s, 1 Mpc = 3.0856775814913673e19 km, 1 Gyr = 3.15576e16 s).
+ */
+#ifndef COSMO_H
+#define COSMO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    COSMO_OK = 0,
+    COSMO_E_ARG = -1,       /* NULL pointer, negative size, bad stride          */
+    COSMO_E_KIND = -2,      /* unknown cosmo_kind                                */
+    COSMO_E_DTYPE = -3,     /* unknown cosmo_dtype                               */
+    COSMO_E_HIP = -4,       /* a HIP runtime call or kernel launch failed       */
+    COSMO_E_WORKSPACE = -5  /* workspace too small (see cosmo_workspace_size)   */
+} cosmo_status;
+
+typedef enum { COSMO_F32 = 0, COSMO_F64 = 1 } cosmo_dtype;
+
+/* Observables (sec. 2.1.1).  All from z1 = 0 to z2 = z.
+ *  DC: comoving distance chi (eq. 2.3), Mpc
+ *  DM: transverse comoving distance, curvature-modified chi, Mpc
+ *  DL: luminosity distance (1+z) D_M, Mpc
+ *  MU: distance modulus 5 log10(D_L / 10 pc) (fn. 22), mag
+ *  T : time coordinate / lookback time t(0, z) (eq. 2.4), Gyr
+ *  X : absorption distance d_abs (eq. 2.5), Mpc
+ *  DA: angular-diameter distance D_M / (1+z), Mpc                                */
+typedef enum {
+    COSMO_DC = 0, COSMO_DM = 1, COSMO_DL = 2, COSMO_MU = 3,
+    COSMO_T = 4, COSMO_X = 5, COSMO_DA = 6
+} cosmo_kind;
+
+/* Bits of the per-cosmology `info` word (int32).                                */
+#define COSMO_INFO_CUBIC          0x0001 /* Or0 == 0: radiationless cubic (app. B.1) */
+#define COSMO_INFO_QUARTIC        0x0002 /* Or0 > 0: quartic E^2 (eqs. 3.7-3.9)     */
+#define COSMO_INFO_THREE_REAL     0x0004 /* cubic factor has three real roots        */
+#define COSMO_INFO_YELLOW         0x0008 /* complex pair with Re(r) > 0 (Fig. 1)     */
+#define COSMO_INFO_RED            0x0010 /* a real root on the integration path: no Big Bang (Fig. 1, sec. 3) */
+#define COSMO_INFO_DOMAIN         0x0020 /* outside the method (degree < 3, no negative real root, ...): NaN */
+#define COSMO_INFO_ROOT_NOCONV    0x0040 /* root polishing hit its iteration cap     */
+#define COSMO_INFO_NEAR_MULTIROOT 0x0080 /* two roots closer than 1e-4 (relative): gradients by quadrature */
+#define COSMO_INFO_X_QUADRATURE   0x0100 /* some X lanes used the Gauss-Legendre route */
+
+/* Number of bytes of device workspace that cosmo_distance / cosmo_distance_vjp
+ * need for this problem size.  A NULL workspace is also accepted by those calls:
+ * the library then takes stream-ordered memory from HIP's default pool for the
+ * duration of the call (hipMallocAsync / hipFreeAsync on `stream`).              */
+int cosmo_workspace_size(int64_t n_cosmo, int64_t n_z, size_t *bytes);
+
+/* cosmo_roots -- factorisation of E^2 (sec. 3, eq. 3.2; fn. 12/13), FP64.
+ * params: [n_cosmo][4] FP64 (H0, Om0, OL0, Or0).
+ * roots : [n_cosmo][4][2] FP64 out, z-roots r_j as (re, im).  Slots 0..2 are
+ *         the roots of the cubic factor (slot 0 real; slots 1, 2 a conjugate pair
+ *         with Im >= 0 first, or two further real roots), slot 3 the radiation
+ *         root (the real root of largest modulus when Or0 > 0; NaN when Or0 == 0).
+ * info  : [n_cosmo] int32 out, nullable.                                        */
+int cosmo_roots(const double *params, int64_t n_cosmo, double *roots, int32_t *info,
+                void *stream);
+
+/* Carlson symmetric integrals (eqs. 2.6-2.9) for complex arguments, by the
+ * duplication method; element-wise over n.  Every operand is interleaved
+ * (re, im) of the given dtype, length 2n.  Arguments must avoid the cut of the
+ * definitions (non-positive reals; R_F and R_D allow one zero argument); for a
+ * negative real p (R_J) or y (R_C) the Cauchy principal value is returned.      */
+int carlson_rf(cosmo_dtype dt, int64_t n, const void *x, const void *y, const void *z,
+               void *out, void *stream);
+int carlson_rd(cosmo_dtype dt, int64_t n, const void *x, const void *y, const void *z,
+               void *out, void *stream);
+int carlson_rj(cosmo_dtype dt, int64_t n, const void *x, const void *y, const void *z,
+               const void *p, void *out, void *stream);
+int carlson_rc(cosmo_dtype dt, int64_t n, const void *x, const void *y, void *out,
+               void *stream);
+
+/* cosmo_distance -- forward evaluation, sec. 3.1 eqs. 3.7-3.9 (Or0 > 0) and
+ * app. B.1 eqs. B.1-B.3 (Or0 == 0), curvature transform and observables.
+ * z     : element (c, i) at z[c * z_cosmo_stride + i]; z_cosmo_stride = 0 shares
+ *         one row of n_z redshifts between all cosmologies.
+ * out   : [n_cosmo][n_z] of dtype, row-major.
+ * info  : [n_cosmo] int32, nullable.
+ * workspace / workspace_bytes: see cosmo_workspace_size (NULL allowed).          */
+int cosmo_distance(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo,
+                   const void *z, int64_t n_z, int64_t z_cosmo_stride, void *out,
+                   int32_t *info, void *workspace, size_t workspace_bytes, void *stream);
+
+/* cosmo_distance_vjp -- adjoint of cosmo_distance for a cotangent `cot`
+ * ([n_cosmo][n_z], dtype).  Gradients through the Carlson derivatives (eqs.
+ * 2.10-2.12) and the differentiated root finding (app. A, eqs. A.1-A.4); the
+ * z-gradient by the fundamental theorem of calculus.
+ * grad_params: [n_cosmo][4] FP64 out, sum over z of cot * d out/d(H0, Om0, OL0,
+ *              Or0); overwritten; nullable.
+ * grad_z     : dtype out, nullable; [n_z] summed over cosmologies when
+ *              z_cosmo_stride == 0, else [n_cosmo][n_z]; overwritten.           */
+int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params,
+                       int64_t n_cosmo, const void *z, int64_t n_z, int64_t z_cosmo_stride,
+                       const void *cot, double *grad_params, void *grad_z, int32_t *info,
+                       void *workspace, size_t workspace_bytes, void *stream);
+
+/* Library version string (static storage). */
+const char *cosmo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COSMO_H */

@@ -41,6 +41,7 @@ def _load():
         lib.oracle_gk15_panel.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                           ctypes.c_double]
         lib.oracle_gk15_panel.restype = ctypes.c_double
+        lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -108,6 +109,11 @@ def carlson(which, x, y, z=None, p=None):
     if rc != 0:
         raise ValueError("oracle_carlson rejected its arguments")
     return out.view(np.complex128)
+
+
+def threads():
+    """OpenMP threads the oracle uses by default."""
+    return int(_load().oracle_threads())
 
 
 def gk15_panel(rule, power, a, b):

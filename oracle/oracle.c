@@ -328,6 +328,16 @@ int oracle_eval(int kind, const double *params, long n_cosmo, const double *z, l
     return 0;
 }
 
+/* Number of OpenMP threads oracle_eval uses by default. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* E(z) itself (for the fundamental-theorem pins in the tests). */
 double oracle_E(const double *prm, double z)
 {

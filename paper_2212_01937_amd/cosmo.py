@@ -1,0 +1,232 @@
+"""ctypes binding of libcosmo.so -- the C ABI of include/cosmo.h -- on torch tensors.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of csrc/.  Entry points keep the C names (cosmo_roots, carlson_rf,
+carlson_rd, carlson_rj, carlson_rc, cosmo_distance, cosmo_distance_vjp);
+`distance` wraps the forward/adjoint pair in a torch.autograd.Function.
+
+Device tensors are passed as raw pointers together with the current torch
+stream, so calls are stream-ordered with surrounding torch work.  There is no
+CPU implementation behind these functions: if the shared library is missing or
+no GPU is visible they raise.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcosmo.so")
+
+KINDS = {"DC": 0, "DM": 1, "DL": 2, "MU": 3, "T": 4, "X": 5, "DA": 6}
+DTYPES = {torch.float32: 0, torch.float64: 1}
+STATUS = {0: "COSMO_OK", -1: "COSMO_E_ARG", -2: "COSMO_E_KIND", -3: "COSMO_E_DTYPE",
+          -4: "COSMO_E_HIP", -5: "COSMO_E_WORKSPACE"}
+INFO = {"CUBIC": 0x1, "QUARTIC": 0x2, "THREE_REAL": 0x4, "YELLOW": 0x8, "RED": 0x10,
+        "DOMAIN": 0x20, "ROOT_NOCONV": 0x40, "NEAR_MULTIROOT": 0x80, "X_QUADRATURE": 0x100}
+
+# every function declared in include/cosmo.h
+EXPORTS = ("cosmo_workspace_size", "cosmo_roots", "carlson_rf", "carlson_rd", "carlson_rj",
+           "carlson_rc", "cosmo_distance", "cosmo_distance_vjp", "cosmo_version")
+
+_lib = None
+
+
+class CosmoError(RuntimeError):
+    pass
+
+
+def load():
+    """Load libcosmo.so (built by paper_2212_01937_amd.build).  Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise CosmoError(f"{LIB_PATH} is missing: build it with `python -m paper_2212_01937_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32p = ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p
+    lib.cosmo_workspace_size.argtypes = [i64, i64, ctypes.POINTER(ctypes.c_size_t)]
+    lib.cosmo_roots.argtypes = [vp, i64, vp, i32p, vp]
+    for n in ("carlson_rf", "carlson_rd"):
+        getattr(lib, n).argtypes = [ctypes.c_int, i64, vp, vp, vp, vp, vp]
+    lib.carlson_rj.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp, vp, vp]
+    lib.carlson_rc.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp]
+    lib.cosmo_distance.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, i32p, vp,
+                                   ctypes.c_size_t, vp]
+    lib.cosmo_distance_vjp.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, vp,
+                                       i32p, vp, ctypes.c_size_t, vp]
+    for n in EXPORTS[:-1]:
+        getattr(lib, n).restype = ctypes.c_int
+    lib.cosmo_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise CosmoError(f"{what} failed: {STATUS.get(rc, rc)}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(dev):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _need_gpu(t, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise CosmoError(f"{name} must be a CUDA (HIP) tensor; this library has no CPU path")
+
+
+def _params(params):
+    _need_gpu(params, "params")
+    if params.dtype != torch.float64:
+        raise CosmoError("params must be float64 (H0, Om0, OL0, Or0) rows")
+    p = params.reshape(-1, 4)
+    return p if p.is_contiguous() else p.contiguous()
+
+
+def _z_layout(z, n_cosmo):
+    """Returns (z_contig, n_z, stride, shared)."""
+    _need_gpu(z, "z")
+    if z.dtype not in DTYPES:
+        raise CosmoError("z must be float32 or float64")
+    if z.dim() == 1:
+        zc = z if z.is_contiguous() else z.contiguous()
+        return zc, zc.shape[0], 0, True
+    if z.dim() == 2 and z.shape[0] == n_cosmo:
+        zc = z if (z.stride(1) == 1) else z.contiguous()
+        return zc, zc.shape[1], zc.stride(0), False
+    raise CosmoError("z must be [n_z] (shared) or [n_cosmo, n_z]")
+
+
+def workspace_size(n_cosmo, n_z):
+    lib = load()
+    b = ctypes.c_size_t(0)
+    _check(lib.cosmo_workspace_size(int(n_cosmo), int(n_z), ctypes.byref(b)), "cosmo_workspace_size")
+    return int(b.value)
+
+
+def _workspace(n_cosmo, n_z, dev):
+    return torch.empty(max(workspace_size(n_cosmo, n_z), 1), dtype=torch.uint8, device=dev)
+
+
+def cosmo_roots(params, with_info=True):
+    """Roots of E^2(z) per cosmology: complex128 [n, 4] (slot 3: radiation root, NaN if
+    Or0 == 0) and int32 info flags."""
+    lib = load()
+    p = _params(params)
+    n = p.shape[0]
+    out = torch.empty((n, 4, 2), dtype=torch.float64, device=p.device)
+    info = torch.empty(n, dtype=torch.int32, device=p.device)
+    with torch.cuda.device(p.device):
+        _check(lib.cosmo_roots(_ptr(p), n, _ptr(out), _ptr(info), _stream(p.device)), "cosmo_roots")
+    r = torch.view_as_complex(out)
+    return (r, info) if with_info else r
+
+
+def _carlson(name, args):
+    lib = load()
+    dev = args[0].device
+    cdt = args[0].dtype
+    if cdt not in (torch.complex64, torch.complex128):
+        raise CosmoError("Carlson arguments must be complex64 or complex128 tensors")
+    n = args[0].numel()
+    conv = []
+    for a in args:
+        _need_gpu(a, name)
+        if a.dtype != cdt or a.numel() != n:
+            raise CosmoError(f"{name}: arguments must share dtype and size")
+        conv.append(torch.view_as_real(a.reshape(-1).contiguous()))
+    out = torch.empty(n, dtype=cdt, device=dev)
+    ro = torch.view_as_real(out)
+    dt = 0 if cdt == torch.complex64 else 1
+    with torch.cuda.device(dev):
+        rc = getattr(lib, name)(dt, n, *[_ptr(a) for a in conv], _ptr(ro), _stream(dev))
+    _check(rc, name)
+    return out.reshape(args[0].shape)
+
+
+def carlson_rf(x, y, z):
+    return _carlson("carlson_rf", (x, y, z))
+
+
+def carlson_rd(x, y, z):
+    return _carlson("carlson_rd", (x, y, z))
+
+
+def carlson_rj(x, y, z, p):
+    return _carlson("carlson_rj", (x, y, z, p))
+
+
+def carlson_rc(x, y):
+    return _carlson("carlson_rc", (x, y))
+
+
+def cosmo_distance(kind, params, z, info=False, workspace=None):
+    """Observable `kind` ('DC','DM','DL','MU','T','X','DA') of shape [n_cosmo, n_z],
+    in z's dtype.  With info=True also returns the int32 per-cosmology flags."""
+    lib = load()
+    p = _params(params)
+    n_c = p.shape[0]
+    zc, n_z, stride, _ = _z_layout(z, n_c)
+    if zc.device != p.device:
+        raise CosmoError("params and z must be on the same device")
+    out = torch.empty((n_c, n_z), dtype=zc.dtype, device=p.device)
+    inf = torch.empty(n_c, dtype=torch.int32, device=p.device) if info else None
+    ws = workspace if workspace is not None else _workspace(n_c, n_z, p.device)
+    with torch.cuda.device(p.device):
+        rc = lib.cosmo_distance(KINDS[kind], DTYPES[zc.dtype], _ptr(p), n_c, _ptr(zc), n_z, stride,
+                                _ptr(out), _ptr(inf), _ptr(ws), ws.numel(), _stream(p.device))
+    _check(rc, "cosmo_distance")
+    return (out, inf) if info else out
+
+
+def cosmo_distance_vjp(kind, params, z, cot, want_params=True, want_z=True, info=False, workspace=None):
+    """Adjoint: (grad_params [n_cosmo, 4] float64 or None, grad_z like z or None)."""
+    lib = load()
+    p = _params(params)
+    n_c = p.shape[0]
+    zc, n_z, stride, shared = _z_layout(z, n_c)
+    _need_gpu(cot, "cot")
+    c = cot.to(zc.dtype).reshape(n_c, n_z).contiguous()
+    gp = torch.empty((n_c, 4), dtype=torch.float64, device=p.device) if want_params else None
+    gz = None
+    if want_z:
+        gz = torch.empty(n_z if shared else (n_c, n_z), dtype=zc.dtype, device=p.device)
+    inf = torch.empty(n_c, dtype=torch.int32, device=p.device) if info else None
+    ws = workspace if workspace is not None else _workspace(n_c, n_z, p.device)
+    with torch.cuda.device(p.device):
+        rc = lib.cosmo_distance_vjp(KINDS[kind], DTYPES[zc.dtype], _ptr(p), n_c, _ptr(zc), n_z, stride,
+                                    _ptr(c), _ptr(gp), _ptr(gz), _ptr(inf), _ptr(ws), ws.numel(),
+                                    _stream(p.device))
+    _check(rc, "cosmo_distance_vjp")
+    return (gp, gz, inf) if info else (gp, gz)
+
+
+class _Distance(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, kind, params, z):
+        ctx.kind = kind
+        ctx.save_for_backward(params, z)
+        return cosmo_distance(kind, params.detach(), z.detach())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        params, z = ctx.saved_tensors
+        gp, gz = cosmo_distance_vjp(ctx.kind, params.detach(), z.detach(), grad_out,
+                                    want_params=ctx.needs_input_grad[1], want_z=ctx.needs_input_grad[2])
+        if gz is not None:
+            gz = gz.reshape(z.shape)
+        return None, gp.reshape(params.shape) if gp is not None else None, gz
+
+
+def distance(kind, params, z):
+    """Differentiable observable: autograd through cosmo_distance / cosmo_distance_vjp."""
+    return _Distance.apply(kind, params, z)
+
+
+def version():
+    return load().cosmo_version().decode()

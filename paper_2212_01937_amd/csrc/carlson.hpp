@@ -1,0 +1,437 @@
+// carlson.hpp -- Carlson symmetric elliptic integrals R_F, R_D, R_J, R_C
+// (definitions: sec. 2.2, eqs. 2.6-2.9) by the duplication method the paper
+// relies on ([10] in sec. 2.2): repeated application of the duplication
+// theorem x -> (x + lambda)/4, lambda = sqrt(x)sqrt(y) + sqrt(x)sqrt(z) +
+// sqrt(y)sqrt(z), until every argument is within a relative distance tau of
+// the mean A_m, then a Taylor expansion about A_m in the symmetric functions of
+// the normalised deviations X_i = (A_0 - x_i) 4^-m / A_m (taken from the
+// initial arguments, which avoids the rounding of the iterated ones).  The
+// expansions used are the seventh-order one for R_F and R_C and the
+// fifth-order one for R_D and R_J (DLMF 19.36.1-2).
+//
+// Two families:
+//  * general complex (rf_c, rd_c, rj_c, rc_c) -- the C-ABI carlson_* entry points;
+//  * "structured" real-result versions for the distance kernels, whose argument
+//    triples are always (real, real, real) or (real, w, conj(w)).  A triple is
+//    passed as (x, a, b): x real; PAIR -> y = a + i b, z = a - i b; otherwise
+//    y = a, z = b.  Duplication maps each structure onto itself (lambda is real),
+//    so every iterate stays real or a conjugate pair.
+#pragma once
+
+#include "cmath.hpp"
+
+namespace cosmo {
+
+// ---------------------------------------------------------------- tails
+template <typename T> __device__ __forceinline__ T rf_tail(T E2, T E3) {
+    // 1 - E2/10 + E3/14 + E2^2/24 - 3E2E3/44 - 5E2^3/208 + 3E3^2/104 + E2^2E3/16
+    return T(1) + E2 * (T(-0.1) + E2 * (T(1.0 / 24.0) - T(5.0 / 208.0) * E2)) +
+           E3 * (T(1.0 / 14.0) + T(3.0 / 104.0) * E3 - T(3.0 / 44.0) * E2 + T(1.0 / 16.0) * E2 * E2);
+}
+template <typename T> __device__ __forceinline__ cx<T> rf_tail(cx<T> E2, cx<T> E3) {
+    cx<T> a = (E2 * T(-5.0 / 208.0)) + T(1.0 / 24.0);
+    cx<T> b = (E2 * a) + T(-0.1);
+    cx<T> c = (E3 * T(3.0 / 104.0)) - (E2 * T(3.0 / 44.0)) + (E2 * E2 * T(1.0 / 16.0)) + T(1.0 / 14.0);
+    return (E2 * b) + (E3 * c) + T(1);
+}
+// 1 - 3E2/14 + E3/6 + 9E2^2/88 - 3E4/22 - 9E2E3/52 + 3E5/26
+template <typename T> __device__ __forceinline__ T rj_tail(T E2, T E3, T E4, T E5) {
+    return T(1) + E2 * (T(-3.0 / 14.0) + T(9.0 / 88.0) * E2 - T(9.0 / 52.0) * E3) + T(1.0 / 6.0) * E3 -
+           T(3.0 / 22.0) * E4 + T(3.0 / 26.0) * E5;
+}
+template <typename T> __device__ __forceinline__ cx<T> rj_tail(cx<T> E2, cx<T> E3, cx<T> E4, cx<T> E5) {
+    cx<T> a = (E2 * T(9.0 / 88.0)) - (E3 * T(9.0 / 52.0)) + T(-3.0 / 14.0);
+    return (E2 * a) + (E3 * T(1.0 / 6.0)) - (E4 * T(3.0 / 22.0)) + (E5 * T(3.0 / 26.0)) + T(1);
+}
+// 1 + 3s^2/10 + s^3/7 + 3s^4/8 + 9s^5/22 + 159s^6/208 + 9s^7/8
+template <typename T> __device__ __forceinline__ T rc_tail(T s) {
+    return T(1) + s * s * (T(0.3) + s * (T(1.0 / 7.0) + s * (T(0.375) + s * (T(9.0 / 22.0) +
+                          s * (T(159.0 / 208.0) + s * T(1.125))))));
+}
+template <typename T> __device__ __forceinline__ cx<T> rc_tail(cx<T> s) {
+    cx<T> p = (s * T(1.125)) + T(159.0 / 208.0);
+    p = (s * p) + T(9.0 / 22.0);
+    p = (s * p) + T(0.375);
+    p = (s * p) + T(1.0 / 7.0);
+    p = (s * p) + T(0.3);
+    return (s * s * p) + T(1);
+}
+
+constexpr int kMaxDup = 64; // iteration cap: guarantees termination on NaN/degenerate input
+
+// ---------------------------------------------------------------- general complex
+template <typename T> __device__ cx<T> rf_c(cx<T> x, cx<T> y, cx<T> z) {
+    const T third = T(1.0 / 3.0);
+    cx<T> A0 = (x + y + z) * third;
+    cx<T> dx = A0 - x, dy = A0 - y;
+    T Q = tmax(tmax(cabs(dx), cabs(dy)), cabs(A0 - z));
+    cx<T> A = A0;
+    T f = T(1);
+    for (int m = 0; m < kMaxDup && Q * f > Fp<T>::tau7 * cabs(A); ++m) {
+        cx<T> sx = csqrt(x), sy = csqrt(y), sz = csqrt(z);
+        cx<T> lam = sx * sy + sx * sz + sy * sz;
+        x = (x + lam) * T(0.25);
+        y = (y + lam) * T(0.25);
+        z = (z + lam) * T(0.25);
+        A = (A + lam) * T(0.25);
+        f *= T(0.25);
+    }
+    cx<T> g = crcp(A) * f;
+    cx<T> X = dx * g, Y = dy * g;
+    cx<T> Z = -(X + Y);
+    cx<T> E2 = X * Y - Z * Z, E3 = X * Y * Z;
+    return rf_tail(E2, E3) * crcp(csqrt(A));
+}
+
+template <typename T> __device__ cx<T> rd_c(cx<T> x, cx<T> y, cx<T> z) {
+    cx<T> A0 = (x + y + z * T(3)) * T(0.2);
+    cx<T> dx = A0 - x, dy = A0 - y;
+    T Q = tmax(tmax(cabs(dx), cabs(dy)), cabs(A0 - z));
+    cx<T> A = A0, acc = mkc(T(0), T(0));
+    T f = T(1);
+    for (int m = 0; m < kMaxDup && Q * f > Fp<T>::tau5 * cabs(A); ++m) {
+        cx<T> sx = csqrt(x), sy = csqrt(y), sz = csqrt(z);
+        cx<T> lam = sx * sy + sx * sz + sy * sz;
+        acc = acc + crcp(sz * (z + lam)) * f;
+        x = (x + lam) * T(0.25);
+        y = (y + lam) * T(0.25);
+        z = (z + lam) * T(0.25);
+        A = (A + lam) * T(0.25);
+        f *= T(0.25);
+    }
+    cx<T> g = crcp(A) * f;
+    cx<T> X = dx * g, Y = dy * g;
+    cx<T> Z = (X + Y) * T(-1.0 / 3.0);
+    cx<T> XY = X * Y, Z2 = Z * Z;
+    cx<T> E2 = XY - Z2 * T(6), E3 = (XY * T(3) - Z2 * T(8)) * Z;
+    cx<T> E4 = (XY - Z2) * Z2 * T(3), E5 = XY * Z2 * Z;
+    return rj_tail(E2, E3, E4, E5) * crcp(A * csqrt(A)) * f + acc * T(3);
+}
+
+template <typename T> __device__ cx<T> rc_c(cx<T> x, cx<T> y) {
+    T scale = T(1);
+    if (y.im == T(0) && y.re < T(0) && x.im == T(0) && x.re >= T(0)) {
+        // Cauchy principal value: R_C(x, y) = sqrt(x/(x-y)) R_C(x - y, -y)  (DLMF 19.2.20)
+        scale = Fp<T>::sqrt(Fp<T>::div(x.re, x.re - y.re));
+        x = x - y;
+        y = -y;
+    }
+    cx<T> A0 = (x + y * T(2)) * T(1.0 / 3.0);
+    cx<T> dy = y - A0;
+    T Q = cabs(A0 - x);
+    cx<T> A = A0;
+    T f = T(1);
+    for (int m = 0; m < kMaxDup && Q * f > Fp<T>::tau7 * cabs(A); ++m) {
+        cx<T> lam = csqrt(x) * csqrt(y) * T(2) + y;
+        x = (x + lam) * T(0.25);
+        y = (y + lam) * T(0.25);
+        A = (A + lam) * T(0.25);
+        f *= T(0.25);
+    }
+    cx<T> s = dy * crcp(A) * f;
+    return rc_tail(s) * crcp(csqrt(A)) * scale;
+}
+
+// R_C(1, 1 + e): series sum_n (-e)^n / (2n+1) for small |e|, else by duplication.
+template <typename T> __device__ __forceinline__ cx<T> rc1_c(cx<T> e) {
+    if (cabs(e) < Fp<T>::rc_series_max) {
+        cx<T> s = mkc(T(0), T(0)), t = mkc(T(1), T(0));
+        for (int n = 0; n < Fp<T>::rc_series_terms; ++n) {
+            s = s + t * T(1.0 / (2 * n + 1));
+            t = t * (-e);
+        }
+        return s;
+    }
+    return rc_c(mkc(T(1), T(0)), e + T(1));
+}
+
+template <typename T> __device__ cx<T> rj_c(cx<T> x, cx<T> y, cx<T> z, cx<T> p) {
+    cx<T> A0 = (x + y + z + p * T(2)) * T(0.2);
+    cx<T> dx = A0 - x, dy = A0 - y, dz = A0 - z, dp = A0 - p;
+    T Q = tmax(tmax(cabs(dx), cabs(dy)), tmax(cabs(dz), cabs(dp)));
+    cx<T> delta = (p - x) * (p - y) * (p - z);
+    cx<T> A = A0, acc = mkc(T(0), T(0));
+    T f = T(1);
+    for (int m = 0; m < kMaxDup && Q * f > Fp<T>::tau5 * cabs(A); ++m) {
+        cx<T> sx = csqrt(x), sy = csqrt(y), sz = csqrt(z), sp = csqrt(p);
+        cx<T> lam = sx * sy + sx * sz + sy * sz;
+        cx<T> d = (sp + sx) * (sp + sy) * (sp + sz);
+        cx<T> e = delta * crcp(d * d) * (f * f * f);
+        acc = acc + rc1_c(e) * crcp(d) * f;
+        x = (x + lam) * T(0.25);
+        y = (y + lam) * T(0.25);
+        z = (z + lam) * T(0.25);
+        p = (p + lam) * T(0.25);
+        A = (A + lam) * T(0.25);
+        f *= T(0.25);
+    }
+    cx<T> g = crcp(A) * f;
+    cx<T> X = dx * g, Y = dy * g, Z = dz * g, P = dp * g;
+    cx<T> xyz = X * Y * Z, P2 = P * P;
+    cx<T> E2 = X * Y + X * Z + Y * Z - P2 * T(3);
+    cx<T> E3 = xyz + E2 * P * T(2) + P2 * P * T(4);
+    cx<T> E4 = (xyz * T(2) + E2 * P + P2 * P * T(3)) * P;
+    cx<T> E5 = xyz * P2;
+    return rj_tail(E2, E3, E4, E5) * crcp(A * csqrt(A)) * f + acc * T(6);
+}
+
+// ---------------------------------------------------------------- real R_C
+// Real arguments x >= 0, y != 0 (principal value for y < 0).
+template <typename T> __device__ T rc_r(T x, T y) {
+    T scale = T(1);
+    if (y < T(0)) {
+        scale = Fp<T>::sqrt(Fp<T>::div(x, x - y));
+        x = x - y;
+        y = -y;
+    }
+    T A0 = (x + T(2) * y) * T(1.0 / 3.0);
+    T dy = y - A0;
+    T Q = Fp<T>::abs(A0 - x);
+    T A = A0, f = T(1);
+    for (int m = 0; m < kMaxDup && Q * f > Fp<T>::tau7 * Fp<T>::abs(A); ++m) {
+        T lam = T(2) * Fp<T>::sqrt(x) * Fp<T>::sqrt(y) + y;
+        x = (x + lam) * T(0.25);
+        y = (y + lam) * T(0.25);
+        A = (A + lam) * T(0.25);
+        f *= T(0.25);
+    }
+    T s = dy * f * Fp<T>::rcp(A);
+    return rc_tail(s) * Fp<T>::rsqrt(A) * scale;
+}
+
+template <typename T> __device__ __forceinline__ T rc1_r(T e) {
+    if (Fp<T>::abs(e) < Fp<T>::rc_series_max) {
+        T s = T(0), t = T(1);
+#pragma unroll
+        for (int n = 0; n < Fp<T>::rc_series_terms; ++n) {
+            s += t * T(1.0 / (2 * n + 1));
+            t *= -e;
+        }
+        return s;
+    }
+    return rc_r(T(1), T(1) + e);
+}
+
+// ---------------------------------------------------------------- structured
+// One duplication step on a structured triple; returns lambda.  For PAIR also
+// returns Re sqrt(y) and |y| (reused by R_J's d_m).
+template <typename T, bool PAIR>
+__device__ __forceinline__ T dup_lambda(T x, T a, T b, T &sx, T &sy_re, T &sy_abs2, T &sz) {
+    sx = Fp<T>::sqrt(x);
+    if (PAIR) {
+        T r;
+        sy_re = csqrt_re(a, b, r);
+        sy_abs2 = r;
+        sz = T(0);
+        return sx * (T(2) * sy_re) + r;
+    } else {
+        sy_re = Fp<T>::sqrt(a);
+        sz = Fp<T>::sqrt(b);
+        sy_abs2 = T(0);
+        return sx * (sy_re + sz) + sy_re * sz;
+    }
+}
+
+template <typename T, bool PAIR> __device__ __forceinline__ T mean3(T x, T a, T b) {
+    return PAIR ? (x + T(2) * a) * T(1.0 / 3.0) : (x + a + b) * T(1.0 / 3.0);
+}
+
+// max_i |A0 - x_i| for a structured triple
+template <typename T, bool PAIR> __device__ __forceinline__ T spread3(T A0, T x, T a, T b) {
+    T m = tmax(Fp<T>::abs(A0 - x), PAIR ? Fp<T>::sqrt((A0 - a) * (A0 - a) + b * b) : Fp<T>::abs(A0 - a));
+    return PAIR ? m : tmax(m, Fp<T>::abs(A0 - b));
+}
+
+// Symmetric functions of the deviations of (y, z) about A0, scaled by g:
+// s = Y + Z and q = Y Z.
+template <typename T, bool PAIR>
+__device__ __forceinline__ void yz_sym(T A0, T a, T b, T g, T &s, T &q) {
+    if (PAIR) {
+        T u = (A0 - a) * g, v = b * g;
+        s = T(2) * u;
+        q = u * u + v * v;
+    } else {
+        T Y = (A0 - a) * g, Z = (A0 - b) * g;
+        s = Y + Z;
+        q = Y * Z;
+    }
+}
+
+template <typename T, bool PAIR> __device__ T rf_s(T x, T a, T b) {
+    const T A0 = mean3<T, PAIR>(x, a, b);
+    const T x0 = x, a0 = a, b0 = b;
+    const T Q = spread3<T, PAIR>(A0, x, a, b);
+    T A = A0, f = T(1);
+    for (int m = 0; m < kMaxDup && Q * f > Fp<T>::tau7 * Fp<T>::abs(A); ++m) {
+        T sx, syr, sya, sz;
+        T lam = dup_lambda<T, PAIR>(x, a, b, sx, syr, sya, sz);
+        x = (x + lam) * T(0.25);
+        a = (a + lam) * T(0.25);
+        b = PAIR ? b * T(0.25) : (b + lam) * T(0.25);
+        A = (A + lam) * T(0.25);
+        f *= T(0.25);
+    }
+    T g = f * Fp<T>::rcp(A);
+    T X = (A0 - x0) * g, s, q;
+    yz_sym<T, PAIR>(A0, a0, b0, g, s, q);
+    // with X + s = 0: E2 = XY + XZ + YZ = q - X^2, E3 = XYZ = X q
+    return rf_tail(q - X * X, X * q) * Fp<T>::rsqrt(A);
+}
+
+// R_F(x, y, z) and R_J(x, y, z, p) from one shared duplication sequence
+// (p real > 0; p <= 0 would need the principal-value transformation and yields NaN).
+template <typename T, bool PAIR>
+__device__ void rfj_s(T x, T a, T b, T p, T &rf, T &rj) {
+    const T AF0 = mean3<T, PAIR>(x, a, b);
+    const T AJ0 = (T(3) * AF0 + T(2) * p) * T(0.2);
+    const T x0 = x, a0 = a, b0 = b, p0 = p;
+    const T QF = spread3<T, PAIR>(AF0, x, a, b);
+    const T QJ = tmax(spread3<T, PAIR>(AJ0, x, a, b), Fp<T>::abs(AJ0 - p));
+    T delta = PAIR ? (p - x) * ((p - a) * (p - a) + b * b) : (p - x) * (p - a) * (p - b);
+    T AF = AF0, AJ = AJ0, f = T(1), acc = T(0);
+    for (int m = 0; m < kMaxDup && (QF * f > Fp<T>::tau7 * Fp<T>::abs(AF) ||
+                                   QJ * f > Fp<T>::tau5 * Fp<T>::abs(AJ)); ++m) {
+        T sx, syr, sya, sz;
+        T lam = dup_lambda<T, PAIR>(x, a, b, sx, syr, sya, sz);
+        T sp = Fp<T>::sqrt(p);
+        T d = (sp + sx) * (PAIR ? p + T(2) * sp * syr + sya : (sp + syr) * (sp + sz));
+        T rd = Fp<T>::rcp(d);
+        T e = delta * rd * rd * (f * f * f);
+        acc += f * rc1_r(e) * rd;
+        x = (x + lam) * T(0.25);
+        a = (a + lam) * T(0.25);
+        b = PAIR ? b * T(0.25) : (b + lam) * T(0.25);
+        p = (p + lam) * T(0.25);
+        AF = (AF + lam) * T(0.25);
+        AJ = (AJ + lam) * T(0.25);
+        f *= T(0.25);
+    }
+    {
+        T g = f * Fp<T>::rcp(AF);
+        T X = (AF0 - x0) * g, s, q;
+        yz_sym<T, PAIR>(AF0, a0, b0, g, s, q);
+        rf = rf_tail(q - X * X, X * q) * Fp<T>::rsqrt(AF);
+    }
+    {
+        T g = f * Fp<T>::rcp(AJ);
+        T X = (AJ0 - x0) * g, s, q;
+        yz_sym<T, PAIR>(AJ0, a0, b0, g, s, q);
+        T P = (AJ0 - p0) * g;
+        T sym2 = X * s + q, xyz = X * q, P2 = P * P;
+        T E2 = sym2 - T(3) * P2;
+        T E3 = xyz + T(2) * E2 * P + T(4) * P2 * P;
+        T E4 = (T(2) * xyz + E2 * P + T(3) * P2 * P) * P;
+        T E5 = xyz * P2;
+        rj = rj_tail(E2, E3, E4, E5) * f * Fp<T>::rcp(AJ) * Fp<T>::rsqrt(AJ) + T(6) * acc;
+    }
+    if (!(p0 > T(0))) rj = Fp<T>::nan();
+}
+
+// R_D(y, z, x): the real member x of the triple is the last argument.
+template <typename T, bool PAIR> __device__ T rd_last_x(T x, T a, T b) {
+    const T A0 = PAIR ? (T(2) * a + T(3) * x) * T(0.2) : (a + b + T(3) * x) * T(0.2);
+    const T a0 = a, b0 = b;
+    const T Q = spread3<T, PAIR>(A0, x, a, b);
+    T A = A0, f = T(1), acc = T(0);
+    for (int m = 0; m < kMaxDup && Q * f > Fp<T>::tau5 * Fp<T>::abs(A); ++m) {
+        T sx, syr, sya, sz;
+        T lam = dup_lambda<T, PAIR>(x, a, b, sx, syr, sya, sz);
+        acc += f * Fp<T>::rcp(sx * (x + lam));
+        x = (x + lam) * T(0.25);
+        a = (a + lam) * T(0.25);
+        b = PAIR ? b * T(0.25) : (b + lam) * T(0.25);
+        A = (A + lam) * T(0.25);
+        f *= T(0.25);
+    }
+    T g = f * Fp<T>::rcp(A);
+    T s, q; // (Y + Z, Y Z) of the two leading arguments
+    yz_sym<T, PAIR>(A0, a0, b0, g, s, q);
+    T Z = s * T(-1.0 / 3.0);
+    T Z2 = Z * Z;
+    T E2 = q - T(6) * Z2, E3 = (T(3) * q - T(8) * Z2) * Z;
+    T E4 = T(3) * (q - Z2) * Z2, E5 = q * Z2 * Z;
+    return rj_tail(E2, E3, E4, E5) * f * Fp<T>::rcp(A) * Fp<T>::rsqrt(A) + T(3) * acc;
+}
+
+// R_F together with the three R_D(., ., x_k) that give its partial derivatives,
+// dR_F/dx_k = -R_D(., ., x_k)/6 (eq. 2.10), from one duplication sequence.
+// Outputs: rf; rdx = R_D(y, z, x); rdy = R_D(x, z, y) (complex for PAIR; for a
+// PAIR triple R_D(x, y, z) = conj(rdy)); rdz = R_D(x, y, z) for real triples.
+template <typename T, bool PAIR>
+__device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
+    const T AF0 = mean3<T, PAIR>(x, a, b);
+    const T x0 = x, a0 = a, b0 = b;
+    const T QF = spread3<T, PAIR>(AF0, x, a, b);
+    // The R_D means (3 A_F + 2 x_k)/5 deviate from the arguments by at most 1.4 QF.
+    T AF = AF0, f = T(1), accx = T(0), accz = T(0);
+    cx<T> accy = mkc(T(0), T(0));
+    for (int m = 0; m < kMaxDup && T(1.4) * QF * f > Fp<T>::tau5 * Fp<T>::abs(AF); ++m) {
+        T sx = Fp<T>::sqrt(x);
+        T lam;
+        if (PAIR) {
+            T r;
+            cx<T> sy = csqrt(mkc(a, b), r);
+            lam = sx * (T(2) * sy.re) + r;
+            accy = accy + crcp(sy * (mkc(a, b) + lam)) * f;
+        } else {
+            T sy = Fp<T>::sqrt(a), sz = Fp<T>::sqrt(b);
+            lam = sx * (sy + sz) + sy * sz;
+            accy.re += f * Fp<T>::rcp(sy * (a + lam));
+            accz += f * Fp<T>::rcp(sz * (b + lam));
+        }
+        accx += f * Fp<T>::rcp(sx * (x + lam));
+        x = (x + lam) * T(0.25);
+        a = (a + lam) * T(0.25);
+        b = PAIR ? b * T(0.25) : (b + lam) * T(0.25);
+        AF = (AF + lam) * T(0.25);
+        f *= T(0.25);
+    }
+    {
+        T g = f * Fp<T>::rcp(AF);
+        T X = (AF0 - x0) * g, s, q;
+        yz_sym<T, PAIR>(AF0, a0, b0, g, s, q);
+        rf = rf_tail(q - X * X, X * q) * Fp<T>::rsqrt(AF);
+    }
+    {   // R_D(y, z, x)
+        T A0 = (T(3) * AF0 + T(2) * x0) * T(0.2), A = (T(3) * AF + T(2) * x) * T(0.2);
+        T g = f * Fp<T>::rcp(A), s, q;
+        yz_sym<T, PAIR>(A0, a0, b0, g, s, q);
+        T Z = s * T(-1.0 / 3.0), Z2 = Z * Z;
+        T E2 = q - T(6) * Z2, E3 = (T(3) * q - T(8) * Z2) * Z;
+        T E4 = T(3) * (q - Z2) * Z2, E5 = q * Z2 * Z;
+        rdx = rj_tail(E2, E3, E4, E5) * f * Fp<T>::rcp(A) * Fp<T>::rsqrt(A) + T(3) * accx;
+    }
+    if (PAIR) {
+        // R_D(x, z, y) with y = a + i b last, z = conj(y)
+        cx<T> y0 = mkc(a0, b0), y = mkc(a, b);
+        cx<T> A0 = (y0 * T(2) + T(3) * AF0) * T(0.2), A = (y * T(2) + T(3) * AF) * T(0.2);
+        cx<T> g = crcp(A) * f;
+        cx<T> X = (A0 - x0) * g, Y = (A0 - conj(y0)) * g;
+        cx<T> Z = (X + Y) * T(-1.0 / 3.0);
+        cx<T> XY = X * Y, Z2 = Z * Z;
+        cx<T> E2 = XY - Z2 * T(6), E3 = (XY * T(3) - Z2 * T(8)) * Z;
+        cx<T> E4 = (XY - Z2) * Z2 * T(3), E5 = XY * Z2 * Z;
+        rdy = rj_tail(E2, E3, E4, E5) * crcp(A * csqrt(A)) * f + accy * T(3);
+        rdz = T(0);
+    } else {
+        // R_D(x, z, y) and R_D(x, y, z)
+        T A0 = (T(3) * AF0 + T(2) * a0) * T(0.2), A = (T(3) * AF + T(2) * a) * T(0.2);
+        T g = f * Fp<T>::rcp(A);
+        T X = (A0 - x0) * g, Y = (A0 - b0) * g, Z = (X + Y) * T(-1.0 / 3.0);
+        T XY = X * Y, Z2 = Z * Z;
+        rdy = mkc(rj_tail(XY - T(6) * Z2, (T(3) * XY - T(8) * Z2) * Z, T(3) * (XY - Z2) * Z2, XY * Z2 * Z) *
+                          f * Fp<T>::rcp(A) * Fp<T>::rsqrt(A) + T(3) * accy.re, T(0));
+        A0 = (T(3) * AF0 + T(2) * b0) * T(0.2);
+        A = (T(3) * AF + T(2) * b) * T(0.2);
+        g = f * Fp<T>::rcp(A);
+        X = (A0 - x0) * g;
+        Y = (A0 - a0) * g;
+        Z = (X + Y) * T(-1.0 / 3.0);
+        XY = X * Y;
+        Z2 = Z * Z;
+        rdz = rj_tail(XY - T(6) * Z2, (T(3) * XY - T(8) * Z2) * Z, T(3) * (XY - Z2) * Z2, XY * Z2 * Z) *
+                  f * Fp<T>::rcp(A) * Fp<T>::rsqrt(A) + T(3) * accz;
+    }
+}
+
+} // namespace cosmo

@@ -1,0 +1,112 @@
+// cmath.hpp -- precision traits and a minimal complex type for the gfx950 kernels.
+//
+// The FP32 path uses the hardware transcendental instructions (v_sqrt_f32,
+// v_rcp_f32, v_rsq_f32: about 1 ulp) instead of the correctly rounded sequences;
+// the FP64 path uses correctly rounded sqrt and division.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cosmo {
+
+template <typename T> struct Fp;
+
+template <> struct Fp<float> {
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float abs(float x) { return __builtin_fabsf(x); }
+    static __device__ __forceinline__ float exp(float x) { return expf(x); }
+    static __device__ __forceinline__ float log(float x) { return logf(x); }
+    static __device__ __forceinline__ float log1p(float x) { return log1pf(x); }
+    static __device__ __forceinline__ float log10(float x) { return log10f(x); }
+    static __device__ __forceinline__ float atan(float x) { return atanf(x); }
+    static __device__ __forceinline__ float sin(float x) { return sinf(x); }
+    static __device__ __forceinline__ float cos(float x) { return cosf(x); }
+    static __device__ __forceinline__ float nan() { return __builtin_nanf(""); }
+    // Duplication stopping thresholds: iterate while max|A0 - x_i| 4^-m > tau |A_m|.
+    // 7th-order tails (R_F, R_C): remainder ~ tau^8 / 4; 5th-order (R_D, R_J): ~ tau^6.
+    static constexpr float tau7 = 0.136f;
+    static constexpr float tau5 = 0.070f;
+    static constexpr float rc_series_max = 0.02f; // |e| below which R_C(1, 1+e) uses its series
+    static constexpr int rc_series_terms = 5;
+};
+
+template <> struct Fp<double> {
+    static __device__ __forceinline__ double sqrt(double x) { return __builtin_sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / __builtin_sqrt(x); }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double abs(double x) { return __builtin_fabs(x); }
+    static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+    static __device__ __forceinline__ double log(double x) { return ::log(x); }
+    static __device__ __forceinline__ double log1p(double x) { return ::log1p(x); }
+    static __device__ __forceinline__ double log10(double x) { return ::log10(x); }
+    static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
+    static __device__ __forceinline__ double sin(double x) { return ::sin(x); }
+    static __device__ __forceinline__ double cos(double x) { return ::cos(x); }
+    static __device__ __forceinline__ double nan() { return __builtin_nan(""); }
+    static constexpr double tau7 = 0.0121;
+    static constexpr double tau5 = 0.0028;
+    static constexpr double rc_series_max = 0.01;
+    static constexpr int rc_series_terms = 9;
+};
+
+template <typename T> struct cx {
+    T re, im;
+};
+
+template <typename T> __device__ __forceinline__ cx<T> mkc(T r, T i) { return cx<T>{r, i}; }
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator*(cx<T> a, T s) { return {s * a.re, s * a.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, T s) { return {a.re + s, a.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, T s) { return {a.re - s, a.im}; }
+template <typename T> __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+template <typename T> __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+template <typename T> __device__ __forceinline__ T cabs(cx<T> a) { return Fp<T>::sqrt(norm2(a)); }
+template <typename T> __device__ __forceinline__ cx<T> crcp(cx<T> a) {
+    T s = Fp<T>::rcp(norm2(a));
+    return {a.re * s, -a.im * s};
+}
+template <typename T> __device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> b) { return a * crcp(b); }
+
+// Principal square root; also returns |w| (= |sqrt(w)|^2), which callers reuse.
+template <typename T> __device__ __forceinline__ cx<T> csqrt(cx<T> w, T &absw) {
+    T r = cabs(w);
+    absw = r;
+    bool pos = w.re >= T(0);
+    T t = T(0.5) * (pos ? r + w.re : r - w.re);
+    T s = Fp<T>::sqrt(t);
+    T o = (s > T(0)) ? T(0.5) * Fp<T>::abs(w.im) * Fp<T>::rcp(s) : T(0);
+    cx<T> res;
+    res.re = pos ? s : o;
+    res.im = pos ? (w.im >= T(0) ? o : -o) : (w.im >= T(0) ? s : -s);
+    return res;
+}
+template <typename T> __device__ __forceinline__ cx<T> csqrt(cx<T> w) {
+    T r;
+    return csqrt(w, r);
+}
+
+// Real part of the principal square root only (cheaper: no division on the
+// w.re >= 0 branch).  Used where only Re(sqrt(w)) and |w| are needed.
+template <typename T> __device__ __forceinline__ T csqrt_re(T wre, T wim, T &absw) {
+    T r = Fp<T>::sqrt(wre * wre + wim * wim);
+    absw = r;
+    bool pos = wre >= T(0);
+    T t = T(0.5) * (pos ? r + wre : r - wre);
+    T s = Fp<T>::sqrt(t);
+    return pos ? s : ((s > T(0)) ? T(0.5) * Fp<T>::abs(wim) * Fp<T>::rcp(s) : T(0));
+}
+
+template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+
+} // namespace cosmo

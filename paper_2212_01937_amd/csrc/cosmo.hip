@@ -1,0 +1,640 @@
+// cosmo.hip -- gfx950 kernels and the C ABI of libcosmo.so (include/cosmo.h).
+//
+// Launch layout of the distance and adjoint kernels: 256-lane blocks; a block
+// owns 256 consecutive redshifts (one per lane, coalesced loads/stores along z)
+// and a tile of `ct` consecutive cosmologies that it walks in order, so a shared
+// redshift row is loaded once per block and reused across the tile.  The
+// per-cosmology record (roots, constants, Jacobian) is block-uniform and is read
+// through the scalar cache.  The flat block index is split as
+// (cosmology tile, z block) with z blocks fastest.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <mutex>
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/cosmo.h"
+#include "lane.hpp"
+
+namespace cosmo {
+
+__constant__ double c_gl64_x[kGlN64], c_gl64_w[kGlN64];
+__constant__ float c_gl32_x[kGlN32], c_gl32_w[kGlN32];
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------- kernels
+__global__ void k_setup(const double *__restrict__ params, int64_t n, CosmoRec *__restrict__ recs,
+                        int32_t *__restrict__ info) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    CosmoRec r;
+    setup_cosmo(params + 4 * c, r);
+    recs[c] = r;
+    if (info) info[c] = r.info;
+}
+
+__global__ void k_roots(const double *__restrict__ params, int64_t n, double *__restrict__ roots,
+                        int32_t *__restrict__ info) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    CosmoRec r;
+    setup_cosmo(params + 4 * c, r);
+    double *o = roots + 8 * c;
+    bool have = !(r.info & COSMO_INFO_DOMAIN);
+    const double nan = __builtin_nan("");
+    if (have) {
+        const LaneConst<double> &d = r.d;
+        o[0] = d.r0 - 1.0; o[1] = 0.0;
+        o[2] = d.r1re - 1.0; o[3] = d.r1im;
+        o[4] = (r.pair ? d.r1re : d.r2) - 1.0; o[5] = r.pair ? -d.r1im : 0.0;
+        o[6] = r.rl - 1.0; o[7] = (r.info & COSMO_INFO_QUARTIC) ? 0.0 : nan;
+    } else {
+        for (int i = 0; i < 8; ++i) o[i] = nan;
+    }
+    if (info) info[c] = r.info;
+}
+
+template <typename T, int KIND, bool PAIR>
+__device__ __forceinline__ T eval_kind(const LaneConst<T> &k, T z, bool &used_gl) {
+    used_gl = false;
+    if (KIND == COSMO_T) return k.th * t_hat<T, PAIR>(k, z);
+    if (KIND == COSMO_X) return k.dh * x_hat<T, PAIR>(k, z, used_gl);
+    T chi = chi_hat<T, PAIR>(k, z);
+    T a, b, c, d;
+    return observable<T>(KIND, k, chi, z, T(0), a, b, c, d);
+}
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(kBlock) void k_forward(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
+                                                     const T *__restrict__ z, int64_t n_z, int64_t zstride,
+                                                     T *__restrict__ out, int32_t *__restrict__ info,
+                                                     int ct, int64_t nzb) {
+    const int64_t b = blockIdx.x;
+    const int64_t tile = b / nzb, zb = b - tile * nzb;
+    const int64_t i = zb * kBlock + threadIdx.x;
+    const bool active = i < n_z;
+    const int64_t c0 = tile * ct;
+    const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
+    const T zshared = (zstride == 0 && active) ? z[i] : T(0);
+    for (int64_t c = c0; c < c1; ++c) {
+        const CosmoRec &r = recs[c];
+        if (!active) continue;
+        const T zz = zstride == 0 ? zshared : z[c * zstride + i];
+        T v;
+        bool used_gl = false;
+        if (!r.valid) v = Fp<T>::nan();
+        else if (r.pair) v = eval_kind<T, KIND, true>(lane_of<T>(r), zz, used_gl);
+        else v = eval_kind<T, KIND, false>(lane_of<T>(r), zz, used_gl);
+        out[c * n_z + i] = v;
+        if (KIND == COSMO_X && info) {
+            unsigned long long m = __ballot(used_gl);
+            if (m && (int)__lane_id() == __ffsll((long long)m) - 1) atomicOr(info + c, COSMO_INFO_X_QUADRATURE);
+        }
+    }
+}
+
+// Accumulator slots of the adjoint (per lane, then per block, then per cosmology)
+//   root mode:   0 sum w chi, 1 sum w dchi/dsigma, 2 sum w dchi/drho0,
+//                3/4 sum w dchi/drho1 (re, im) [pair] or drho1, drho2 [real],
+//                5 sum cot dout/dOk, 6 sum cot dout/dH0
+//   direct mode: 0..2 sum w dI/d(Om, OL, Or) (Leibniz quadrature), 5, 6 as above
+constexpr int kAcc = 8;
+
+__device__ __forceinline__ bool direct_mode(int kind, const CosmoRec &r, bool fp32) {
+    if (kind == COSMO_T || kind == COSMO_X) return true;
+    return r.minsep < (fp32 ? 2e-2 : 1e-4);
+}
+
+// Kept out of line: a rarely taken FP64 branch whose registers should not
+// count against the hot adjoint kernels.
+template <bool PAIR>
+__device__ __attribute__((noinline)) void gl_chi_grad(const CosmoRec &r, double z, double &chi, double g[3]) {
+    gl_integral<double, PAIR>(r.d, z, 0, true, chi, g);
+}
+
+template <typename T, int KIND, bool PAIR>
+__device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kAcc], T &gz) {
+    const LaneConst<T> &k = lane_of<T>(r);
+    const bool fp32 = sizeof(T) == 4;
+    const T H0inv = T(1.0 / r.H0);
+    if (KIND == COSMO_T || KIND == COSMO_X) {
+        T val, g[3];
+        gl_integral<T, PAIR>(k, z, KIND == COSMO_T ? 1 : 2, true, val, g);
+        const T scale = KIND == COSMO_T ? k.th : k.dh;
+        const T x = T(1) + z;
+        const T e = Ez<T>(k, z);
+        gz = cot * scale * (KIND == COSMO_T ? Fp<T>::rcp(x * e) : x * x * Fp<T>::rcp(e));
+        // value for the H0 derivative: recompute with the Carlson forward
+        bool ugl;
+        T v = KIND == COSMO_T ? k.th * t_hat<T, PAIR>(k, z) : k.dh * x_hat<T, PAIR>(k, z, ugl);
+        acc[0] += cot * scale * g[0];
+        acc[1] += cot * scale * g[1];
+        acc[2] += cot * scale * g[2];
+        acc[6] += -cot * v * H0inv;
+        return;
+    }
+    if (direct_mode(KIND, r, fp32)) {
+        // near-multiple roots: chi and its parameter gradient by FP64 quadrature
+        double chi, g[3];
+        gl_chi_grad<PAIR>(r, (double)z, chi, g);
+        T dchi, dok, dzz, dh;
+        observable<T>(KIND, k, T(chi), z, H0inv, dchi, dok, dzz, dh);
+        const double w = (double)cot * (double)dchi;
+        acc[0] += T(w * g[0]);
+        acc[1] += T(w * g[1]);
+        acc[2] += T(w * g[2]);
+        acc[5] += cot * dok;
+        acc[6] += cot * dh;
+        gz = cot * (dzz + dchi * Fp<T>::rcp(Ez<T>(k, z)));
+        return;
+    }
+    ChiGrad<T, PAIR> cg;
+    chi_grad<T, PAIR>(k, z, cg);
+    T dchi, dok, dzz, dh;
+    observable<T>(KIND, k, cg.chi, z, H0inv, dchi, dok, dzz, dh);
+    const T w = cot * dchi;
+    acc[0] += w * cg.chi;
+    acc[1] += w * cg.dsig;
+    acc[2] += w * cg.dr0;
+    acc[3] += w * cg.dr1re;
+    acc[4] += w * (PAIR ? cg.dr1im : cg.dr2);
+    acc[5] += cot * dok;
+    acc[6] += cot * dh;
+    gz = cot * (dzz + dchi * Fp<T>::rcp(Ez<T>(k, z)));
+}
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Redshifts per lane of the adjoint: lane t of z-block zb handles
+// i = zb * kBlock * ZPT + t + k * kBlock, k < ZPT (coalesced for every k).  The
+// parameter partials of a cosmology are summed over the lane's ZPT redshifts in
+// registers, then over the wave, and each wave writes its own partial (no block
+// barrier).  The shared-z gradient is summed over the tile's cosmologies in
+// thread-private LDS slots (gzl[k][t]), which keeps the rolled k-loop free of
+// dynamically indexed register arrays.
+template <typename T, int KIND, bool PAIR, int ZPT>
+__device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T *__restrict__ z, int64_t n_z,
+                                          int64_t zstride, const T *__restrict__ cot, int64_t base,
+                                          T acc[kAcc], T *gzl, T *__restrict__ gz_out) {
+#pragma unroll 1
+    for (int k = 0; k < ZPT; ++k) {
+        const int64_t i = base + (int64_t)k * kBlock;
+        if (i >= n_z) break;
+        const T zz = z[c * zstride + i];
+        T gz;
+        vjp_lane<T, KIND, PAIR>(r, zz, cot[c * n_z + i], acc, gz);
+        if (zstride != 0) {
+            if (gz_out) gz_out[c * n_z + i] = gz;
+        } else {
+            gzl[k * kBlock + threadIdx.x] += gz;
+        }
+    }
+}
+
+template <typename T, int KIND, int ZPT>
+__global__ __launch_bounds__(kBlock) void k_vjp(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
+                                                 const T *__restrict__ z, int64_t n_z, int64_t zstride,
+                                                 const T *__restrict__ cot, double *__restrict__ pacc,
+                                                 T *__restrict__ gz_out, double *__restrict__ gz_part,
+                                                 int ct, int64_t nzb) {
+    __shared__ T gzl[ZPT * kBlock];
+    const int64_t b = blockIdx.x;
+    const int64_t tile = b / nzb, zb = b - tile * nzb;
+    const int64_t base = zb * (int64_t)(kBlock * ZPT) + threadIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t nwz = nzb * (kBlock / 64);           // wave partials per cosmology
+    const int64_t gw = zb * (kBlock / 64) + wave;
+    const int64_t c0 = tile * ct;
+    const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
+    for (int k = 0; k < ZPT; ++k) gzl[k * kBlock + threadIdx.x] = T(0);
+    for (int64_t c = c0; c < c1; ++c) {
+        const CosmoRec &r = recs[c];
+        T acc[kAcc];
+#pragma unroll
+        for (int s = 0; s < kAcc; ++s) acc[s] = T(0);
+        if (r.valid) {
+            if (r.pair) vjp_cosmo<T, KIND, true, ZPT>(r, c, z, n_z, zstride, cot, base, acc, gzl, gz_out);
+            else vjp_cosmo<T, KIND, false, ZPT>(r, c, z, n_z, zstride, cot, base, acc, gzl, gz_out);
+        } else {
+            for (int k = 0; k < ZPT; ++k) {
+                const int64_t i = base + (int64_t)k * kBlock;
+                if (i >= n_z) break;
+                if (zstride != 0) {
+                    if (gz_out) gz_out[c * n_z + i] = Fp<T>::nan();
+                } else {
+                    gzl[k * kBlock + threadIdx.x] = Fp<T>::nan();
+                }
+            }
+        }
+        if (pacc) {
+#pragma unroll
+            for (int s = 0; s < kAcc - 1; ++s) {
+                T v = wave_sum(acc[s]);
+                if (lane == 0) pacc[(c * nwz + gw) * kAcc + s] = (double)v;
+            }
+        }
+    }
+    if (zstride == 0 && gz_out) {
+        for (int k = 0; k < ZPT; ++k) {
+            const int64_t i = base + (int64_t)k * kBlock;
+            if (i >= n_z) break;
+            const T v = gzl[k * kBlock + threadIdx.x];
+            if (gz_part) gz_part[tile * n_z + i] = (double)v;
+            else gz_out[i] = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize_params(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
+                                                            const double *__restrict__ pacc, int64_t nwz,
+                                                            int kind, int fp32, double *__restrict__ grad) {
+    __shared__ double red[kBlock / 64][kAcc];
+    const int64_t c = blockIdx.x;
+    if (c >= n_cosmo) return;
+    double acc[kAcc] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t q = threadIdx.x; q < nwz; q += kBlock)
+#pragma unroll
+        for (int s = 0; s < kAcc - 1; ++s) acc[s] += pacc[(c * nwz + q) * kAcc + s];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int s = 0; s < kAcc; ++s) {
+        double v = wave_sum(acc[s]);
+        if (lane == 0) red[wave][s] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double a[kAcc];
+    for (int s = 0; s < kAcc; ++s) {
+        a[s] = 0.0;
+        for (int w2 = 0; w2 < kBlock / 64; ++w2) a[s] += red[w2][s];
+    }
+    const CosmoRec &r = recs[c];
+    double *g = grad + 4 * c;
+    if (!r.valid) {
+        for (int q = 0; q < 4; ++q) g[q] = __builtin_nan("");
+        return;
+    }
+    g[0] = a[6];
+    for (int th = 0; th < 3; ++th) {
+        double v;
+        if (direct_mode(kind, r, fp32 != 0)) {
+            v = a[th];
+        } else {
+            v = -a[0] / (2.0 * r.beta) * r.dbeta[th] + a[1] * r.dsigma[th] + a[2] * r.drho_re[0][th];
+            if (r.pair) v += 2.0 * (a[3] * r.drho_re[1][th] - a[4] * r.drho_im[1][th]);
+            else v += a[3] * r.drho_re[1][th] + a[4] * r.drho_re[2][th];
+        }
+        g[1 + th] = v - a[5]; // explicit Ok in the curvature transform: dOk/dtheta = -1
+    }
+}
+
+template <typename T> __global__ void k_fill_zero(T *__restrict__ p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = T(0);
+}
+
+template <typename T>
+__global__ void k_reduce_gz(const double *__restrict__ part, int64_t ntile, int64_t n_z, T *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_z) return;
+    double s = 0.0;
+    for (int64_t t = 0; t < ntile; ++t) s += part[t * n_z + i];
+    out[i] = (T)s;
+}
+
+// ---------------------------------------------------------------- Carlson entry kernels
+template <typename T, int WHICH>
+__global__ void k_carlson(int64_t n, const T *__restrict__ x, const T *__restrict__ y, const T *__restrict__ z,
+                          const T *__restrict__ p, T *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cx<T> a = mkc(x[2 * i], x[2 * i + 1]), bb = mkc(y[2 * i], y[2 * i + 1]);
+    cx<T> r;
+    if (WHICH == 0) r = rf_c(a, bb, mkc(z[2 * i], z[2 * i + 1]));
+    else if (WHICH == 1) r = rd_c(a, bb, mkc(z[2 * i], z[2 * i + 1]));
+    else if (WHICH == 2) r = rj_c(a, bb, mkc(z[2 * i], z[2 * i + 1]), mkc(p[2 * i], p[2 * i + 1]));
+    else r = rc_c(a, bb);
+    out[2 * i] = r.re;
+    out[2 * i + 1] = r.im;
+}
+
+} // namespace cosmo
+
+// ==================================================================== host side
+using namespace cosmo;
+
+namespace {
+
+struct Tiling {
+    int ct;
+    int64_t nzb, ntile, nblocks;
+};
+
+// zpt: redshifts per lane (1 for the forward kernels; the adjoint uses 8 on long
+// redshift rows).  Cosmology tiles of up to 16 are formed while the grid keeps
+// about 8192 lane-blocks of work.
+Tiling tiling(int64_t n_cosmo, int64_t n_z, int zpt = 1) {
+    Tiling t;
+    const int64_t span = (int64_t)kBlock * zpt;
+    t.nzb = (n_z + span - 1) / span;
+    if (t.nzb < 1) t.nzb = 1;
+    int64_t want = (n_cosmo * t.nzb * zpt) / 8192;
+    t.ct = (int)(want < 1 ? 1 : (want > 16 ? 16 : want));
+    t.ntile = (n_cosmo + t.ct - 1) / t.ct;
+    t.nblocks = t.ntile * t.nzb;
+    return t;
+}
+
+int vjp_zpt(int64_t n_z) { return n_z >= 8192 ? 8 : 1; }
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct WsLayout {
+    size_t recs, pacc, gzp, total;
+};
+
+WsLayout ws_layout(int64_t n_cosmo, int64_t n_z) {
+    Tiling t = tiling(n_cosmo, n_z, vjp_zpt(n_z));
+    WsLayout w;
+    w.recs = 0;
+    w.pacc = align256(sizeof(CosmoRec) * (size_t)n_cosmo);
+    w.gzp = w.pacc + align256(sizeof(double) * kAcc * (size_t)n_cosmo * (size_t)t.nzb * (kBlock / 64));
+    w.total = w.gzp + align256(sizeof(double) * (size_t)t.ntile * (size_t)n_z);
+    return w;
+}
+
+// Gauss-Legendre nodes on [-1, 1] by Newton iteration on the Legendre polynomial.
+void gauss_legendre(int n, double *x, double *w) {
+    for (int i = 0; i < n; ++i) {
+        double t = cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+            double dt = p1 / dp;
+            t -= dt;
+            if (fabs(dt) < 1e-16) {
+                // recompute derivative at the converged node for the weight
+                p0 = 1.0; p1 = t;
+                for (int k = 2; k <= n; ++k) {
+                    double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = n * (t * p1 - p0) / (t * t - 1.0);
+                break;
+            }
+        }
+        x[i] = t;
+        w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+std::mutex g_init_mu;
+bool g_init_done[64];
+
+int ensure_init() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return COSMO_E_HIP;
+    if (dev < 0 || dev >= 64) return COSMO_E_HIP;
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    if (g_init_done[dev]) return COSMO_OK;
+    double x64[kGlN64], w64[kGlN64], x32d[kGlN32], w32d[kGlN32];
+    float x32[kGlN32], w32[kGlN32];
+    gauss_legendre(kGlN64, x64, w64);
+    gauss_legendre(kGlN32, x32d, w32d);
+    for (int i = 0; i < kGlN32; ++i) { x32[i] = (float)x32d[i]; w32[i] = (float)w32d[i]; }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_gl64_x), x64, sizeof x64) != hipSuccess) return COSMO_E_HIP;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_gl64_w), w64, sizeof w64) != hipSuccess) return COSMO_E_HIP;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_gl32_x), x32, sizeof x32) != hipSuccess) return COSMO_E_HIP;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_gl32_w), w32, sizeof w32) != hipSuccess) return COSMO_E_HIP;
+    g_init_done[dev] = true;
+    return COSMO_OK;
+}
+
+bool valid_kind(int k) { return k >= COSMO_DC && k <= COSMO_DA; }
+bool valid_dtype(int d) { return d == COSMO_F32 || d == COSMO_F64; }
+
+// Scoped workspace: the caller's, or stream-ordered pool memory.
+struct Workspace {
+    void *ptr = nullptr;
+    bool owned = false;
+    hipStream_t s = nullptr;
+    int acquire(void *user, size_t user_bytes, size_t need, hipStream_t stream) {
+        s = stream;
+        if (user) {
+            if (user_bytes < need) return COSMO_E_WORKSPACE;
+            ptr = user;
+            return COSMO_OK;
+        }
+        if (hipMallocAsync(&ptr, need, stream) != hipSuccess) return COSMO_E_HIP;
+        owned = true;
+        return COSMO_OK;
+    }
+    ~Workspace() {
+        if (owned && ptr) (void)hipFreeAsync(ptr, s);
+    }
+};
+
+template <typename T>
+int launch_forward(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int64_t n_z, int64_t zstride,
+                   T *out, int32_t *info, hipStream_t s) {
+    Tiling t = tiling(n_cosmo, n_z);
+    dim3 grid((unsigned)t.nblocks), block(kBlock);
+#define COSMO_FWD(K) hipLaunchKernelGGL((k_forward<T, K>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, out, info, t.ct, t.nzb)
+    switch (kind) {
+    case COSMO_DC: COSMO_FWD(COSMO_DC); break;
+    case COSMO_DM: COSMO_FWD(COSMO_DM); break;
+    case COSMO_DL: COSMO_FWD(COSMO_DL); break;
+    case COSMO_MU: COSMO_FWD(COSMO_MU); break;
+    case COSMO_T: COSMO_FWD(COSMO_T); break;
+    case COSMO_X: COSMO_FWD(COSMO_X); break;
+    case COSMO_DA: COSMO_FWD(COSMO_DA); break;
+    }
+#undef COSMO_FWD
+    return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
+}
+
+template <typename T>
+int launch_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int64_t n_z, int64_t zstride,
+               const T *cot, double *grad_params, T *grad_z, const WsLayout &L, char *ws, hipStream_t s) {
+    const int zpt = vjp_zpt(n_z);
+    Tiling t = tiling(n_cosmo, n_z, zpt);
+    double *pacc = grad_params ? (double *)(ws + L.pacc) : nullptr;
+    double *gzp = (grad_z && zstride == 0 && t.ntile > 1) ? (double *)(ws + L.gzp) : nullptr;
+    dim3 grid((unsigned)t.nblocks), block(kBlock);
+#define COSMO_VJP(K)                                                                                            \
+    if (zpt == 8)                                                                                               \
+        hipLaunchKernelGGL((k_vjp<T, K, 8>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, cot, pacc,     \
+                           grad_z, gzp, t.ct, t.nzb);                                                           \
+    else                                                                                                        \
+        hipLaunchKernelGGL((k_vjp<T, K, 1>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, cot, pacc,     \
+                           grad_z, gzp, t.ct, t.nzb)
+    switch (kind) {
+    case COSMO_DC: COSMO_VJP(COSMO_DC); break;
+    case COSMO_DM: COSMO_VJP(COSMO_DM); break;
+    case COSMO_DL: COSMO_VJP(COSMO_DL); break;
+    case COSMO_MU: COSMO_VJP(COSMO_MU); break;
+    case COSMO_T: COSMO_VJP(COSMO_T); break;
+    case COSMO_X: COSMO_VJP(COSMO_X); break;
+    case COSMO_DA: COSMO_VJP(COSMO_DA); break;
+    }
+#undef COSMO_VJP
+    if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
+    if (grad_params) {
+        hipLaunchKernelGGL(k_finalize_params, dim3((unsigned)n_cosmo), dim3(kBlock), 0, s, recs, n_cosmo, pacc,
+                           t.nzb * (kBlock / 64), kind, (int)(sizeof(T) == 4), grad_params);
+        if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
+    }
+    if (gzp) {
+        hipLaunchKernelGGL((k_reduce_gz<T>), dim3((unsigned)((n_z + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, gzp,
+                           t.ntile, n_z, grad_z);
+        if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
+    }
+    return COSMO_OK;
+}
+
+int launch_setup(const double *params, int64_t n_cosmo, CosmoRec *recs, int32_t *info, hipStream_t s) {
+    unsigned nb = (unsigned)((n_cosmo + 63) / 64);
+    hipLaunchKernelGGL(k_setup, dim3(nb), dim3(64), 0, s, params, n_cosmo, recs, info);
+    return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
+}
+
+template <typename T, int WHICH>
+int launch_carlson(int64_t n, const void *x, const void *y, const void *z, const void *p, void *out, hipStream_t s) {
+    unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_carlson<T, WHICH>), dim3(nb), dim3(kBlock), 0, s, n, (const T *)x, (const T *)y,
+                       (const T *)z, (const T *)p, (T *)out);
+    return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
+}
+
+template <int WHICH>
+int carlson_entry(int dt, int64_t n, const void *x, const void *y, const void *z, const void *p, void *out,
+                  void *stream) {
+    if (!valid_dtype(dt)) return COSMO_E_DTYPE;
+    if (n < 0 || (n > 0 && (!x || !y || !out))) return COSMO_E_ARG;
+    if (n > 0 && (WHICH == 0 || WHICH == 1 || WHICH == 2) && !z) return COSMO_E_ARG;
+    if (n > 0 && WHICH == 2 && !p) return COSMO_E_ARG;
+    if (n == 0) return COSMO_OK;
+    if (n > (int64_t)0xFFFFFFFFll * kBlock) return COSMO_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    return dt == COSMO_F32 ? launch_carlson<float, WHICH>(n, x, y, z, p, out, s)
+                           : launch_carlson<double, WHICH>(n, x, y, z, p, out, s);
+}
+
+int check_grid(int64_t n_cosmo, int64_t n_z) {
+    Tiling t = tiling(n_cosmo, n_z);  // the forward grid is the larger one
+    if (t.nblocks > 0x7FFFFFFFll) return COSMO_E_ARG;
+    if (n_cosmo > 0x7FFFFFFFll) return COSMO_E_ARG;
+    return COSMO_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *cosmo_version(void) { return "cosmo-carlson-gfx950 1.0"; }
+
+int cosmo_workspace_size(int64_t n_cosmo, int64_t n_z, size_t *bytes) {
+    if (!bytes || n_cosmo < 0 || n_z < 0) return COSMO_E_ARG;
+    *bytes = ws_layout(n_cosmo, n_z).total;
+    return COSMO_OK;
+}
+
+int cosmo_roots(const double *params, int64_t n_cosmo, double *roots, int32_t *info, void *stream) {
+    if (n_cosmo < 0 || (n_cosmo > 0 && (!params || !roots))) return COSMO_E_ARG;
+    if (n_cosmo == 0) return COSMO_OK;
+    if (n_cosmo > 0x7FFFFFFFll) return COSMO_E_ARG;
+    unsigned nb = (unsigned)((n_cosmo + 63) / 64);
+    hipLaunchKernelGGL(k_roots, dim3(nb), dim3(64), 0, (hipStream_t)stream, params, n_cosmo, roots, info);
+    return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
+}
+
+int carlson_rf(cosmo_dtype dt, int64_t n, const void *x, const void *y, const void *z, void *out, void *stream) {
+    return carlson_entry<0>(dt, n, x, y, z, nullptr, out, stream);
+}
+int carlson_rd(cosmo_dtype dt, int64_t n, const void *x, const void *y, const void *z, void *out, void *stream) {
+    return carlson_entry<1>(dt, n, x, y, z, nullptr, out, stream);
+}
+int carlson_rj(cosmo_dtype dt, int64_t n, const void *x, const void *y, const void *z, const void *p, void *out,
+               void *stream) {
+    return carlson_entry<2>(dt, n, x, y, z, p, out, stream);
+}
+int carlson_rc(cosmo_dtype dt, int64_t n, const void *x, const void *y, void *out, void *stream) {
+    return carlson_entry<3>(dt, n, x, y, nullptr, nullptr, out, stream);
+}
+
+int cosmo_distance(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo, const void *z,
+                   int64_t n_z, int64_t z_cosmo_stride, void *out, int32_t *info, void *workspace,
+                   size_t workspace_bytes, void *stream) {
+    if (!valid_kind(kind)) return COSMO_E_KIND;
+    if (!valid_dtype(dt)) return COSMO_E_DTYPE;
+    if (n_cosmo < 0 || n_z < 0 || z_cosmo_stride < 0) return COSMO_E_ARG;
+    if (n_cosmo > 0 && !params) return COSMO_E_ARG;
+    if (n_cosmo > 0 && n_z > 0 && (!z || !out)) return COSMO_E_ARG;
+    if (check_grid(n_cosmo, n_z) != COSMO_OK) return COSMO_E_ARG;
+    if (n_cosmo == 0) return COSMO_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_init();
+    if (rc != COSMO_OK) return rc;
+    WsLayout L = ws_layout(n_cosmo, 0);
+    Workspace ws;
+    rc = ws.acquire(workspace, workspace_bytes, L.pacc, s);
+    if (rc != COSMO_OK) return rc;
+    CosmoRec *recs = (CosmoRec *)ws.ptr;
+    rc = launch_setup(params, n_cosmo, recs, info, s);
+    if (rc != COSMO_OK || n_z == 0) return rc;
+    if (dt == COSMO_F32)
+        return launch_forward<float>(kind, recs, n_cosmo, (const float *)z, n_z, z_cosmo_stride, (float *)out, info, s);
+    return launch_forward<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, (double *)out, info, s);
+}
+
+int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo, const void *z,
+                       int64_t n_z, int64_t z_cosmo_stride, const void *cot, double *grad_params, void *grad_z,
+                       int32_t *info, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!valid_kind(kind)) return COSMO_E_KIND;
+    if (!valid_dtype(dt)) return COSMO_E_DTYPE;
+    if (n_cosmo < 0 || n_z < 0 || z_cosmo_stride < 0) return COSMO_E_ARG;
+    if (n_cosmo > 0 && !params) return COSMO_E_ARG;
+    if (n_cosmo > 0 && n_z > 0 && (!z || !cot)) return COSMO_E_ARG;
+    if (check_grid(n_cosmo, n_z) != COSMO_OK) return COSMO_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_cosmo == 0) {
+        // empty sum over cosmologies: a shared-z gradient is zero (fill kernel, no memset,
+        // so that the call stays capturable in a HIP graph)
+        if (grad_z && n_z > 0 && z_cosmo_stride == 0) {
+            unsigned nb = (unsigned)((n_z + kBlock - 1) / kBlock);
+            if (dt == COSMO_F32) hipLaunchKernelGGL(k_fill_zero<float>, dim3(nb), dim3(kBlock), 0, s, (float *)grad_z, n_z);
+            else hipLaunchKernelGGL(k_fill_zero<double>, dim3(nb), dim3(kBlock), 0, s, (double *)grad_z, n_z);
+            if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
+        }
+        return COSMO_OK;
+    }
+    int rc = ensure_init();
+    if (rc != COSMO_OK) return rc;
+    WsLayout L = ws_layout(n_cosmo, n_z);
+    Workspace ws;
+    rc = ws.acquire(workspace, workspace_bytes, L.total, s);
+    if (rc != COSMO_OK) return rc;
+    CosmoRec *recs = (CosmoRec *)ws.ptr;
+    rc = launch_setup(params, n_cosmo, recs, info, s);
+    if (rc != COSMO_OK) return rc;
+    if (dt == COSMO_F32)
+        return launch_vjp<float>(kind, recs, n_cosmo, (const float *)z, n_z, z_cosmo_stride, (const float *)cot,
+                                 grad_params, (float *)grad_z, L, (char *)ws.ptr, s);
+    return launch_vjp<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, (const double *)cot,
+                              grad_params, (double *)grad_z, L, (char *)ws.ptr, s);
+}
+
+} // extern "C"

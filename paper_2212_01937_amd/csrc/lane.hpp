@@ -1,0 +1,365 @@
+// lane.hpp -- per-(cosmology, redshift) formulas, one GPU lane each.
+//
+// Notation (x = 1 + z, integration from x1 = 1 to x2 = 1 + z, dz = z):
+//   X_n = sqrt(x2 - rho_n) = sqrt(z + w_n),  Y_n = sqrt(1 - rho_n)     (roots of Q)
+//   Xt  = sqrt(1 - sigma x2),                Yt  = sqrt(1 - sigma)       (radiation factor)
+//   U_m = Xt X_m Y_a Y_b + Yt Y_m X_a X_b    ({m, a, b} = {0, 1, 2})
+// U_m is the paper's u_{lm} of sec. 3.1 (pairing the radiation root l with root
+// m; the complementary pairs coincide, u_{ij} = u_{kl}) divided by sqrt(|rho_l|).
+// For Or = 0 the radiation factor is one and U_m is the u_m of app. B.1.
+//
+//   D_C = (c/H0) beta^(-1/2) 2 dz R_F(U_0^2, U_1^2, U_2^2)                (eqs. 3.7, B.1)
+//   T   = (1/H0) beta^(-1/2) 2 dz { (dz^2/3) prod_n(1 - s rho_n) R_J(U^2, W5)
+//                                   + R_C(S5, Q5) + sigma R_F(U^2) }       (eqs. 3.8, B.2)
+//         with j = 0 the real root of Q:  W5 = U_0^2 + dz^2 (1-s rho_1)(1-s rho_2) rho_0,
+//         Q5 = x2 W5 / ((1-s)(1-s x2)),  S5 = Q5 - dz^2 rho_0 rho_1 rho_2
+//   X   = (c/H0) beta^(-1/2) ...  (eq. 3.9 with i = 0 the real root of Q and l the
+//         radiation root; eq. B.3 for Or = 0), with a Gauss-Legendre route for
+//         lanes where eq. 3.9 cancels (see x_hat).
+// The expressions in sigma are eqs. 3.7-3.9 after the substitution
+// sqrt(z - r_l) = sqrt(|rho_l|) sqrt(1 - sigma x) and the homogeneity of the
+// Carlson integrals; at sigma = 0 they are literally eqs. B.1-B.3.
+#pragma once
+
+#include "carlson.hpp"
+#include "setup.hpp"
+
+namespace cosmo {
+
+template <typename T> __device__ __forceinline__ const LaneConst<T> &lane_of(const CosmoRec &r);
+template <> __device__ __forceinline__ const LaneConst<float> &lane_of<float>(const CosmoRec &r) { return r.f; }
+template <> __device__ __forceinline__ const LaneConst<double> &lane_of<double>(const CosmoRec &r) { return r.d; }
+
+// Geometry of one lane.  For PAIR, slot 1 is complex and slot 2 its conjugate.
+template <typename T, bool PAIR> struct Geo {
+    T Xt, Xt2, X0, X02;
+    T X1re, X1im, X1abs;   // X_1 (PAIR: complex; |X_1|^2 = |z + w_1| in X1abs); REAL: X1re
+    T X2;                  // REAL only
+    T U0, U1re, U1im, U2;  // U_m (PAIR: U_1 complex, U_2 = conj)
+    T T1_0, T2_0;          // the two products making U_0
+    T T1_1re, T1_1im, T2_1re, T2_1im; // same for U_1 (PAIR) ; REAL: T1_1re, T2_1re
+    T T1_2, T2_2;          // REAL only
+    T va, vb;              // structured second/third Carlson arguments
+};
+
+template <typename T, bool PAIR>
+__device__ __forceinline__ void build_u(const LaneConst<T> &k, T z, Geo<T, PAIR> &g) {
+    g.Xt2 = k.yt2 - k.sigma * z; // 1 - sigma (1 + z)
+    g.Xt = Fp<T>::sqrt(g.Xt2);
+    g.X02 = z + k.w0;
+    g.X0 = Fp<T>::sqrt(g.X02);
+    if (PAIR) {
+        T ab;
+        cx<T> X1 = csqrt(mkc(z + k.w1re, k.w1im), ab);
+        g.X1re = X1.re; g.X1im = X1.im; g.X1abs = ab;
+        // U_0 = Xt X_0 |Y_1|^2 + Yt Y_0 |X_1|^2
+        g.T1_0 = g.Xt * g.X0 * k.y1abs2;
+        g.T2_0 = k.yt * k.y0 * ab;
+        g.U0 = g.T1_0 + g.T2_0;
+        // U_1 = Xt Y_0 w + Yt X_0 conj(w),  w = X_1 conj(Y_1)
+        cx<T> w = X1 * mkc(k.y1re, -k.y1im);
+        T cA = g.Xt * k.y0, cB = k.yt * g.X0;
+        g.T1_1re = cA * w.re; g.T1_1im = cA * w.im;
+        g.T2_1re = cB * w.re; g.T2_1im = -cB * w.im;
+        g.U1re = g.T1_1re + g.T2_1re;
+        g.U1im = g.T1_1im + g.T2_1im;
+        g.va = g.U1re * g.U1re - g.U1im * g.U1im;
+        g.vb = T(2) * g.U1re * g.U1im;
+    } else {
+        g.X1re = Fp<T>::sqrt(z + k.w1re);
+        g.X2 = Fp<T>::sqrt(z + k.w2);
+        g.X1im = T(0); g.X1abs = T(0);
+        g.T1_0 = g.Xt * g.X0 * k.y1re * k.y2;
+        g.T2_0 = k.yt * k.y0 * g.X1re * g.X2;
+        g.T1_1re = g.Xt * g.X1re * k.y0 * k.y2;
+        g.T2_1re = k.yt * k.y1re * g.X0 * g.X2;
+        g.T1_2 = g.Xt * g.X2 * k.y0 * k.y1re;
+        g.T2_2 = k.yt * k.y2 * g.X0 * g.X1re;
+        g.T1_1im = g.T2_1im = T(0);
+        g.U0 = g.T1_0 + g.T2_0;
+        g.U1re = g.T1_1re + g.T2_1re;
+        g.U1im = T(0);
+        g.U2 = g.T1_2 + g.T2_2;
+        g.va = g.U1re * g.U1re;
+        g.vb = g.U2 * g.U2;
+    }
+}
+
+// chi / D_H (dimensionless comoving distance), eqs. 3.7 / B.1
+template <typename T, bool PAIR> __device__ __forceinline__ T chi_hat(const LaneConst<T> &k, T z) {
+    Geo<T, PAIR> g;
+    build_u<T, PAIR>(k, z, g);
+    return k.pre * T(2) * z * rf_s<T, PAIR>(g.U0 * g.U0, g.va, g.vb);
+}
+
+// t / (1/H0), eqs. 3.8 / B.2
+template <typename T, bool PAIR> __device__ __forceinline__ T t_hat(const LaneConst<T> &k, T z) {
+    Geo<T, PAIR> g;
+    build_u<T, PAIR>(k, z, g);
+    T V0 = g.U0 * g.U0;
+    T z2 = z * z;
+    T W5 = V0 + z2 * k.c5;
+    T Q5 = (T(1) + z) * W5 * Fp<T>::rcp(k.yt2 * g.Xt2);
+    T S5 = Q5 - z2 * k.rprod;
+    T rf, rj;
+    rfj_s<T, PAIR>(V0, g.va, g.vb, W5, rf, rj);
+    T rc = rc_r(S5, Q5);
+    return k.pre * T(2) * z * (z2 * T(1.0 / 3.0) * k.pre3 * rj + rc + k.sigma * rf);
+}
+
+// sqrt(Q(x)) at x2 = 1 + z and at x1 = 1 (products of the X_n / Y_n)
+template <typename T, bool PAIR>
+__device__ __forceinline__ void sqrtQ(const LaneConst<T> &k, const Geo<T, PAIR> &g, T &f2, T &f1) {
+    if (PAIR) {
+        f2 = g.X0 * g.X1abs;
+        f1 = k.y0 * k.y1abs2;
+    } else {
+        f2 = g.X0 * g.X1re * g.X2;
+        f1 = k.y0 * k.y1re * k.y2;
+    }
+}
+
+// Gauss-Legendre nodes (filled by the host once per device).
+constexpr int kGlNp = 4;         // panels in u = ln(1+z)
+constexpr int kGlN64 = 20;       // nodes per panel, FP64
+constexpr int kGlN32 = 8;        // nodes per panel, FP32
+extern __constant__ double c_gl64_x[kGlN64], c_gl64_w[kGlN64];
+extern __constant__ float c_gl32_x[kGlN32], c_gl32_w[kGlN32];
+
+template <typename Q> struct GlRule;
+template <> struct GlRule<double> {
+    static constexpr int n = kGlN64;
+    static __device__ __forceinline__ double x(int i) { return c_gl64_x[i]; }
+    static __device__ __forceinline__ double w(int i) { return c_gl64_w[i]; }
+    static __device__ __forceinline__ double expm1(double u) { return ::expm1(u); }
+};
+template <> struct GlRule<float> {
+    static constexpr int n = kGlN32;
+    static __device__ __forceinline__ float x(int i) { return c_gl32_x[i]; }
+    static __device__ __forceinline__ float w(int i) { return c_gl32_w[i]; }
+    static __device__ __forceinline__ float expm1(float u) { return expm1f(u); }
+};
+
+// Composite Gauss-Legendre quadrature in u = ln(1+z) of the defining integrals
+// (eqs. 2.3-2.5): power 0 -> int x/E du (D_C), 1 -> int 1/E du (T), 2 -> int x^3/E du
+// (X).  With grad, also the Leibniz derivatives -1/2 int f dP/dtheta / E^3 du for
+// theta = (Om, OL, Or).  E^2 = beta (1 - sigma x) Q(x) in factored form.
+template <typename Q, bool PAIR>
+__device__ void gl_integral(const LaneConst<Q> &k, Q z, int power, bool grad, Q &val, Q gth[3]) {
+    const Q U = Fp<Q>::log1p(z);
+    const Q h = U * Q(1.0 / kGlNp);
+    const Q beta = Fp<Q>::rcp(k.pre * k.pre);
+    Q s = Q(0), g0 = Q(0), g1 = Q(0), g2 = Q(0);
+    for (int p = 0; p < kGlNp; ++p) {
+        const Q mid = h * (Q(p) + Q(0.5));
+        for (int i = 0; i < GlRule<Q>::n; ++i) {
+            Q u = mid + Q(0.5) * h * GlRule<Q>::x(i);
+            Q xm1 = GlRule<Q>::expm1(u);
+            Q x = Q(1) + xm1;
+            Q q = PAIR ? (xm1 + k.w0) * ((xm1 + k.w1re) * (xm1 + k.w1re) + k.w1im * k.w1im)
+                       : (xm1 + k.w0) * (xm1 + k.w1re) * (xm1 + k.w2);
+            Q e2 = beta * (k.yt2 - k.sigma * xm1) * q;
+            Q ie = Fp<Q>::rsqrt(e2);
+            Q fx = power == 0 ? x : (power == 1 ? Q(1) : x * x * x);
+            Q wf = GlRule<Q>::w(i) * fx * ie;
+            s += wf;
+            if (grad) {
+                Q c = Q(-0.5) * wf * ie * ie;
+                Q x2 = x * x;
+                g0 += c * x2 * xm1;                      // x^3 - x^2
+                g1 += c * (-xm1 * (Q(2) + xm1));        // 1 - x^2
+                g2 += c * x2 * xm1 * (Q(2) + xm1);      // x^4 - x^2
+            }
+        }
+    }
+    const Q hh = Q(0.5) * h;
+    val = s * hh;
+    if (grad) { gth[0] = g0 * hh; gth[1] = g1 * hh; gth[2] = g2 * hh; }
+}
+
+// X / (c/H0): eq. B.3 (Or = 0) or eq. 3.9, else the quadrature route.
+// Returns the value; sets used_gl when the quadrature route was taken.
+template <typename T, bool PAIR> __device__ T x_hat(const LaneConst<T> &k, T z, bool &used_gl) {
+    used_gl = false;
+    const bool cubic = (k.sigma == T(0));
+    const bool fp32 = sizeof(T) == 4;
+    if (!cubic && fp32) { // eq. 3.9 cancels by ~|rho_l| >> 1/eps_32: quadrature
+        used_gl = true;
+        T v, gd[3];
+        gl_integral<T, PAIR>(k, z, 2, false, v, gd);
+        return v;
+    }
+    Geo<T, PAIR> g;
+    build_u<T, PAIR>(k, z, g);
+    const T V0 = g.U0 * g.U0;
+    const T z2 = z * z;
+    const T x2 = T(1) + z;
+    T f2, f1;
+    sqrtQ<T, PAIR>(k, g, f2, f1);
+    // (Q(x2) - Q(1))/dz as a divided difference (no cancellation at small z)
+    const T DQ = T(3) + z * (T(3) + z) + k.q2 * (T(2) + z) + k.q1;
+    const T rd = rd_last_x<T, PAIR>(V0, g.va, g.vb); // R_D(U_1^2, U_2^2, U_0^2)
+    if (cubic) {
+        // eq. B.3 with i = 0:  (2 dz/3) { [f]/dz + (3 r0^2 - d01 d02) R_F
+        //                     + 2 S3 [ (dz^2/3) d01 d02 R_D(U1^2, U2^2, U0^2) + X0 Y0 / U0 ] }
+        const T A1 = DQ * Fp<T>::rcp(f2 + f1);
+        const T rf = rf_s<T, PAIR>(V0, g.va, g.vb);
+        const T br = z2 * T(1.0 / 3.0) * k.d0102 * rd + g.X0 * k.y0 * Fp<T>::rcp(g.U0);
+        return k.pre * T(2.0 / 3.0) * z * (A1 + k.xc3 * rf + T(2) * k.xs3 * br);
+    }
+    // eq. 3.9, normalised (i = 0 real root of Q, (j, k) = slots (1, 2), l = radiation root)
+    const T yt2x = k.yt2 * g.Xt2;
+    const T fq2 = f2 * Fp<T>::rsqrt(g.Xt2), fq1 = f1 * Fp<T>::rsqrt(k.yt2);
+    const T num = DQ - k.sigma * (x2 * (T(1) + x2) + k.q2 * x2 - k.q0);
+    const T A = num * Fp<T>::rcp(yt2x * (fq2 + fq1));
+    // U0tilde = U_2^2 + dz^2 d_02 (1 - s r0)  (real)
+    const T u0t = (PAIR ? g.va : g.vb) + z2 * k.om1s0 * k.d02re;
+    const T q0t = u0t * Fp<T>::rcp(g.X02 * k.w0);
+    T rf, rj;
+    rfj_s<T, PAIR>(V0, g.va, g.vb, u0t, rf, rj);
+    const T rc = rc_r(q0t - k.sigma * z2, q0t);
+    const T t2 = k.xc2 * rf;
+    const T B1 = k.om1s12 * (z2 * T(1.0 / 3.0) * k.d0102 * rd + g.X0 * k.y0 * Fp<T>::rcp(g.Xt * k.yt * g.U0));
+    const T B2 = k.op1s3 * (z2 * T(1.0 / 3.0) * k.d0102 * k.om1s0 * rj + rc);
+    const T L = -Fp<T>::rcp(k.sigma);
+    const T sum = A + t2 + L * (B1 - B2);
+    const T mag = Fp<T>::abs(A) + Fp<T>::abs(t2) + L * (Fp<T>::abs(B1) + Fp<T>::abs(B2));
+    if (!(mag <= T(64) * Fp<T>::abs(sum))) { // cancellation beyond ~64 eps: quadrature
+        used_gl = true;
+        T v, gd[3];
+        gl_integral<T, PAIR>(k, z, 2, false, v, gd);
+        return v;
+    }
+    return k.pre * z * sum;
+}
+
+// Curvature transform: S = sinn(chi) (sec. 2.1.1; sinh for Ok > 0, sin for Ok < 0),
+// C = dS/dchi, dS = dS/dOk.  Series in t = Ok chi^2 near flatness.
+template <typename T>
+__device__ __forceinline__ void sinn(T chi, T ok, T sk, T &S, T &C, T &dS) {
+    const T t = ok * chi * chi;
+    if (Fp<T>::abs(t) < T(0.1)) {
+        constexpr int N = sizeof(T) == 4 ? 5 : 8;
+        T s = T(0), c = T(0), d = T(0);
+        // Horner in t from the top: S/chi = sum t^n/(2n+1)!, C = sum t^n/(2n)!,
+        // dS/(chi^3) = sum_{n>=1} n t^(n-1)/(2n+1)!
+        T fs[N + 1], fc[N + 1];
+        fs[0] = T(1); fc[0] = T(1);
+#pragma unroll
+        for (int n = 1; n <= N; ++n) {
+            fs[n] = fs[n - 1] / T((2 * n) * (2 * n + 1));
+            fc[n] = fc[n - 1] / T((2 * n - 1) * (2 * n));
+        }
+#pragma unroll
+        for (int n = N; n >= 0; --n) {
+            s = s * t + fs[n];
+            c = c * t + fc[n];
+            if (n >= 1) d = d * t + T(n) * fs[n];
+        }
+        S = chi * s;
+        C = c;
+        dS = chi * chi * chi * d;
+        return;
+    }
+    if (ok > T(0)) {
+        T e = Fp<T>::exp(sk * chi), ie = Fp<T>::rcp(e);
+        S = T(0.5) * (e - ie) * Fp<T>::rcp(sk);
+        C = T(0.5) * (e + ie);
+    } else {
+        S = Fp<T>::sin(sk * chi) * Fp<T>::rcp(sk);
+        C = Fp<T>::cos(sk * chi);
+    }
+    dS = (chi * C - S) * Fp<T>::rcp(T(2) * ok);
+}
+
+// Observable from chi/D_H for the comoving-distance family.  Also returns the
+// partials needed by the adjoint: dout/dchi, dout/dOk at fixed chi, dout/dz at
+// fixed chi, dout/dH0.
+template <typename T>
+__device__ __forceinline__ T observable(int kind, const LaneConst<T> &k, T chi, T z, T H0inv,
+                                        T &d_chi, T &d_ok, T &d_z, T &d_h) {
+    if (kind == COSMO_DC) {
+        T v = k.dh * chi;
+        d_chi = k.dh; d_ok = T(0); d_z = T(0); d_h = -v * H0inv;
+        return v;
+    }
+    T S, C, dS;
+    sinn(chi, k.ok, k.sk, S, C, dS);
+    const T x = T(1) + z;
+    if (kind == COSMO_DM) {
+        T v = k.dh * S;
+        d_chi = k.dh * C; d_ok = k.dh * dS; d_z = T(0); d_h = -v * H0inv;
+        return v;
+    }
+    if (kind == COSMO_DA) {
+        T ix = Fp<T>::rcp(x);
+        T v = k.dh * S * ix;
+        d_chi = k.dh * C * ix; d_ok = k.dh * dS * ix; d_z = -v * ix; d_h = -v * H0inv;
+        return v;
+    }
+    const T DL = x * k.dh * S;
+    if (kind == COSMO_DL) {
+        d_chi = x * k.dh * C; d_ok = x * k.dh * dS; d_z = k.dh * S; d_h = -DL * H0inv;
+        return DL;
+    }
+    // COSMO_MU: 5 log10(D_L / Mpc) + 25 (fn. 22)
+    const T k5 = T(2.1714724095162591); // 5 / ln 10
+    T iS = Fp<T>::rcp(S);
+    d_chi = k5 * C * iS; d_ok = k5 * dS * iS; d_z = k5 * Fp<T>::rcp(x); d_h = -k5 * H0inv;
+    return T(5) * Fp<T>::log10(DL) + T(25);
+}
+
+// E(z) from eq. 2.2 (for the fundamental-theorem z-derivatives)
+template <typename T> __device__ __forceinline__ T Ez(const LaneConst<T> &k, T z) {
+    const T x = T(1) + z;
+    const T x2 = x * x;
+    return Fp<T>::sqrt((k.Or * x2 + k.Om * x + k.ok) * x2 + k.OL);
+}
+
+// ---------------------------------------------------------------- adjoint
+// Gradient of chi/D_H with respect to the per-cosmology root parameters
+// (sigma, rho_0, rho_1[, rho_2]), by the chain rule through the Carlson
+// arguments: dR_F/d(U_m^2) = -R_D(., ., U_m^2)/6 (eq. 2.10).
+template <typename T, bool PAIR> struct ChiGrad {
+    T chi, dsig, dr0, dr1re, dr1im, dr2;
+};
+
+template <typename T, bool PAIR>
+__device__ __forceinline__ void chi_grad(const LaneConst<T> &k, T z, ChiGrad<T, PAIR> &o) {
+    Geo<T, PAIR> g;
+    build_u<T, PAIR>(k, z, g);
+    T rf, rdx, rdz;
+    cx<T> rdy;
+    rfd_s<T, PAIR>(g.U0 * g.U0, g.va, g.vb, rf, rdx, rdy, rdz);
+    const T scale = k.pre * T(2) * z;
+    o.chi = scale * rf;
+    // G_m = dR_F/dU_m = -U_m R_D(., ., U_m^2)/3 ; a_m = G_m T1_m, b_m = G_m T2_m
+    const T G0 = -g.U0 * rdx * T(1.0 / 3.0);
+    const T a0 = G0 * g.T1_0, b0 = G0 * g.T2_0;
+    // derivative of X_n, Y_n in rho_n: -1/(2 X_n), -1/(2 Y_n); of Xt, Yt in sigma: -x/(2 Xt)
+    if (PAIR) {
+        cx<T> G1 = mkc(g.U1re, g.U1im) * rdy * T(-1.0 / 3.0);
+        cx<T> a1 = G1 * mkc(g.T1_1re, g.T1_1im), b1 = G1 * mkc(g.T2_1re, g.T2_1im);
+        const T A = a0 + T(2) * a1.re, B = b0 + T(2) * b1.re;
+        o.dsig = scale * T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * Fp<T>::rcp(k.yt2));
+        o.dr0 = scale * T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * Fp<T>::rcp(k.w0));
+        cx<T> iX1sq = crcp(mkc(z + k.w1re, k.w1im));
+        cx<T> iW1 = crcp(mkc(k.w1re, k.w1im));
+        // (a1 + B - b1)/X1^2 + (b1 + A - a1)/W1
+        cx<T> d1 = (a1 + B - b1) * iX1sq + (b1 + A - a1) * iW1;
+        o.dr1re = scale * T(-0.5) * d1.re;
+        o.dr1im = scale * T(-0.5) * d1.im;
+        o.dr2 = T(0);
+    } else {
+        const T G1 = -g.U1re * rdy.re * T(1.0 / 3.0), G2 = -g.U2 * rdz * T(1.0 / 3.0);
+        const T a1 = G1 * g.T1_1re, b1 = G1 * g.T2_1re, a2 = G2 * g.T1_2, b2 = G2 * g.T2_2;
+        const T A = a0 + a1 + a2, B = b0 + b1 + b2;
+        o.dsig = scale * T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * Fp<T>::rcp(k.yt2));
+        o.dr0 = scale * T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * Fp<T>::rcp(k.w0));
+        o.dr1re = scale * T(-0.5) * ((a1 + B - b1) * Fp<T>::rcp(z + k.w1re) + (b1 + A - a1) * Fp<T>::rcp(k.w1re));
+        o.dr2 = scale * T(-0.5) * ((a2 + B - b2) * Fp<T>::rcp(z + k.w2) + (b2 + A - a2) * Fp<T>::rcp(k.w2));
+        o.dr1im = T(0);
+    }
+}
+
+} // namespace cosmo

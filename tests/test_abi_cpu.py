@@ -1,0 +1,66 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function that
+include/cosmo.h declares, and rejects bad arguments synchronously with the
+documented status codes (no HIP call is made on these paths)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2212_01937_amd import build, cosmo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if build.stale():
+        build.build()
+    return cosmo.load()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "cosmo.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "cosmo_distance" in names and "cosmo_distance_vjp" in names and "carlson_rj" in names
+    assert set(names) == set(cosmo.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.cosmo_version().startswith(b"cosmo-carlson")
+
+
+def test_argument_errors_are_synchronous(lib):
+    E_ARG, E_KIND, E_DTYPE = -1, -2, -3
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced on these paths
+    null = None
+    # unknown kind / dtype
+    assert lib.cosmo_distance(99, 1, dummy, 1, dummy, 1, 0, dummy, null, null, 0, null) == E_KIND
+    assert lib.cosmo_distance(0, 7, dummy, 1, dummy, 1, 0, dummy, null, null, 0, null) == E_DTYPE
+    assert lib.cosmo_distance_vjp(-1, 1, dummy, 1, dummy, 1, 0, dummy, null, null, null, null, 0, null) == E_KIND
+    # NULL pointers and negative sizes
+    assert lib.cosmo_distance(0, 1, null, 1, dummy, 1, 0, dummy, null, null, 0, null) == E_ARG
+    assert lib.cosmo_distance(0, 1, dummy, -1, dummy, 1, 0, dummy, null, null, 0, null) == E_ARG
+    assert lib.cosmo_distance(0, 1, dummy, 1, dummy, 1, -5, dummy, null, null, 0, null) == E_ARG
+    assert lib.cosmo_distance(0, 1, dummy, 1, null, 1, 0, dummy, null, null, 0, null) == E_ARG
+    assert lib.cosmo_distance_vjp(0, 1, dummy, 1, dummy, 1, 0, null, null, null, null, null, 0, null) == E_ARG
+    assert lib.cosmo_roots(null, 3, dummy, null, null) == E_ARG
+    assert lib.cosmo_roots(dummy, -1, dummy, null, null) == E_ARG
+    assert lib.carlson_rf(0, 4, dummy, dummy, null, dummy, null) == E_ARG
+    assert lib.carlson_rj(1, 4, dummy, dummy, dummy, null, dummy, null) == E_ARG
+    assert lib.carlson_rc(5, 4, dummy, dummy, dummy, null) == E_DTYPE
+    # empty problems are valid no-ops
+    assert lib.cosmo_roots(null, 0, null, null, null) == 0
+    assert lib.carlson_rd(0, 0, null, null, null, null, null) == 0
+    assert lib.cosmo_distance(0, 1, null, 0, null, 0, 0, null, null, null, 0, null) == 0
+
+
+def test_workspace_size_monotone(lib):
+    sz = [cosmo.workspace_size(nc, nz) for nc, nz in ((1, 1), (16, 1000), (256, 10 ** 6))]
+    assert sz[0] > 0 and sz[0] <= sz[1] <= sz[2]
+    b = ctypes.c_size_t(0)
+    assert lib.cosmo_workspace_size(-1, 3, ctypes.byref(b)) == -1

@@ -1,0 +1,175 @@
+"""GPU parity of the forward path against the CPU oracle (element by element).
+
+FP64 path: max relative error <= 1e-12 (D_C, D_M, D_L, D_A, T, X); mu absolute
+<= 1e-11 mag.  FP32 path (FP64 roots): max relative error <= 1e-6, mu <= 1e-4 mag
+absolute (these are the stated bounds of the method's two precisions).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2212_01937_amd import cosmo, workloads
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["DC", "DM", "DL", "MU", "T", "X", "DA"]
+TOL = {torch.float64: 1e-12, torch.float32: 1e-6}
+MU_TOL = {torch.float64: 1e-11, torch.float32: 1e-4}
+
+
+def errs(kind, got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    if kind == "MU":
+        return np.abs(got - ref)
+    return np.abs(got - ref) / np.abs(ref)
+
+
+def check(kind, dt, got, ref, label=""):
+    got = np.asarray(got).ravel()
+    ref = np.asarray(ref).ravel()
+    e = errs(kind, got, ref)
+    tol = MU_TOL[dt] if kind == "MU" else TOL[dt]
+    assert np.all(np.isfinite(got)), (label, kind, dt, "non-finite output")
+    i = int(np.argmax(e))
+    assert e[i] <= tol, f"{label} {kind} {dt}: max err {e[i]:.3e} at flat index {i}"
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_config1_golden(dev, dt):
+    g = np.loadtxt(__file__.rsplit("/", 1)[0] + "/golden/config1_oracle.txt")
+    params, z = workloads.config1()
+    p = torch.tensor(params, device=dev)
+    zt = torch.tensor(z, dtype=dt, device=dev)
+    zref = zt.double().cpu().numpy()  # the oracle sees the same (rounded) redshifts
+    for kind, col in (("DC", 1), ("DL", 2), ("MU", 3)):
+        out = cosmo.cosmo_distance(kind, p, zt)[0].cpu().numpy()
+        ref = g[:, col] if dt == torch.float64 else oracle.distance(kind, params, zref)[0]
+        check(kind, dt, out, ref, "config1")
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_config1_all_kinds(dev, dt):
+    params, z = workloads.config1()
+    p = torch.tensor(params, device=dev)
+    zt = torch.tensor(z, dtype=dt, device=dev)
+    zref = zt.double().cpu().numpy()
+    for kind in KINDS:
+        out = cosmo.cosmo_distance(kind, p, zt)[0].cpu().numpy()
+        check(kind, dt, out, oracle.distance(kind, params, zref)[0], "config1")
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_config2_subset_per_cosmology_z(dev, dt):
+    """37 cosmologies x 300 per-cosmology redshifts: several tiles and a ragged tail."""
+    params, z = workloads.config2(n_cosmo=37, n_z=300, seed=7)
+    p = torch.tensor(params, device=dev)
+    zt = torch.tensor(z, dtype=dt, device=dev)
+    zref = zt.double().cpu().numpy()
+    for kind in KINDS:
+        out, info = cosmo.cosmo_distance(kind, p, zt, info=True)
+        ref = oracle.distance(kind, params, zref, shared_z=False)
+        check(kind, dt, out.cpu().numpy(), ref, "config2-subset")
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_config4_families(dev, dt):
+    """Near-degenerate cosmologies (near-flat, near-cubic, near-double root, near-EdS),
+    z log-uniform on [1e-5, 1e3]."""
+    params, z, fam = workloads.config4(n_per_family=8, n_z=700, seed=11)
+    p = torch.tensor(params, device=dev)
+    zt = torch.tensor(z, dtype=dt, device=dev)
+    zref = zt.double().cpu().numpy()
+    for kind in KINDS:
+        out = cosmo.cosmo_distance(kind, p, zt).cpu().numpy()
+        ref = oracle.distance(kind, params, zref)
+        for f in "ABCD":
+            check(kind, dt, out[fam == f], ref[fam == f], f"config4-{f}")
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_config2_full_size_sampled(dev, dt):
+    params, z = workloads.config2()
+    p = torch.tensor(params, device=dev)
+    zt = torch.tensor(z, dtype=dt, device=dev)
+    ci, zi = workloads.subsample(params.shape[0], z.shape[1], 600)
+    zs = zt.double().cpu().numpy()[ci, zi]
+    for kind in ("DC", "DM", "T", "X"):
+        out = cosmo.cosmo_distance(kind, p, zt)[ci, zi].cpu().numpy()
+        ref = np.array([oracle.distance(kind, params[c:c + 1], np.array([zz]))[0, 0] for c, zz in zip(ci, zs)])
+        check(kind, dt, out, ref, "config2-full-sampled")
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_config5_full_size_sampled(dev, dt):
+    params, z = workloads.config5()
+    p = torch.tensor(params, device=dev)
+    zt = torch.tensor(z, dtype=dt, device=dev)
+    mu = cosmo.cosmo_distance("MU", p, zt)
+    assert mu.shape == (256, 10 ** 6)
+    assert torch.isfinite(mu).all()
+    ci, zi = workloads.subsample(256, 10 ** 6, 600)
+    zs = zt.double().cpu().numpy()[zi]
+    got = mu[ci, zi].double().cpu().numpy()
+    ref = np.array([oracle.distance("MU", params[c:c + 1], np.array([zz]))[0, 0] for c, zz in zip(ci, zs)])
+    check("MU", dt, got, ref, "config5-full-sampled")
+
+
+def test_closed_forms_on_gpu(dev):
+    """Einstein-de Sitter (cubic branch, triple root at x = 0) and the radiationless
+    open matter universe (Mattig) through the full GPU path, FP64."""
+    z = np.array([1e-5, 1e-3, 0.1, 0.5, 1.0, 2.0, 10.0, 100.0, 1000.0])
+    zt = torch.tensor(z, dtype=torch.float64, device=dev)
+    dh = 299792.458 / 70.0
+    x = 1 + z
+    p = torch.tensor([[70.0, 1.0, 0.0, 0.0]], dtype=torch.float64, device=dev)
+    dc = cosmo.cosmo_distance("DC", p, zt)[0].cpu().numpy()
+    assert np.max(np.abs(dc / (-2 * dh * np.expm1(-0.5 * np.log1p(z))) - 1)) < 1e-13
+    xx = cosmo.cosmo_distance("X", p, zt)[0].cpu().numpy()
+    assert np.max(np.abs(xx / ((2.0 / 3.0) * dh * np.expm1(1.5 * np.log1p(z))) - 1)) < 1e-12
+    om = 0.3
+    p = torch.tensor([[70.0, om, 0.0, 0.0]], dtype=torch.float64, device=dev)
+    w2 = np.sqrt(1 + om * z)
+    dm = dh * 2 * z * (1 + z / (1 + w2)) / ((1 + w2) * x)
+    got = cosmo.cosmo_distance("DM", p, zt)[0].cpu().numpy()
+    assert np.max(np.abs(got / dm - 1)) < 1e-12
+
+
+def test_domain_flags_and_nan(dev):
+    """No Big Bang (red region of Fig. 1), degree < 3, and a radiation-only universe
+    outside the method: NaN outputs and the documented info bits."""
+    params = np.array([[70.0, 0.05, 1.3, 0.0],      # two positive real roots: RED
+                       [70.0, 0.0, 1.0, 0.0],       # de Sitter: degree 0
+                       [70.0, 0.0, 0.0, 0.0],       # Milne: degree 2
+                       [70.0, 0.3, 0.7, 0.0],       # fine
+                       [-5.0, 0.3, 0.7, 0.0]])      # H0 <= 0
+    p = torch.tensor(params, device=dev)
+    zt = torch.tensor([0.5, 1.0], dtype=torch.float64, device=dev)
+    out, info = cosmo.cosmo_distance("DC", p, zt, info=True)
+    out = out.cpu().numpy()
+    info = info.cpu().numpy()
+    assert info[0] & cosmo.INFO["RED"] and np.all(np.isnan(out[0]))
+    assert info[1] & cosmo.INFO["DOMAIN"] and np.all(np.isnan(out[1]))
+    assert info[2] & cosmo.INFO["DOMAIN"] and np.all(np.isnan(out[2]))
+    assert info[3] & cosmo.INFO["CUBIC"] and np.all(np.isfinite(out[3]))
+    assert info[4] & cosmo.INFO["DOMAIN"] and np.all(np.isnan(out[4]))
+
+
+def test_empty_and_tiny_inputs(dev):
+    p = torch.tensor([[70.0, 0.3, 0.7, 9e-5]], dtype=torch.float64, device=dev)
+    out = cosmo.cosmo_distance("DC", p, torch.empty(0, dtype=torch.float64, device=dev))
+    assert out.shape == (1, 0)
+    out = cosmo.cosmo_distance("DC", torch.empty((0, 4), dtype=torch.float64, device=dev),
+                               torch.tensor([0.5], dtype=torch.float64, device=dev))
+    assert out.shape == (0, 1)
+    out = cosmo.cosmo_distance("DC", p, torch.tensor([0.0, 1e-12], dtype=torch.float64, device=dev)).cpu().numpy()
+    assert out[0, 0] == 0.0 and abs(out[0, 1] / (299792.458 / 70 * 1e-12) - 1) < 1e-10
+
+
+def test_determinism(dev):
+    params, z = workloads.config2(n_cosmo=64, n_z=512, seed=3)
+    p = torch.tensor(params, device=dev)
+    zt = torch.tensor(z, dtype=torch.float32, device=dev)
+    a = cosmo.cosmo_distance("T", p, zt)
+    b = cosmo.cosmo_distance("T", p, zt)
+    assert torch.equal(a, b)
