@@ -238,8 +238,11 @@ template <typename T, bool PAIR> __device__ __forceinline__ T mean3(T x, T a, T 
 
 // max_i |A0 - x_i| for a structured triple
 template <typename T, bool PAIR> __device__ __forceinline__ T spread3(T A0, T x, T a, T b) {
-    T m = tmax(Fp<T>::abs(A0 - x), PAIR ? Fp<T>::sqrt((A0 - a) * (A0 - a) + b * b) : Fp<T>::abs(A0 - a));
-    return PAIR ? m : tmax(m, Fp<T>::abs(A0 - b));
+    if (PAIR) {
+        T dx = A0 - x, da = A0 - a;
+        return Fp<T>::sqrt(tmax(dx * dx, da * da + b * b));
+    }
+    return tmax(tmax(Fp<T>::abs(A0 - x), Fp<T>::abs(A0 - a)), Fp<T>::abs(A0 - b));
 }
 
 // Symmetric functions of the deviations of (y, z) about A0, scaled by g:
@@ -357,13 +360,16 @@ template <typename T, bool PAIR> __device__ T rd_last_x(T x, T a, T b) {
 // dR_F/dx_k = -R_D(., ., x_k)/6 (eq. 2.10), from one duplication sequence.
 // Outputs: rf; rdx = R_D(y, z, x); rdy = R_D(x, z, y) (complex for PAIR; for a
 // PAIR triple R_D(x, y, z) = conj(rdy)); rdz = R_D(x, y, z) for real triples.
+// rdx is not accumulated: it follows from the cyclic identity
+// R_D(x,y,z) + R_D(y,z,x) + R_D(z,x,y) = 3/sqrt(xyz) (DLMF 19.21.7), whose terms are
+// of one size on these argument triples (cancellation below a factor 5).
 template <typename T, bool PAIR>
 __device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
     const T AF0 = mean3<T, PAIR>(x, a, b);
     const T x0 = x, a0 = a, b0 = b;
     const T QF = spread3<T, PAIR>(AF0, x, a, b);
     // The R_D means (3 A_F + 2 x_k)/5 deviate from the arguments by at most 1.4 QF.
-    T AF = AF0, f = T(1), accx = T(0), accz = T(0);
+    T AF = AF0, f = T(1), accz = T(0);
     cx<T> accy = mkc(T(0), T(0));
     for (int m = 0; m < kMaxDup && T(1.4) * QF * f > Fp<T>::tau5 * Fp<T>::abs(AF); ++m) {
         T sx = Fp<T>::sqrt(x);
@@ -379,7 +385,6 @@ __device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
             accy.re += f * Fp<T>::rcp(sy * (a + lam));
             accz += f * Fp<T>::rcp(sz * (b + lam));
         }
-        accx += f * Fp<T>::rcp(sx * (x + lam));
         x = (x + lam) * T(0.25);
         a = (a + lam) * T(0.25);
         b = PAIR ? b * T(0.25) : (b + lam) * T(0.25);
@@ -391,15 +396,6 @@ __device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
         T X = (AF0 - x0) * g, s, q;
         yz_sym<T, PAIR>(AF0, a0, b0, g, s, q);
         rf = rf_tail(q - X * X, X * q) * Fp<T>::rsqrt(AF);
-    }
-    {   // R_D(y, z, x)
-        T A0 = (T(3) * AF0 + T(2) * x0) * T(0.2), A = (T(3) * AF + T(2) * x) * T(0.2);
-        T g = f * Fp<T>::rcp(A), s, q;
-        yz_sym<T, PAIR>(A0, a0, b0, g, s, q);
-        T Z = s * T(-1.0 / 3.0), Z2 = Z * Z;
-        T E2 = q - T(6) * Z2, E3 = (T(3) * q - T(8) * Z2) * Z;
-        T E4 = T(3) * (q - Z2) * Z2, E5 = q * Z2 * Z;
-        rdx = rj_tail(E2, E3, E4, E5) * f * Fp<T>::rcp(A) * Fp<T>::rsqrt(A) + T(3) * accx;
     }
     if (PAIR) {
         // R_D(x, z, y) with y = a + i b last, z = conj(y)
@@ -413,6 +409,8 @@ __device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
         cx<T> E4 = (XY - Z2) * Z2 * T(3), E5 = XY * Z2 * Z;
         rdy = rj_tail(E2, E3, E4, E5) * crcp(A * csqrt(A)) * f + accy * T(3);
         rdz = T(0);
+        // 3/sqrt(x y conj(y)) = 3 / (sqrt(x) |y|)
+        rdx = T(3) * Fp<T>::rsqrt(x0) * Fp<T>::rsqrt(a0 * a0 + b0 * b0) - T(2) * rdy.re;
     } else {
         // R_D(x, z, y) and R_D(x, y, z)
         T A0 = (T(3) * AF0 + T(2) * a0) * T(0.2), A = (T(3) * AF + T(2) * a) * T(0.2);
@@ -431,7 +429,100 @@ __device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
         Z2 = Z * Z;
         rdz = rj_tail(XY - T(6) * Z2, (T(3) * XY - T(8) * Z2) * Z, T(3) * (XY - Z2) * Z2, XY * Z2 * Z) *
                   f * Fp<T>::rcp(A) * Fp<T>::rsqrt(A) + T(3) * accz;
+        rdx = T(3) * Fp<T>::rsqrt(x0 * a0 * b0) - rdy.re - rdz;
     }
+}
+
+// R_F, R_J(x, y, z, p) and the R_D(., ., x_k) of the triple, from one duplication
+// sequence (the adjoint of the time coordinate).  p real > 0.  Output conventions
+// as rfd_s.
+template <typename T, bool PAIR>
+__device__ void rfjd_s(T x, T a, T b, T p, T &rf, T &rj, T &rdx, cx<T> &rdy, T &rdz) {
+    const T AF0 = mean3<T, PAIR>(x, a, b);
+    const T AJ0 = (T(3) * AF0 + T(2) * p) * T(0.2);
+    const T x0 = x, a0 = a, b0 = b, p0 = p;
+    const T QF = spread3<T, PAIR>(AF0, x, a, b);
+    const T QJ = tmax(spread3<T, PAIR>(AJ0, x, a, b), Fp<T>::abs(AJ0 - p));
+    const T delta = PAIR ? (p - x) * ((p - a) * (p - a) + b * b) : (p - x) * (p - a) * (p - b);
+    T AF = AF0, AJ = AJ0, f = T(1), acc = T(0), accz = T(0);
+    cx<T> accy = mkc(T(0), T(0));
+    for (int m = 0; m < kMaxDup && (T(1.4) * QF * f > Fp<T>::tau5 * Fp<T>::abs(AF) ||
+                                   QJ * f > Fp<T>::tau5 * Fp<T>::abs(AJ)); ++m) {
+        T sx = Fp<T>::sqrt(x), sp = Fp<T>::sqrt(p);
+        T lam, d;
+        if (PAIR) {
+            T r;
+            cx<T> sy = csqrt(mkc(a, b), r);
+            lam = sx * (T(2) * sy.re) + r;
+            d = (sp + sx) * (p + T(2) * sp * sy.re + r);
+            accy = accy + crcp(sy * (mkc(a, b) + lam)) * f;
+        } else {
+            T sy = Fp<T>::sqrt(a), sz = Fp<T>::sqrt(b);
+            lam = sx * (sy + sz) + sy * sz;
+            d = (sp + sx) * (sp + sy) * (sp + sz);
+            accy.re += f * Fp<T>::rcp(sy * (a + lam));
+            accz += f * Fp<T>::rcp(sz * (b + lam));
+        }
+        T rdd = Fp<T>::rcp(d);
+        acc += f * rc1_r(delta * rdd * rdd * (f * f * f)) * rdd;
+        x = (x + lam) * T(0.25);
+        a = (a + lam) * T(0.25);
+        b = PAIR ? b * T(0.25) : (b + lam) * T(0.25);
+        p = (p + lam) * T(0.25);
+        AF = (AF + lam) * T(0.25);
+        AJ = (AJ + lam) * T(0.25);
+        f *= T(0.25);
+    }
+    {
+        T g = f * Fp<T>::rcp(AF);
+        T X = (AF0 - x0) * g, s, q;
+        yz_sym<T, PAIR>(AF0, a0, b0, g, s, q);
+        rf = rf_tail(q - X * X, X * q) * Fp<T>::rsqrt(AF);
+    }
+    {
+        T g = f * Fp<T>::rcp(AJ);
+        T X = (AJ0 - x0) * g, s, q;
+        yz_sym<T, PAIR>(AJ0, a0, b0, g, s, q);
+        T P = (AJ0 - p0) * g;
+        T sym2 = X * s + q, xyz = X * q, P2 = P * P;
+        T E2 = sym2 - T(3) * P2;
+        T E3 = xyz + T(2) * E2 * P + T(4) * P2 * P;
+        T E4 = (T(2) * xyz + E2 * P + T(3) * P2 * P) * P;
+        T E5 = xyz * P2;
+        rj = rj_tail(E2, E3, E4, E5) * f * Fp<T>::rcp(AJ) * Fp<T>::rsqrt(AJ) + T(6) * acc;
+    }
+    if (PAIR) {
+        cx<T> y0 = mkc(a0, b0), y = mkc(a, b);
+        cx<T> A0 = (y0 * T(2) + T(3) * AF0) * T(0.2), A = (y * T(2) + T(3) * AF) * T(0.2);
+        cx<T> g = crcp(A) * f;
+        cx<T> X = (A0 - x0) * g, Y = (A0 - conj(y0)) * g;
+        cx<T> Z = (X + Y) * T(-1.0 / 3.0);
+        cx<T> XY = X * Y, Z2 = Z * Z;
+        cx<T> E2 = XY - Z2 * T(6), E3 = (XY * T(3) - Z2 * T(8)) * Z;
+        cx<T> E4 = (XY - Z2) * Z2 * T(3), E5 = XY * Z2 * Z;
+        rdy = rj_tail(E2, E3, E4, E5) * crcp(A * csqrt(A)) * f + accy * T(3);
+        rdz = T(0);
+        rdx = T(3) * Fp<T>::rsqrt(x0) * Fp<T>::rsqrt(a0 * a0 + b0 * b0) - T(2) * rdy.re;
+    } else {
+        T A0 = (T(3) * AF0 + T(2) * a0) * T(0.2), A = (T(3) * AF + T(2) * a) * T(0.2);
+        T g = f * Fp<T>::rcp(A);
+        T X = (A0 - x0) * g, Y = (A0 - b0) * g, Z = (X + Y) * T(-1.0 / 3.0);
+        T XY = X * Y, Z2 = Z * Z;
+        rdy = mkc(rj_tail(XY - T(6) * Z2, (T(3) * XY - T(8) * Z2) * Z, T(3) * (XY - Z2) * Z2, XY * Z2 * Z) *
+                          f * Fp<T>::rcp(A) * Fp<T>::rsqrt(A) + T(3) * accy.re, T(0));
+        A0 = (T(3) * AF0 + T(2) * b0) * T(0.2);
+        A = (T(3) * AF + T(2) * b) * T(0.2);
+        g = f * Fp<T>::rcp(A);
+        X = (A0 - x0) * g;
+        Y = (A0 - a0) * g;
+        Z = (X + Y) * T(-1.0 / 3.0);
+        XY = X * Y;
+        Z2 = Z * Z;
+        rdz = rj_tail(XY - T(6) * Z2, (T(3) * XY - T(8) * Z2) * Z, T(3) * (XY - Z2) * Z2, XY * Z2 * Z) *
+                  f * Fp<T>::rcp(A) * Fp<T>::rsqrt(A) + T(3) * accz;
+        rdx = T(3) * Fp<T>::rsqrt(x0 * a0 * b0) - rdy.re - rdz;
+    }
+    if (!(p0 > T(0))) rj = Fp<T>::nan();
 }
 
 } // namespace cosmo

@@ -2,7 +2,7 @@
 //
 // The FP32 path uses the hardware transcendental instructions (v_sqrt_f32,
 // v_rcp_f32, v_rsq_f32: about 1 ulp) instead of the correctly rounded sequences;
-// the FP64 path uses correctly rounded sqrt and division.
+// the FP64 path uses correctly rounded sqrt and Newton-refined reciprocals.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,8 +36,19 @@ template <> struct Fp<float> {
 
 template <> struct Fp<double> {
     static __device__ __forceinline__ double sqrt(double x) { return __builtin_sqrt(x); }
-    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / __builtin_sqrt(x); }
+    // Reciprocal and reciprocal square root: hardware estimate refined by two Newton
+    // steps (error within 2 ulp for the positive normal arguments used here).
+    static __device__ __forceinline__ double rcp(double x) {
+        double y = __builtin_amdgcn_rcp(x);
+        y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+        return __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+    }
+    static __device__ __forceinline__ double rsqrt(double x) {
+        double y = __builtin_amdgcn_rsq(x);
+        double h = 0.5 * x;
+        y = y * __builtin_fma(-h * y, y, 1.5);
+        return y * __builtin_fma(-h * y, y, 1.5);
+    }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
     static __device__ __forceinline__ double abs(double x) { return __builtin_fabs(x); }
     static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
@@ -79,16 +90,18 @@ template <typename T> __device__ __forceinline__ cx<T> crcp(cx<T> a) {
 template <typename T> __device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> b) { return a * crcp(b); }
 
 // Principal square root; also returns |w| (= |sqrt(w)|^2), which callers reuse.
+// With t = (|w| + |Re w|)/2 and q = 1/sqrt(t), the larger component of sqrt(w)
+// is t q and the smaller |Im w| q / 2 (no cancellation on either half-plane).
 template <typename T> __device__ __forceinline__ cx<T> csqrt(cx<T> w, T &absw) {
     T r = cabs(w);
     absw = r;
     bool pos = w.re >= T(0);
-    T t = T(0.5) * (pos ? r + w.re : r - w.re);
-    T s = Fp<T>::sqrt(t);
-    T o = (s > T(0)) ? T(0.5) * Fp<T>::abs(w.im) * Fp<T>::rcp(s) : T(0);
+    T t = T(0.5) * (r + Fp<T>::abs(w.re));
+    T q = (t > T(0)) ? Fp<T>::rsqrt(t) : T(0);
+    T big = t * q, small = T(0.5) * Fp<T>::abs(w.im) * q;
     cx<T> res;
-    res.re = pos ? s : o;
-    res.im = pos ? (w.im >= T(0) ? o : -o) : (w.im >= T(0) ? s : -s);
+    res.re = pos ? big : small;
+    res.im = pos ? (w.im >= T(0) ? small : -small) : (w.im >= T(0) ? big : -big);
     return res;
 }
 template <typename T> __device__ __forceinline__ cx<T> csqrt(cx<T> w) {
@@ -96,15 +109,13 @@ template <typename T> __device__ __forceinline__ cx<T> csqrt(cx<T> w) {
     return csqrt(w, r);
 }
 
-// Real part of the principal square root only (cheaper: no division on the
-// w.re >= 0 branch).  Used where only Re(sqrt(w)) and |w| are needed.
+// Real part of the principal square root and |w| only (one sqrt, one rsqrt).
 template <typename T> __device__ __forceinline__ T csqrt_re(T wre, T wim, T &absw) {
     T r = Fp<T>::sqrt(wre * wre + wim * wim);
     absw = r;
-    bool pos = wre >= T(0);
-    T t = T(0.5) * (pos ? r + wre : r - wre);
-    T s = Fp<T>::sqrt(t);
-    return pos ? s : ((s > T(0)) ? T(0.5) * Fp<T>::abs(wim) * Fp<T>::rcp(s) : T(0));
+    T t = T(0.5) * (r + Fp<T>::abs(wre));
+    T q = (t > T(0)) ? Fp<T>::rsqrt(t) : T(0);
+    return (wre >= T(0) ? t : T(0.5) * Fp<T>::abs(wim)) * q;
 }
 
 template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(const CosmoRec *__restrict__
 constexpr int kAcc = 8;
 
 __device__ __forceinline__ bool direct_mode(int kind, const CosmoRec &r, bool fp32) {
-    if (kind == COSMO_T || kind == COSMO_X) return true;
+    if (kind == COSMO_X) return true;
     return r.minsep < (fp32 ? 2e-2 : 1e-4);
 }
 
@@ -119,6 +119,20 @@ __device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kA
     const LaneConst<T> &k = lane_of<T>(r);
     const bool fp32 = sizeof(T) == 4;
     const T H0inv = T(1.0 / r.H0);
+    if (KIND == COSMO_T && !direct_mode(KIND, r, fp32)) {
+        // time coordinate: Carlson derivatives (eqs. 2.10, 2.11) and the root chain
+        TGrad<T, PAIR> tg;
+        t_grad<T, PAIR>(k, z, tg);
+        const T w = cot * k.th;
+        acc[0] += w * tg.t;
+        acc[1] += w * tg.dsig;
+        acc[2] += w * tg.dr0;
+        acc[3] += w * tg.dr1re;
+        acc[4] += w * (PAIR ? tg.dr1im : tg.dr2);
+        acc[6] += -w * tg.t * H0inv;
+        gz = w * Fp<T>::rcp((T(1) + z) * Ez<T>(k, z));
+        return;
+    }
     if (KIND == COSMO_T || KIND == COSMO_X) {
         T val, g[3];
         gl_integral<T, PAIR>(k, z, KIND == COSMO_T ? 1 : 2, true, val, g);

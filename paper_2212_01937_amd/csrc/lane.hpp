@@ -362,4 +362,116 @@ __device__ __forceinline__ void chi_grad(const LaneConst<T> &k, T z, ChiGrad<T, 
     }
 }
 
+// Chain from dF/dV_m (V_m = U_m^2) to the root parameters through the U-products:
+// with G_m = dF/dV_m 2 U_m, a_m = G_m T1_m, b_m = G_m T2_m, A = sum a, B = sum b:
+//   dF/dsigma += -1/2 [ x2 A / Xt^2 + B / Yt^2 ],
+//   dF/drho_n += -1/2 [ (a_n + B - b_n)/X_n^2 + (b_n + A - a_n)/Y_n^2 ].
+// For PAIR the slot-1 quantities are complex and slot 2 is their conjugate.
+template <typename T, bool PAIR>
+__device__ __forceinline__ void u_chain(const LaneConst<T> &k, const Geo<T, PAIR> &g, T z, T dV0, cx<T> dV1,
+                                        T dV2, T &dsig, T &dr0, cx<T> &dr1, T &dr2) {
+    const T G0 = dV0 * T(2) * g.U0;
+    const T a0 = G0 * g.T1_0, b0 = G0 * g.T2_0;
+    if (PAIR) {
+        cx<T> G1 = dV1 * mkc(g.U1re, g.U1im) * T(2);
+        cx<T> a1 = G1 * mkc(g.T1_1re, g.T1_1im), b1 = G1 * mkc(g.T2_1re, g.T2_1im);
+        const T A = a0 + T(2) * a1.re, B = b0 + T(2) * b1.re;
+        dsig += T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * Fp<T>::rcp(k.yt2));
+        dr0 += T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * Fp<T>::rcp(k.w0));
+        cx<T> iX1sq = crcp(mkc(z + k.w1re, k.w1im));
+        cx<T> iW1 = crcp(mkc(k.w1re, k.w1im));
+        dr1 = dr1 + ((a1 + B - b1) * iX1sq + (b1 + A - a1) * iW1) * T(-0.5);
+    } else {
+        const T G1 = dV1.re * T(2) * g.U1re, G2 = dV2 * T(2) * g.U2;
+        const T a1 = G1 * g.T1_1re, b1 = G1 * g.T2_1re, a2 = G2 * g.T1_2, b2 = G2 * g.T2_2;
+        const T A = a0 + a1 + a2, B = b0 + b1 + b2;
+        dsig += T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * Fp<T>::rcp(k.yt2));
+        dr0 += T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * Fp<T>::rcp(k.w0));
+        dr1.re += T(-0.5) * ((a1 + B - b1) * Fp<T>::rcp(z + k.w1re) + (b1 + A - a1) * Fp<T>::rcp(k.w1re));
+        dr2 += T(-0.5) * ((a2 + B - b2) * Fp<T>::rcp(z + k.w2) + (b2 + A - a2) * Fp<T>::rcp(k.w2));
+    }
+}
+
+// Gradient of t/(1/H0) (eq. 3.8 / B.2 in the normalised form of t_hat) with respect
+// to (sigma, rho_0, rho_1[, rho_2]) at fixed beta:
+//   B = (dz^2/3) P3 R_J(V, W) + R_C(S, Q) + sigma R_F(V),  t_hat = beta^(-1/2) 2 dz B.
+// Carlson derivatives: dR_F/dV_m = -R_D(., ., V_m)/6 (eq. 2.10); dR_J/dV_m =
+// (R_J - R_D(., ., V_m)) / (2 (W - V_m)) (eq. 2.11); dR_J/dW from Euler's relation
+// for the degree -3/2 homogeneous R_J (W dR_J/dW = -3/2 R_J - sum V_m dR_J/dV_m);
+// dR_C(S, Q)/dS = -R_D(Q, Q, S)/6 and Q dR_C/dQ = -R_C/2 - S dR_C/dS.
+template <typename T, bool PAIR> struct TGrad {
+    T t, dsig, dr0, dr1re, dr1im, dr2;
+};
+
+template <typename T, bool PAIR>
+__device__ void t_grad(const LaneConst<T> &k, T z, TGrad<T, PAIR> &o) {
+    Geo<T, PAIR> g;
+    build_u<T, PAIR>(k, z, g);
+    const T V0 = g.U0 * g.U0;
+    const T z2 = z * z, x2 = T(1) + z;
+    const T C5 = k.c5;
+    const T W = V0 + z2 * C5;
+    const T iD = Fp<T>::rcp(k.yt2 * g.Xt2);
+    const T Qv = x2 * W * iD;
+    const T S = Qv - z2 * k.rprod;
+    T rf, rj, rdx, rdz;
+    cx<T> rdy;
+    rfjd_s<T, PAIR>(V0, g.va, g.vb, W, rf, rj, rdx, rdy, rdz);
+    const T rc = rc_r(S, Qv);
+    const T dRC_S = rd_last_x<T, false>(S, Qv, Qv) * T(-1.0 / 6.0); // -R_D(Q, Q, S)/6
+    const T dRC_Q = (T(-0.5) * rc - S * dRC_S) * Fp<T>::rcp(Qv);
+    const T P3 = k.pre3;
+    const T c3 = z2 * T(1.0 / 3.0) * P3;
+    // R_J partials in its three triple arguments (eq. 2.11); W - V0 = dz^2 C5 exactly
+    const T dJ0 = (rj - rdx) * Fp<T>::rcp(T(2) * z2 * C5);
+    cx<T> dJ1;
+    T dJ2 = T(0), sumVdJ;
+    if (PAIR) {
+        dJ1 = (mkc(rj, T(0)) - rdy) * crcp(mkc(W - g.va, -g.vb) * T(2));
+        sumVdJ = V0 * dJ0 + T(2) * (g.va * dJ1.re - g.vb * dJ1.im);
+    } else {
+        dJ1 = mkc((rj - rdy.re) * Fp<T>::rcp(T(2) * (W - g.va)), T(0));
+        dJ2 = (rj - rdz) * Fp<T>::rcp(T(2) * (W - g.vb));
+        sumVdJ = V0 * dJ0 + g.va * dJ1.re + g.vb * dJ2;
+    }
+    const T dJW = (T(-1.5) * rj - sumVdJ) * Fp<T>::rcp(W);
+    const T dRC_sum = dRC_S + dRC_Q; // S = Q - dz^2 Rp moves with Q
+    const T dB_dW = c3 * dJW + dRC_sum * x2 * iD;
+    const T dB_dV0 = c3 * dJ0 - k.sigma * rdx * T(1.0 / 6.0) + dB_dW;
+    const cx<T> dB_dV1 = dJ1 * c3 - rdy * (k.sigma * T(1.0 / 6.0));
+    const T dB_dV2 = PAIR ? T(0) : c3 * dJ2 - k.sigma * rdz * T(1.0 / 6.0);
+    // explicit dependence of P3, C5, Rp and Q on sigma and the roots
+    const T s = k.sigma;
+    const cx<T> om1 = mkc(T(1) - s * k.r1re, -s * k.r1im);
+    const cx<T> om2 = PAIR ? conj(om1) : mkc(T(1) - s * k.r2, T(0));
+    const T om0 = T(1) - s * k.r0;
+    const cx<T> r1 = mkc(k.r1re, k.r1im);
+    const cx<T> r2 = PAIR ? conj(r1) : mkc(k.r2, T(0));
+    const T om12 = (om1 * om2).re;
+    // rho_1 om_2 + rho_2 om_1 (real in both root structures)
+    const T r1o2_r2o1 = (r1 * om2).re + (r2 * om1).re;
+    const T dP3_ds = -(k.r0 * om12 + om0 * r1o2_r2o1);
+    const T dC5_ds = -k.r0 * r1o2_r2o1;
+    const T dQ_ds = Qv * (Fp<T>::rcp(k.yt2) + x2 * Fp<T>::rcp(g.Xt2));
+    T dsig = (z2 * T(1.0 / 3.0)) * rj * dP3_ds + dB_dW * z2 * dC5_ds + dRC_sum * dQ_ds + rf;
+    // rho_0
+    T dr0 = (z2 * T(1.0 / 3.0)) * rj * (-s * om12) + dB_dW * z2 * om12 + dRC_S * (-z2 * (r1 * r2).re);
+    // rho_1 (complex for PAIR)
+    cx<T> dr1 = (om0 * om2 * (-s)) * ((z2 * T(1.0 / 3.0)) * rj) + om2 * (-s * k.r0) * (dB_dW * z2) +
+                (r2 * k.r0) * (-z2 * dRC_S);
+    T dr2 = PAIR ? T(0)
+                 : ((z2 * T(1.0 / 3.0)) * rj * (-s * om0 * om1.re) + dB_dW * z2 * (-s * om1.re * k.r0) +
+                    dRC_S * (-z2 * k.r0 * k.r1re));
+    // through the Carlson arguments V_m(U_m)
+    u_chain<T, PAIR>(k, g, z, dB_dV0, dB_dV1, dB_dV2, dsig, dr0, dr1, dr2);
+    const T scale = k.pre * T(2) * z;
+    const T Bv = c3 * rj + rc + s * rf;
+    o.t = scale * Bv;
+    o.dsig = scale * dsig;
+    o.dr0 = scale * dr0;
+    o.dr1re = scale * dr1.re;
+    o.dr1im = scale * dr1.im;
+    o.dr2 = scale * dr2;
+}
+
 } // namespace cosmo

@@ -184,3 +184,36 @@ def test_vjp_empty(dev):
     gp, gz = cosmo.cosmo_distance_vjp("DC", torch.empty((0, 4), **f64),
                                       torch.tensor([0.5, 1.0], **f64), torch.empty((0, 2), **f64))
     assert gp.shape == (0, 4) and torch.all(gz == 0)
+
+
+def test_config3_full_size_likelihood(dev):
+    """The SN Ia likelihood at full size (64 parameter samples x 1e6 SNe): sampled mu
+    against the oracle, and the FP32 path's loss and gradients against the FP64 path
+    (both validated element by element at small size above)."""
+    fid, zs, noise, th = workloads.config3()
+    mu_obs = oracle.distance("MU", fid, zs[:2000])[0]
+    # fiducial mu for all SNe from the validated FP64 GPU path is not used: the
+    # observed magnitudes come from the oracle on the full redshift set
+    mu_fid = np.empty_like(zs)
+    for s0 in range(0, zs.shape[0], 200000):
+        mu_fid[s0:s0 + 200000] = oracle.distance("MU", fid, zs[s0:s0 + 200000])[0]
+    assert np.allclose(mu_fid[:2000], mu_obs)
+    mo = mu_fid + noise
+    res = {}
+    for dt in (torch.float64, torch.float32):
+        p = torch.tensor(th, device=dev, requires_grad=True)
+        zt = torch.tensor(zs, dtype=dt, device=dev, requires_grad=True)
+        mu = cosmo.distance("MU", p, zt)
+        loss = (-(torch.tensor(mo, dtype=dt, device=dev)[None, :] - mu) ** 2 / (2 * 0.1 ** 2)).sum(dtype=torch.float64)
+        loss.backward()
+        ci, zi = workloads.subsample(th.shape[0], zs.shape[0], 100, seed=303)
+        zr = zt.detach().double().cpu().numpy()
+        got = mu.detach()[torch.tensor(ci, device=dev), torch.tensor(zi, device=dev)].double().cpu().numpy()
+        ref = np.array([oracle.distance("MU", th[c:c + 1], np.array([zr[i]]))[0, 0] for c, i in zip(ci, zi)])
+        assert np.max(np.abs(got - ref)) < (1e-11 if dt == torch.float64 else 1e-4)
+        res[dt] = (loss.item(), p.grad.cpu().numpy(), zt.grad.double().cpu().numpy())
+    l64, g64, z64 = res[torch.float64]
+    l32, g32, z32 = res[torch.float32]
+    assert abs(l32 - l64) <= 5e-4 * abs(l64)
+    assert np.max(np.abs(g32[:, :3] - g64[:, :3]) / np.maximum(np.abs(g64[:, :3]), 1e-3 * np.abs(g64[:, :3]).max())) < 1e-2
+    assert np.max(np.abs(z32 - z64)) <= 1e-3 * np.max(np.abs(z64))

@@ -173,3 +173,19 @@ def test_determinism(dev):
     a = cosmo.cosmo_distance("T", p, zt)
     b = cosmo.cosmo_distance("T", p, zt)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_config4_full_size_sampled(dev, dt):
+    """1024 near-degenerate cosmologies x 4096 shared z on [1e-5, 1e3], sampled per family."""
+    params, z, fam = workloads.config4()
+    p = torch.tensor(params, device=dev)
+    zt = torch.tensor(z, dtype=dt, device=dev)
+    zr = zt.double().cpu().numpy()
+    ci, zi = workloads.subsample(params.shape[0], z.shape[0], 400, seed=404)
+    for kind in ("DC", "DM", "T", "X", "MU"):
+        out = cosmo.cosmo_distance(kind, p, zt)[ci, zi].double().cpu().numpy()
+        ref = np.array([oracle.distance(kind, params[c:c + 1], np.array([zr[i]]))[0, 0] for c, i in zip(ci, zi)])
+        for f in "ABCD":
+            m = fam[ci] == f
+            check(kind, dt, out[m], ref[m], f"config4-full-{f}")
