@@ -22,6 +22,14 @@ template <> struct Fp<float> {
     static __device__ __forceinline__ float log(float x) { return logf(x); }
     static __device__ __forceinline__ float log1p(float x) { return log1pf(x); }
     static __device__ __forceinline__ float log10(float x) { return log10f(x); }
+    // log10 through the hardware base-2 logarithm (v_log_f32, about 1 ulp on normal inputs)
+    static __device__ __forceinline__ float log10_fast(float x) {
+        return __builtin_amdgcn_logf(x) * 0.30102999566398120f;
+    }
+    // exp through the hardware base-2 exponential (v_exp_f32); for |x| of order one
+    static __device__ __forceinline__ float exp_fast(float x) {
+        return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
+    }
     static __device__ __forceinline__ float atan(float x) { return atanf(x); }
     static __device__ __forceinline__ float sin(float x) { return sinf(x); }
     static __device__ __forceinline__ float cos(float x) { return cosf(x); }
@@ -55,6 +63,8 @@ template <> struct Fp<double> {
     static __device__ __forceinline__ double log(double x) { return ::log(x); }
     static __device__ __forceinline__ double log1p(double x) { return ::log1p(x); }
     static __device__ __forceinline__ double log10(double x) { return ::log10(x); }
+    static __device__ __forceinline__ double log10_fast(double x) { return ::log10(x); }
+    static __device__ __forceinline__ double exp_fast(double x) { return ::exp(x); }
     static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
     static __device__ __forceinline__ double sin(double x) { return ::sin(x); }
     static __device__ __forceinline__ double cos(double x) { return ::cos(x); }

@@ -144,13 +144,19 @@ template <> struct GlRule<float> {
 // (eqs. 2.3-2.5): power 0 -> int x/E du (D_C), 1 -> int 1/E du (T), 2 -> int x^3/E du
 // (X).  With grad, also the Leibniz derivatives -1/2 int f dP/dtheta / E^3 du for
 // theta = (Om, OL, Or).  E^2 = beta (1 - sigma x) Q(x) in factored form.
+// The number of equal panels is max(4, U / dpath) (capped at 64): every panel is then
+// no wider than the distance of the nearest singularity of the integrand, which keeps
+// the Bernstein-ellipse parameter of each panel above 3.7 (error below 1e-20 with 20
+// nodes, 1e-9 with 8).
 template <typename Q, bool PAIR>
 __device__ void gl_integral(const LaneConst<Q> &k, Q z, int power, bool grad, Q &val, Q gth[3]) {
     const Q U = Fp<Q>::log1p(z);
-    const Q h = U * Q(1.0 / kGlNp);
+    const Q want = U * Fp<Q>::rcp(k.dpath);
+    const int np = want > Q(64) ? 64 : (want > Q(kGlNp) ? (int)__builtin_ceil((double)want) : kGlNp);
+    const Q h = U * Fp<Q>::rcp(Q(np));
     const Q beta = Fp<Q>::rcp(k.pre * k.pre);
     Q s = Q(0), g0 = Q(0), g1 = Q(0), g2 = Q(0);
-    for (int p = 0; p < kGlNp; ++p) {
+    for (int p = 0; p < np; ++p) {
         const Q mid = h * (Q(p) + Q(0.5));
         for (int i = 0; i < GlRule<Q>::n; ++i) {
             Q u = mid + Q(0.5) * h * GlRule<Q>::x(i);
@@ -234,12 +240,15 @@ template <typename T, bool PAIR> __device__ T x_hat(const LaneConst<T> &k, T z, 
 }
 
 // Curvature transform: S = sinn(chi) (sec. 2.1.1; sinh for Ok > 0, sin for Ok < 0),
-// C = dS/dchi, dS = dS/dOk.  Series in t = Ok chi^2 near flatness.
+// C = dS/dchi, dS = dS/dOk.  The power series in t = Ok chi^2 (one entire function
+// for both signs of Ok) is used for |t| < 1, where its terms stay below one (no
+// cancellation in S or C) and N terms reach the type's precision; the closed forms
+// beyond.
 template <typename T>
 __device__ __forceinline__ void sinn(T chi, T ok, T sk, T &S, T &C, T &dS) {
     const T t = ok * chi * chi;
-    if (Fp<T>::abs(t) < T(0.1)) {
-        constexpr int N = sizeof(T) == 4 ? 5 : 8;
+    if (Fp<T>::abs(t) < T(1)) {
+        constexpr int N = sizeof(T) == 4 ? 6 : 10;
         T s = T(0), c = T(0), d = T(0);
         // Horner in t from the top: S/chi = sum t^n/(2n+1)!, C = sum t^n/(2n)!,
         // dS/(chi^3) = sum_{n>=1} n t^(n-1)/(2n+1)!
@@ -262,7 +271,7 @@ __device__ __forceinline__ void sinn(T chi, T ok, T sk, T &S, T &C, T &dS) {
         return;
     }
     if (ok > T(0)) {
-        T e = Fp<T>::exp(sk * chi), ie = Fp<T>::rcp(e);
+        T e = Fp<T>::exp_fast(sk * chi), ie = Fp<T>::rcp(e);
         S = T(0.5) * (e - ie) * Fp<T>::rcp(sk);
         C = T(0.5) * (e + ie);
     } else {
@@ -306,7 +315,7 @@ __device__ __forceinline__ T observable(int kind, const LaneConst<T> &k, T chi, 
     const T k5 = T(2.1714724095162591); // 5 / ln 10
     T iS = Fp<T>::rcp(S);
     d_chi = k5 * C * iS; d_ok = k5 * dS * iS; d_z = k5 * Fp<T>::rcp(x); d_h = -k5 * H0inv;
-    return T(5) * Fp<T>::log10(DL) + T(25);
+    return T(5) * Fp<T>::log10_fast(DL) + T(25);
 }
 
 // E(z) from eq. 2.2 (for the fundamental-theorem z-derivatives)

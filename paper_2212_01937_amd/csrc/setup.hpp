@@ -61,6 +61,7 @@ template <typename T> struct LaneConst {
     T d0102;                // X: (r1 - r0)(r2 - r0)
     T om1s12, op1s3, om1s0; // X: (1-s r1)(1-s r2), 1 + s S3, 1 - s r0
     T d02re, d02im;         // X: r2 - r0
+    T dpath;                // distance of the nearest singularity ln(rho_n) to the path u >= 0
 };
 
 struct CosmoRec {
@@ -184,6 +185,7 @@ template <typename T> __device__ void fill_lane(LaneConst<T> &L, const LaneConst
     L.xc3 = T(D.xc3); L.xc2 = T(D.xc2); L.xs3 = T(D.xs3); L.d0102 = T(D.d0102);
     L.om1s12 = T(D.om1s12); L.op1s3 = T(D.op1s3); L.om1s0 = T(D.om1s0);
     L.d02re = T(D.d02re); L.d02im = T(D.d02im);
+    L.dpath = T(D.dpath);
 }
 
 // dP/dtheta at x for theta = Om, OL, Or (Ok eliminated)
@@ -357,6 +359,25 @@ __device__ void setup_cosmo(const double *prm, CosmoRec &rec) {
     D.op1s3 = 1.0 + sigma * D.xs3;
     D.om1s0 = 1.0 - sigma * s0;
     D.d02re = d02.re; D.d02im = d02.im;
+    // Quadrature routes integrate in u = ln x along the half-line u >= 0; the
+    // integrand is singular at u = ln(rho_n) (complex log).  Distance of the nearest
+    // singularity to that half-line sizes the quadrature panels.
+    {
+        double dmin = 1e300;
+        for (int n = 0; n < 3; ++n) {
+            double mag = cabs(rho[n]);
+            if (!(mag > 0.0)) continue;
+            double lr = ::log(mag), li = ::atan2(rho[n].im, rho[n].re);
+            double d = lr >= 0.0 ? __builtin_fabs(li) : __builtin_sqrt(lr * lr + li * li);
+            dmin = d < dmin ? d : dmin;
+        }
+        if (Or > 0.0) { // radiation root rho_l = 1/sigma < 0: ln rho_l = ln|rho_l| + i pi
+            double lr = -::log(-sigma);
+            double d = lr >= 0.0 ? M_PI : __builtin_sqrt(lr * lr + M_PI * M_PI);
+            dmin = d < dmin ? d : dmin;
+        }
+        D.dpath = dmin;
+    }
 
     // --- root Jacobian (app. A), FP64
     const double Rp = (4.0 * OL * sigma * sigma + 2.0 * Ok) * sigma + Om; // R'(sigma)

@@ -27,11 +27,19 @@ def ref_vjp(kind, params, z, w, shared):
     sp = np.einsum("cz,czk->ck", np.abs(w), np.abs(g[..., :4]))
     gzf = w * g[..., 4]
     agz = np.abs(gzf)
-    if kind == "DA":
-        # dD_A/dz = -D_A/(1+z) + (dD_M/dz)/(1+z) vanishes at the turnover of D_A:
-        # measure against the size of its two terms
-        zz = z if not shared else np.broadcast_to(z, out.shape)
-        agz = agz + np.abs(w * out / (1 + zz))
+    if kind in ("DM", "DL", "DA", "MU"):
+        # d out/dz carries the factor C = cos(sqrt|Ok| chi) (closed universes), which
+        # vanishes at the antipode, and for D_A a second term -D_A/(1+z) that cancels the
+        # first at the turnover: measure against the size of the terms, |C| -> 1 + |x|
+        zz = np.ascontiguousarray(np.broadcast_to(z, out.shape) if shared else z)
+        dc, gdc = oracle.distance("DC", params, zz, shared_z=False, grad=True)
+        dh = 299792.458 / params[:, :1]
+        ok = (1 - params[:, 1] - params[:, 2] - params[:, 3])[:, None]
+        x = np.sqrt(np.abs(ok)) * dc / dh
+        base = np.abs(gdc[..., 4]) * (1 + np.abs(x))
+        dm = oracle.distance("DM", params, zz, shared_z=False)
+        factor = {"DM": 1.0, "DL": 1 + zz, "DA": 1 / (1 + zz), "MU": 2.1714724095162591 / np.abs(dm)}[kind]
+        agz = agz + np.abs(w) * (base * factor + np.abs(out) / (1 + zz))
     if shared:
         return gp, sp, gzf.sum(0), agz.sum(0)
     return gp, sp, gzf, agz
