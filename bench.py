@@ -2,10 +2,14 @@
 
 Workload (one step): 256 cosmologies x 1e6 shared redshifts (Om0~U(0.1,0.5),
 OL0~U(0.4,1.0), Or0 = 9e-5, H0~U(65,75); z~U(0.01,2.3)), i.e. 2.56e8 evaluations
-of the distance modulus mu and of its gradient: the forward cosmo_distance(MU)
-followed by cosmo_distance_vjp(MU) with a fixed random cotangent w (the adjoint
-of (w * mu).sum()), returning d/d(H0, Om0, OL0, Or0) per cosmology and d/dz per
-redshift.  Inputs are resident in device memory before the timed region.
+of the distance modulus mu and of its gradient: one cosmo_distance_vjp(MU) call
+with a fixed random cotangent w that also writes mu (the value and the adjoint of
+(w * mu).sum() from one pass), returning mu [256, 1e6], d/d(H0, Om0, OL0, Or0)
+per cosmology and d/dz per redshift.  Roots are found inside every step.  Inputs
+are resident in device memory before the timed region.
+
+Also timed, reported under "paths": the forward alone (cosmo_distance) and the
+two-call forward + adjoint sequence, for the FP32 and the FP64 path.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -22,11 +26,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "distance evals/s fwd+grad, FP32 vs FP64 path, at max rel err vs FP64 oracle"
-# Algorithmic floating-point operations per evaluation of the timed kernels (counted
-# from the per-lane algorithm at its typical duplication counts; see the design notes).
-FLOPS_PER_EVAL = {"vjp": {"f32": 560.0, "f64": 760.0}, "fwd": {"f32": 210.0, "f64": 300.0}}
 PEAK = {"f32": 157.3e12, "f64": 78.6e12}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_vjp_mu_config5.json")
+# Per-evaluation VALU operation counts and HBM bytes of the kernels, from rocprofv3
+# counters on this workload (written with the hash of the kernel sources they
+# were taken on).
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_config5.json")
 
 
 def kernel_source_hash():
@@ -38,15 +42,14 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def load_traffic():
+def load_counters():
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(COUNTERS_FILE) as fh:
             t = json.load(fh)
-        if t.get("src_sha256") == kernel_source_hash():
-            return t
+        t["current"] = t.get("src_sha256") == kernel_source_hash()
+        return t
     except (OSError, ValueError):
-        pass
-    return None
+        return None
 
 
 def cpu_baseline(params, z, budget_s=12.0):
@@ -55,7 +58,6 @@ def cpu_baseline(params, z, budget_s=12.0):
     import oracle
     from paper_2212_01937_amd import workloads
     n = 64
-    rate = None
     while True:
         ci, zi = workloads.subsample(params.shape[0], z.shape[0], n, seed=4242 + n)
         zz = z[zi]
@@ -68,10 +70,24 @@ def cpu_baseline(params, z, budget_s=12.0):
         if dt > budget_s / 4 or n >= 2 ** 20:
             break
         n = int(min(n * max(2.0, (budget_s / 2) / max(dt, 1e-3)), 2 ** 20))
-    threads = oracle.threads()
-    return {"value": rate, "unit": "evals/s", "cores": threads, "kind": "oracle",
+    return {"value": rate, "unit": "evals/s", "cores": oracle.threads(), "kind": "oracle",
             "sample": f"{n} random (cosmology, z) pairs of the same workload, mu + d/d(H0,Om0,OL0,Or0,z), "
                       f"adaptive G7K15 at epsrel 1e-14, OpenMP over evaluations"}
+
+
+def timed(fn, steps, stream, torch):
+    """Event-timed repetitions of fn on `stream`; returns (per-call ms list, wall ms per call)."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for a, b in ev:
+        a.record(stream)
+        out = fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    return [a.elapsed_time(b) for a, b in ev], wall, out
 
 
 def main():
@@ -101,49 +117,52 @@ def main():
     p = torch.tensor(params, device=dev)
     ws = torch.empty(cosmo.workspace_size(n_c, n_z), dtype=torch.uint8, device=dev)
     gen = torch.Generator(device=dev)
-    results = {}
+    stream = torch.cuda.current_stream(dev)
+    results, grads = {}, {}
     for path in args.paths.split(","):
         dt = torch.float32 if path == "f32" else torch.float64
         gen.manual_seed(workloads.cotangent_seed())
         zt = torch.tensor(z, dtype=dt, device=dev)
         w = torch.randn((n_c, n_z), dtype=dt, device=dev, generator=gen)
 
-        def step():
-            mu = cosmo.cosmo_distance("MU", p, zt, workspace=ws)
-            gp, gz = cosmo.cosmo_distance_vjp("MU", p, zt, w, workspace=ws)
-            return mu, gp, gz
+        def step():  # mu and the gradient of (w * mu).sum(), one pass
+            return cosmo.cosmo_distance_vjp("MU", p, zt, w, want_value=True, workspace=ws)
+
+        def fwd():
+            return cosmo.cosmo_distance("MU", p, zt, workspace=ws)
+
+        def vjp():
+            return cosmo.cosmo_distance_vjp("MU", p, zt, w, workspace=ws)
 
         for _ in range(args.warmup):
             step()
+            fwd()
+            vjp()
         torch.cuda.synchronize()
-        stream = torch.cuda.current_stream(dev)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-               torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for e0, e1, e2 in ev:
-            e0.record(stream)
-            mu = cosmo.cosmo_distance("MU", p, zt, workspace=ws)
-            e1.record(stream)
-            gp, gz = cosmo.cosmo_distance_vjp("MU", p, zt, w, workspace=ws)
-            e2.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        fwd_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
-        vjp_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
-        ms = wall * 1e3 / args.steps
-        # sampled error vs the FP64 oracle at this size
+        step_ev, step_wall, (mu, gp, gz) = timed(step, args.steps, stream, torch)
+        fwd_ev, _, _ = timed(fwd, args.steps, stream, torch)
+        vjp_ev, _, _ = timed(vjp, args.steps, stream, torch)
+        # sampled error of mu vs the FP64 oracle at this size
         import oracle
         ci, zi = workloads.subsample(n_c, n_z, 200, seed=99)
         zr = zt.double().cpu().numpy()
         mu_s = mu[torch.tensor(ci, device=dev), torch.tensor(zi, device=dev)].double().cpu().numpy()
         ref = np.array([oracle.distance("MU", params[c:c + 1], np.array([zr[i]]))[0, 0] for c, i in zip(ci, zi)])
         dl_rel = np.max(np.abs(10 ** ((mu_s - ref) / 5) - 1))
-        results[path] = {"ms_per_step": ms, "evals_per_s": evals / (ms * 1e-3), "fwd_ms": fwd_ms,
-                         "vjp_ms": vjp_ms, "max_abs_err_mu_mag": float(np.max(np.abs(mu_s - ref))),
+        grads[path] = (gp.cpu().numpy(), gz.double().cpu().numpy())
+        med = float(np.median(step_ev))
+        results[path] = {"ms_per_step": step_wall, "evals_per_s": evals / (step_wall * 1e-3),
+                         "step_event_ms_median": med, "step_event_ms_mean": float(np.mean(step_ev)),
+                         "fwd_ms": float(np.median(fwd_ev)), "fwd_evals_per_s": evals / (np.median(fwd_ev) * 1e-3),
+                         "two_call_fwd_plus_vjp_ms": float(np.median(fwd_ev) + np.median(vjp_ev)),
+                         "max_abs_err_mu_mag": float(np.max(np.abs(mu_s - ref))),
                          "max_rel_err_DL": float(dl_rel)}
         del mu, gp, gz, w, zt
         torch.cuda.empty_cache()
+    if "f32" in grads and "f64" in grads:
+        (g32, z32), (g64, z64) = grads["f32"], grads["f64"]
+        results["f32"]["grad_params_max_rel_diff_vs_f64"] = float(np.max(np.abs(g32 - g64) / np.abs(g64).max(0)))
+        results["f32"]["grad_z_max_rel_diff_vs_f64"] = float(np.max(np.abs(z32 - z64)) / np.max(np.abs(z64)))
 
     if args.copy_check:
         a = torch.empty(2 ** 28, dtype=torch.float32, device=dev)
@@ -153,20 +172,23 @@ def main():
 
     head = "f32" if "f32" in results else next(iter(results))
     r = results[head]
-    flops = FLOPS_PER_EVAL["vjp"][head] * evals
-    achieved = flops / (r["vjp_ms"] * 1e-3)
-    traffic = load_traffic()
-    roofline = {"bound": "alu", "kernel": f"k_vjp<{'float' if head == 'f32' else 'double'}, MU>",
-                "achieved": achieved / 1e12, "peak": PEAK[head] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK[head],
-                "traffic": traffic["traffic_bytes_per_launch"] if traffic else None,
-                "kernel_ms": r["vjp_ms"], "flops_per_eval": FLOPS_PER_EVAL["vjp"][head]}
+    cnt = load_counters()
+    kname = f"k_vjp<{'float' if head == 'f32' else 'double'},MU,8>"
+    roofline = {"bound": "alu", "kernel": kname, "unit": "TFLOP/s", "peak": PEAK[head] / 1e12,
+                "achieved": None, "frac": None, "traffic": None, "kernel_ms": r["step_event_ms_median"]}
+    if cnt and kname in cnt.get("kernels", {}):
+        k = cnt["kernels"][kname]
+        achieved = k["flop_per_eval"] * evals / (r["step_event_ms_median"] * 1e-3)
+        roofline.update({"achieved": achieved / 1e12, "frac": achieved / PEAK[head],
+                         "flop_per_eval": k["flop_per_eval"], "valu_instr_per_eval": k["valu_per_eval"],
+                         "traffic": k["hbm_bytes_per_launch"] if cnt["current"] else None,
+                         "counters_current": cnt["current"]})
     line = {"metric": METRIC, "value": r["evals_per_s"], "unit": "evals/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": head, "data": "synthetic",
-            "config": {"workload": f"mu fwd+grad, {n_c} cosmologies x {n_z} shared redshifts "
-                                   f"(Or0=9e-5, z~U(0.01,2.3)), VJP of (w*mu).sum()",
+            "config": {"workload": f"mu and its gradient, {n_c} cosmologies x {n_z} shared redshifts "
+                                   f"(Or0=9e-5, z~U(0.01,2.3)), VJP of (w*mu).sum(), roots in the step",
                        "n_cosmo": n_c, "n_z": n_z, "evals_per_step": evals},
             "paths": results,
             "speedup_f32_vs_f64": (results["f64"]["ms_per_step"] / results["f32"]["ms_per_step"]

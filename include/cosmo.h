@@ -115,14 +115,18 @@ int cosmo_distance(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_
  * ([n_cosmo][n_z], dtype).  Gradients through the Carlson derivatives (eqs.
  * 2.10-2.12) and the differentiated root finding (app. A, eqs. A.1-A.4); the
  * z-gradient by the fundamental theorem of calculus.
+ * out        : [n_cosmo][n_z] of dtype, nullable.  When given, the observable
+ *              itself is written as well (value and gradient from one pass over
+ *              the lanes; the values agree with cosmo_distance within the
+ *              precision of dt, and the X_QUADRATURE info bit is set as there).
  * grad_params: [n_cosmo][4] FP64 out, sum over z of cot * d out/d(H0, Om0, OL0,
  *              Or0); overwritten; nullable.
  * grad_z     : dtype out, nullable; [n_z] summed over cosmologies when
  *              z_cosmo_stride == 0, else [n_cosmo][n_z]; overwritten.           */
 int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params,
                        int64_t n_cosmo, const void *z, int64_t n_z, int64_t z_cosmo_stride,
-                       const void *cot, double *grad_params, void *grad_z, int32_t *info,
-                       void *workspace, size_t workspace_bytes, void *stream);
+                       const void *cot, void *out, double *grad_params, void *grad_z,
+                       int32_t *info, void *workspace, size_t workspace_bytes, void *stream);
 
 /* Library version string (static storage). */
 const char *cosmo_version(void);

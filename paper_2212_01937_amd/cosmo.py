@@ -53,7 +53,7 @@ def load():
     lib.carlson_rc.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp]
     lib.cosmo_distance.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, i32p, vp,
                                    ctypes.c_size_t, vp]
-    lib.cosmo_distance_vjp.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, vp,
+    lib.cosmo_distance_vjp.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, vp, vp,
                                        i32p, vp, ctypes.c_size_t, vp]
     for n in EXPORTS[:-1]:
         getattr(lib, n).restype = ctypes.c_int
@@ -184,8 +184,11 @@ def cosmo_distance(kind, params, z, info=False, workspace=None):
     return (out, inf) if info else out
 
 
-def cosmo_distance_vjp(kind, params, z, cot, want_params=True, want_z=True, info=False, workspace=None):
-    """Adjoint: (grad_params [n_cosmo, 4] float64 or None, grad_z like z or None)."""
+def cosmo_distance_vjp(kind, params, z, cot, want_params=True, want_z=True, info=False, workspace=None,
+                       want_value=False):
+    """Adjoint: (grad_params [n_cosmo, 4] float64 or None, grad_z like z or None).
+    With want_value=True the observable is computed in the same pass and returned
+    first: (value [n_cosmo, n_z], grad_params, grad_z)."""
     lib = load()
     p = _params(params)
     n_c = p.shape[0]
@@ -196,14 +199,16 @@ def cosmo_distance_vjp(kind, params, z, cot, want_params=True, want_z=True, info
     gz = None
     if want_z:
         gz = torch.empty(n_z if shared else (n_c, n_z), dtype=zc.dtype, device=p.device)
+    val = torch.empty((n_c, n_z), dtype=zc.dtype, device=p.device) if want_value else None
     inf = torch.empty(n_c, dtype=torch.int32, device=p.device) if info else None
     ws = workspace if workspace is not None else _workspace(n_c, n_z, p.device)
     with torch.cuda.device(p.device):
         rc = lib.cosmo_distance_vjp(KINDS[kind], DTYPES[zc.dtype], _ptr(p), n_c, _ptr(zc), n_z, stride,
-                                    _ptr(c), _ptr(gp), _ptr(gz), _ptr(inf), _ptr(ws), ws.numel(),
+                                    _ptr(c), _ptr(val), _ptr(gp), _ptr(gz), _ptr(inf), _ptr(ws), ws.numel(),
                                     _stream(p.device))
     _check(rc, "cosmo_distance_vjp")
-    return (gp, gz, inf) if info else (gp, gz)
+    res = ((val,) if want_value else ()) + (gp, gz)
+    return res + (inf,) if info else res
 
 
 class _Distance(torch.autograd.Function):

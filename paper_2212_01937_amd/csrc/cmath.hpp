@@ -26,7 +26,8 @@ template <> struct Fp<float> {
     static __device__ __forceinline__ float log10_fast(float x) {
         return __builtin_amdgcn_logf(x) * 0.30102999566398120f;
     }
-    // exp through the hardware base-2 exponential (v_exp_f32); for |x| of order one
+    // exp through the hardware base-2 exponential (v_exp_f32, about 1 ulp) after the
+    // scaling by log2(e), whose rounding adds a relative error of about eps |x|
     static __device__ __forceinline__ float exp_fast(float x) {
         return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
     }

@@ -114,11 +114,16 @@ __device__ __attribute__((noinline)) void gl_chi_grad(const CosmoRec &r, double 
     gl_integral<double, PAIR>(r.d, z, 0, true, chi, g);
 }
 
+// One (cosmology, redshift) lane of the adjoint: accumulates the parameter
+// partials into acc, returns the z-gradient in gz and the observable in val
+// (the same quantity cosmo_distance evaluates; used_gl flags the quadrature
+// route of X).
 template <typename T, int KIND, bool PAIR>
-__device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kAcc], T &gz) {
+__device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kAcc], T &gz, T &val,
+                                         bool &used_gl) {
     const LaneConst<T> &k = lane_of<T>(r);
     const bool fp32 = sizeof(T) == 4;
-    const T H0inv = T(1.0 / r.H0);
+    const T H0inv = k.hinv;
     if (KIND == COSMO_T && !direct_mode(KIND, r, fp32)) {
         // time coordinate: Carlson derivatives (eqs. 2.10, 2.11) and the root chain
         TGrad<T, PAIR> tg;
@@ -130,7 +135,8 @@ __device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kA
         acc[3] += w * tg.dr1re;
         acc[4] += w * (PAIR ? tg.dr1im : tg.dr2);
         acc[6] += -w * tg.t * H0inv;
-        gz = w * Fp<T>::rcp((T(1) + z) * Ez<T>(k, z));
+        gz = w * Fp<T>::rcp(T(1) + z) * iEz<T>(k, z);
+        val = k.th * tg.t;
         return;
     }
     if (KIND == COSMO_T || KIND == COSMO_X) {
@@ -141,12 +147,12 @@ __device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kA
         const T e = Ez<T>(k, z);
         gz = cot * scale * (KIND == COSMO_T ? Fp<T>::rcp(x * e) : x * x * Fp<T>::rcp(e));
         // value for the H0 derivative: recompute with the Carlson forward
-        bool ugl;
-        T v = KIND == COSMO_T ? k.th * t_hat<T, PAIR>(k, z) : k.dh * x_hat<T, PAIR>(k, z, ugl);
+        T v = KIND == COSMO_T ? k.th * t_hat<T, PAIR>(k, z) : k.dh * x_hat<T, PAIR>(k, z, used_gl);
         acc[0] += cot * scale * g[0];
         acc[1] += cot * scale * g[1];
         acc[2] += cot * scale * g[2];
         acc[6] += -cot * v * H0inv;
+        val = v;
         return;
     }
     if (direct_mode(KIND, r, fp32)) {
@@ -154,20 +160,20 @@ __device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kA
         double chi, g[3];
         gl_chi_grad<PAIR>(r, (double)z, chi, g);
         T dchi, dok, dzz, dh;
-        observable<T>(KIND, k, T(chi), z, H0inv, dchi, dok, dzz, dh);
+        val = observable<T>(KIND, k, T(chi), z, H0inv, dchi, dok, dzz, dh);
         const double w = (double)cot * (double)dchi;
         acc[0] += T(w * g[0]);
         acc[1] += T(w * g[1]);
         acc[2] += T(w * g[2]);
         acc[5] += cot * dok;
         acc[6] += cot * dh;
-        gz = cot * (dzz + dchi * Fp<T>::rcp(Ez<T>(k, z)));
+        gz = cot * (dzz + dchi * iEz<T>(k, z));
         return;
     }
     ChiGrad<T, PAIR> cg;
     chi_grad<T, PAIR>(k, z, cg);
     T dchi, dok, dzz, dh;
-    observable<T>(KIND, k, cg.chi, z, H0inv, dchi, dok, dzz, dh);
+    val = observable<T>(KIND, k, cg.chi, z, H0inv, dchi, dok, dzz, dh);
     const T w = cot * dchi;
     acc[0] += w * cg.chi;
     acc[1] += w * cg.dsig;
@@ -176,7 +182,7 @@ __device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kA
     acc[4] += w * (PAIR ? cg.dr1im : cg.dr2);
     acc[5] += cot * dok;
     acc[6] += cot * dh;
-    gz = cot * (dzz + dchi * Fp<T>::rcp(Ez<T>(k, z)));
+    gz = cot * (dzz + dchi * iEz<T>(k, z));
 }
 
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
@@ -195,14 +201,23 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 template <typename T, int KIND, bool PAIR, int ZPT>
 __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T *__restrict__ z, int64_t n_z,
                                           int64_t zstride, const T *__restrict__ cot, int64_t base,
-                                          T acc[kAcc], T *gzl, T *__restrict__ gz_out) {
+                                          T acc[kAcc], T *gzl, T *__restrict__ gz_out, T *__restrict__ out,
+                                          int32_t *__restrict__ info) {
 #pragma unroll 1
     for (int k = 0; k < ZPT; ++k) {
         const int64_t i = base + (int64_t)k * kBlock;
         if (i >= n_z) break;
         const T zz = z[c * zstride + i];
-        T gz;
-        vjp_lane<T, KIND, PAIR>(r, zz, cot[c * n_z + i], acc, gz);
+        T gz, val;
+        bool used_gl = false;
+        vjp_lane<T, KIND, PAIR>(r, zz, cot[c * n_z + i], acc, gz, val, used_gl);
+        if (out) {
+            out[c * n_z + i] = val;
+            if (KIND == COSMO_X && info) {
+                unsigned long long m = __ballot(used_gl);
+                if (m && (int)__lane_id() == __ffsll((long long)m) - 1) atomicOr(info + c, COSMO_INFO_X_QUADRATURE);
+            }
+        }
         if (zstride != 0) {
             if (gz_out) gz_out[c * n_z + i] = gz;
         } else {
@@ -216,6 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp(const CosmoRec *__restrict__ rec
                                                  const T *__restrict__ z, int64_t n_z, int64_t zstride,
                                                  const T *__restrict__ cot, double *__restrict__ pacc,
                                                  T *__restrict__ gz_out, double *__restrict__ gz_part,
+                                                 T *__restrict__ out, int32_t *__restrict__ info,
                                                  int ct, int64_t nzb) {
     __shared__ T gzl[ZPT * kBlock];
     const int64_t b = blockIdx.x;
@@ -233,12 +249,13 @@ __global__ __launch_bounds__(kBlock) void k_vjp(const CosmoRec *__restrict__ rec
 #pragma unroll
         for (int s = 0; s < kAcc; ++s) acc[s] = T(0);
         if (r.valid) {
-            if (r.pair) vjp_cosmo<T, KIND, true, ZPT>(r, c, z, n_z, zstride, cot, base, acc, gzl, gz_out);
-            else vjp_cosmo<T, KIND, false, ZPT>(r, c, z, n_z, zstride, cot, base, acc, gzl, gz_out);
+            if (r.pair) vjp_cosmo<T, KIND, true, ZPT>(r, c, z, n_z, zstride, cot, base, acc, gzl, gz_out, out, info);
+            else vjp_cosmo<T, KIND, false, ZPT>(r, c, z, n_z, zstride, cot, base, acc, gzl, gz_out, out, info);
         } else {
             for (int k = 0; k < ZPT; ++k) {
                 const int64_t i = base + (int64_t)k * kBlock;
                 if (i >= n_z) break;
+                if (out) out[c * n_z + i] = Fp<T>::nan();
                 if (zstride != 0) {
                     if (gz_out) gz_out[c * n_z + i] = Fp<T>::nan();
                 } else {
@@ -482,7 +499,8 @@ int launch_forward(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, 
 
 template <typename T>
 int launch_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int64_t n_z, int64_t zstride,
-               const T *cot, double *grad_params, T *grad_z, const WsLayout &L, char *ws, hipStream_t s) {
+               const T *cot, T *out, double *grad_params, T *grad_z, int32_t *info, const WsLayout &L, char *ws,
+               hipStream_t s) {
     const int zpt = vjp_zpt(n_z);
     Tiling t = tiling(n_cosmo, n_z, zpt);
     double *pacc = grad_params ? (double *)(ws + L.pacc) : nullptr;
@@ -491,10 +509,10 @@ int launch_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int6
 #define COSMO_VJP(K)                                                                                            \
     if (zpt == 8)                                                                                               \
         hipLaunchKernelGGL((k_vjp<T, K, 8>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, cot, pacc,     \
-                           grad_z, gzp, t.ct, t.nzb);                                                           \
+                           grad_z, gzp, out, info, t.ct, t.nzb);                                                \
     else                                                                                                        \
         hipLaunchKernelGGL((k_vjp<T, K, 1>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, cot, pacc,     \
-                           grad_z, gzp, t.ct, t.nzb)
+                           grad_z, gzp, out, info, t.ct, t.nzb)
     switch (kind) {
     case COSMO_DC: COSMO_VJP(COSMO_DC); break;
     case COSMO_DM: COSMO_VJP(COSMO_DM); break;
@@ -615,8 +633,8 @@ int cosmo_distance(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_
 }
 
 int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo, const void *z,
-                       int64_t n_z, int64_t z_cosmo_stride, const void *cot, double *grad_params, void *grad_z,
-                       int32_t *info, void *workspace, size_t workspace_bytes, void *stream) {
+                       int64_t n_z, int64_t z_cosmo_stride, const void *cot, void *out, double *grad_params,
+                       void *grad_z, int32_t *info, void *workspace, size_t workspace_bytes, void *stream) {
     if (!valid_kind(kind)) return COSMO_E_KIND;
     if (!valid_dtype(dt)) return COSMO_E_DTYPE;
     if (n_cosmo < 0 || n_z < 0 || z_cosmo_stride < 0) return COSMO_E_ARG;
@@ -646,9 +664,9 @@ int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params, in
     if (rc != COSMO_OK) return rc;
     if (dt == COSMO_F32)
         return launch_vjp<float>(kind, recs, n_cosmo, (const float *)z, n_z, z_cosmo_stride, (const float *)cot,
-                                 grad_params, (float *)grad_z, L, (char *)ws.ptr, s);
+                                 (float *)out, grad_params, (float *)grad_z, info, L, (char *)ws.ptr, s);
     return launch_vjp<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, (const double *)cot,
-                              grad_params, (double *)grad_z, L, (char *)ws.ptr, s);
+                              (double *)out, grad_params, (double *)grad_z, info, L, (char *)ws.ptr, s);
 }
 
 } // extern "C"

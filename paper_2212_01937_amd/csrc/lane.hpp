@@ -131,13 +131,11 @@ template <> struct GlRule<double> {
     static constexpr int n = kGlN64;
     static __device__ __forceinline__ double x(int i) { return c_gl64_x[i]; }
     static __device__ __forceinline__ double w(int i) { return c_gl64_w[i]; }
-    static __device__ __forceinline__ double expm1(double u) { return ::expm1(u); }
 };
 template <> struct GlRule<float> {
     static constexpr int n = kGlN32;
     static __device__ __forceinline__ float x(int i) { return c_gl32_x[i]; }
     static __device__ __forceinline__ float w(int i) { return c_gl32_w[i]; }
-    static __device__ __forceinline__ float expm1(float u) { return expm1f(u); }
 };
 
 // Composite Gauss-Legendre quadrature in u = ln(1+z) of the defining integrals
@@ -148,33 +146,36 @@ template <> struct GlRule<float> {
 // no wider than the distance of the nearest singularity of the integrand, which keeps
 // the Bernstein-ellipse parameter of each panel above 3.7 (error below 1e-20 with 20
 // nodes, 1e-9 with 8).
+// Nodes are placed from the upper limit down, x = (1+z) exp(-(U - u)): the integrands
+// grow with x, and measuring from the top keeps the rounding of the node abscissae
+// (absolute, ~eps times the distance from the anchor) smallest where the weight is.
 template <typename Q, bool PAIR>
 __device__ void gl_integral(const LaneConst<Q> &k, Q z, int power, bool grad, Q &val, Q gth[3]) {
     const Q U = Fp<Q>::log1p(z);
     const Q want = U * Fp<Q>::rcp(k.dpath);
     const int np = want > Q(64) ? 64 : (want > Q(kGlNp) ? (int)__builtin_ceil((double)want) : kGlNp);
     const Q h = U * Fp<Q>::rcp(Q(np));
-    const Q beta = Fp<Q>::rcp(k.pre * k.pre);
+    const Q x2 = Q(1) + z;
     Q s = Q(0), g0 = Q(0), g1 = Q(0), g2 = Q(0);
     for (int p = 0; p < np; ++p) {
-        const Q mid = h * (Q(p) + Q(0.5));
+        const Q vmid = h * (Q(np - p) - Q(0.5)); // U - (panel midpoint)
         for (int i = 0; i < GlRule<Q>::n; ++i) {
-            Q u = mid + Q(0.5) * h * GlRule<Q>::x(i);
-            Q xm1 = GlRule<Q>::expm1(u);
-            Q x = Q(1) + xm1;
+            const Q v = vmid - Q(0.5) * h * GlRule<Q>::x(i);
+            const Q x = x2 * Fp<Q>::exp_fast(-v);
+            const Q xm1 = x - Q(1);
             Q q = PAIR ? (xm1 + k.w0) * ((xm1 + k.w1re) * (xm1 + k.w1re) + k.w1im * k.w1im)
                        : (xm1 + k.w0) * (xm1 + k.w1re) * (xm1 + k.w2);
-            Q e2 = beta * (k.yt2 - k.sigma * xm1) * q;
+            Q e2 = k.beta * (k.yt2 - k.sigma * xm1) * q;
             Q ie = Fp<Q>::rsqrt(e2);
             Q fx = power == 0 ? x : (power == 1 ? Q(1) : x * x * x);
             Q wf = GlRule<Q>::w(i) * fx * ie;
             s += wf;
             if (grad) {
                 Q c = Q(-0.5) * wf * ie * ie;
-                Q x2 = x * x;
-                g0 += c * x2 * xm1;                      // x^3 - x^2
+                Q xx = x * x;
+                g0 += c * xx * xm1;                      // x^3 - x^2
                 g1 += c * (-xm1 * (Q(2) + xm1));        // 1 - x^2
-                g2 += c * x2 * xm1 * (Q(2) + xm1);      // x^4 - x^2
+                g2 += c * xx * xm1 * (Q(2) + xm1);      // x^4 - x^2
             }
         }
     }
@@ -318,12 +319,14 @@ __device__ __forceinline__ T observable(int kind, const LaneConst<T> &k, T chi, 
     return T(5) * Fp<T>::log10_fast(DL) + T(25);
 }
 
-// E(z) from eq. 2.2 (for the fundamental-theorem z-derivatives)
-template <typename T> __device__ __forceinline__ T Ez(const LaneConst<T> &k, T z) {
+// E(z) from eq. 2.2 (for the fundamental-theorem z-derivatives) and its inverse
+template <typename T> __device__ __forceinline__ T E2z(const LaneConst<T> &k, T z) {
     const T x = T(1) + z;
     const T x2 = x * x;
-    return Fp<T>::sqrt((k.Or * x2 + k.Om * x + k.ok) * x2 + k.OL);
+    return (k.Or * x2 + k.Om * x + k.ok) * x2 + k.OL;
 }
+template <typename T> __device__ __forceinline__ T Ez(const LaneConst<T> &k, T z) { return Fp<T>::sqrt(E2z(k, z)); }
+template <typename T> __device__ __forceinline__ T iEz(const LaneConst<T> &k, T z) { return Fp<T>::rsqrt(E2z(k, z)); }
 
 // ---------------------------------------------------------------- adjoint
 // Gradient of chi/D_H with respect to the per-cosmology root parameters
@@ -350,10 +353,10 @@ __device__ __forceinline__ void chi_grad(const LaneConst<T> &k, T z, ChiGrad<T, 
         cx<T> G1 = mkc(g.U1re, g.U1im) * rdy * T(-1.0 / 3.0);
         cx<T> a1 = G1 * mkc(g.T1_1re, g.T1_1im), b1 = G1 * mkc(g.T2_1re, g.T2_1im);
         const T A = a0 + T(2) * a1.re, B = b0 + T(2) * b1.re;
-        o.dsig = scale * T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * Fp<T>::rcp(k.yt2));
-        o.dr0 = scale * T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * Fp<T>::rcp(k.w0));
+        o.dsig = scale * T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * k.iyt2);
+        o.dr0 = scale * T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * k.iw0);
         cx<T> iX1sq = crcp(mkc(z + k.w1re, k.w1im));
-        cx<T> iW1 = crcp(mkc(k.w1re, k.w1im));
+        const cx<T> iW1 = mkc(k.iw1re, k.iw1im);
         // (a1 + B - b1)/X1^2 + (b1 + A - a1)/W1
         cx<T> d1 = (a1 + B - b1) * iX1sq + (b1 + A - a1) * iW1;
         o.dr1re = scale * T(-0.5) * d1.re;
@@ -363,10 +366,10 @@ __device__ __forceinline__ void chi_grad(const LaneConst<T> &k, T z, ChiGrad<T, 
         const T G1 = -g.U1re * rdy.re * T(1.0 / 3.0), G2 = -g.U2 * rdz * T(1.0 / 3.0);
         const T a1 = G1 * g.T1_1re, b1 = G1 * g.T2_1re, a2 = G2 * g.T1_2, b2 = G2 * g.T2_2;
         const T A = a0 + a1 + a2, B = b0 + b1 + b2;
-        o.dsig = scale * T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * Fp<T>::rcp(k.yt2));
-        o.dr0 = scale * T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * Fp<T>::rcp(k.w0));
-        o.dr1re = scale * T(-0.5) * ((a1 + B - b1) * Fp<T>::rcp(z + k.w1re) + (b1 + A - a1) * Fp<T>::rcp(k.w1re));
-        o.dr2 = scale * T(-0.5) * ((a2 + B - b2) * Fp<T>::rcp(z + k.w2) + (b2 + A - a2) * Fp<T>::rcp(k.w2));
+        o.dsig = scale * T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * k.iyt2);
+        o.dr0 = scale * T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * k.iw0);
+        o.dr1re = scale * T(-0.5) * ((a1 + B - b1) * Fp<T>::rcp(z + k.w1re) + (b1 + A - a1) * k.iw1re);
+        o.dr2 = scale * T(-0.5) * ((a2 + B - b2) * Fp<T>::rcp(z + k.w2) + (b2 + A - a2) * k.iw2);
         o.dr1im = T(0);
     }
 }
@@ -385,19 +388,19 @@ __device__ __forceinline__ void u_chain(const LaneConst<T> &k, const Geo<T, PAIR
         cx<T> G1 = dV1 * mkc(g.U1re, g.U1im) * T(2);
         cx<T> a1 = G1 * mkc(g.T1_1re, g.T1_1im), b1 = G1 * mkc(g.T2_1re, g.T2_1im);
         const T A = a0 + T(2) * a1.re, B = b0 + T(2) * b1.re;
-        dsig += T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * Fp<T>::rcp(k.yt2));
-        dr0 += T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * Fp<T>::rcp(k.w0));
+        dsig += T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * k.iyt2);
+        dr0 += T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * k.iw0);
         cx<T> iX1sq = crcp(mkc(z + k.w1re, k.w1im));
-        cx<T> iW1 = crcp(mkc(k.w1re, k.w1im));
+        const cx<T> iW1 = mkc(k.iw1re, k.iw1im);
         dr1 = dr1 + ((a1 + B - b1) * iX1sq + (b1 + A - a1) * iW1) * T(-0.5);
     } else {
         const T G1 = dV1.re * T(2) * g.U1re, G2 = dV2 * T(2) * g.U2;
         const T a1 = G1 * g.T1_1re, b1 = G1 * g.T2_1re, a2 = G2 * g.T1_2, b2 = G2 * g.T2_2;
         const T A = a0 + a1 + a2, B = b0 + b1 + b2;
-        dsig += T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * Fp<T>::rcp(k.yt2));
-        dr0 += T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * Fp<T>::rcp(k.w0));
-        dr1.re += T(-0.5) * ((a1 + B - b1) * Fp<T>::rcp(z + k.w1re) + (b1 + A - a1) * Fp<T>::rcp(k.w1re));
-        dr2 += T(-0.5) * ((a2 + B - b2) * Fp<T>::rcp(z + k.w2) + (b2 + A - a2) * Fp<T>::rcp(k.w2));
+        dsig += T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * k.iyt2);
+        dr0 += T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * k.iw0);
+        dr1.re += T(-0.5) * ((a1 + B - b1) * Fp<T>::rcp(z + k.w1re) + (b1 + A - a1) * k.iw1re);
+        dr2 += T(-0.5) * ((a2 + B - b2) * Fp<T>::rcp(z + k.w2) + (b2 + A - a2) * k.iw2);
     }
 }
 
@@ -461,7 +464,7 @@ __device__ void t_grad(const LaneConst<T> &k, T z, TGrad<T, PAIR> &o) {
     const T r1o2_r2o1 = (r1 * om2).re + (r2 * om1).re;
     const T dP3_ds = -(k.r0 * om12 + om0 * r1o2_r2o1);
     const T dC5_ds = -k.r0 * r1o2_r2o1;
-    const T dQ_ds = Qv * (Fp<T>::rcp(k.yt2) + x2 * Fp<T>::rcp(g.Xt2));
+    const T dQ_ds = Qv * (k.iyt2 + x2 * Fp<T>::rcp(g.Xt2));
     T dsig = (z2 * T(1.0 / 3.0)) * rj * dP3_ds + dB_dW * z2 * dC5_ds + dRC_sum * dQ_ds + rf;
     // rho_0
     T dr0 = (z2 * T(1.0 / 3.0)) * rj * (-s * om12) + dB_dW * z2 * om12 + dRC_S * (-z2 * (r1 * r2).re);

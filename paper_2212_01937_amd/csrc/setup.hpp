@@ -62,6 +62,9 @@ template <typename T> struct LaneConst {
     T om1s12, op1s3, om1s0; // X: (1-s r1)(1-s r2), 1 + s S3, 1 - s r0
     T d02re, d02im;         // X: r2 - r0
     T dpath;                // distance of the nearest singularity ln(rho_n) to the path u >= 0
+    T iyt2, iw0, iw1re, iw1im, iw2; // 1/Yt^2, 1/w_0, 1/w_1 (complex for a pair), 1/w_2
+    T hinv;                 // 1/H0 [s Mpc/km]
+    T beta;                 // E^2 = beta (1 - sigma x) Q(x)
 };
 
 struct CosmoRec {
@@ -105,12 +108,14 @@ __device__ double sigma_root(double Om, double OL, double Or, double Ok, int &it
         double r = R(s);
         if (r == 0.0) break;
         if (r > 0.0) hi = s; else lo = s;
-        double d = dR(s);
-        double sn = s - r / d;
+        const double dn = r / dR(s);
+        // converged: the Newton correction is below the resolution of s (tested before
+        // the bracket safeguard, which a step that rounds to s itself would trip)
+        if (__builtin_fabs(dn) <= 4e-16 * __builtin_fabs(s)) { s -= dn; break; }
+        double sn = s - dn;
         if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
-        double step = sn - s;
         s = sn;
-        if (__builtin_fabs(step) <= 4e-16 * __builtin_fabs(s) || hi - lo <= 4e-16 * __builtin_fabs(s)) break;
+        if (hi - lo <= 4e-16 * __builtin_fabs(s)) break;
     }
     return s;
 }
@@ -128,13 +133,15 @@ __device__ double cubic_real_root(double q2, double q1, double q0, bool from_lef
         double f = cubic_at(q2, q1, q0, x);
         if (f == 0.0) return x;
         if (f < 0.0) lo = x; else hi = x;
-        double d = (3.0 * x + 2.0 * q2) * x + q1;
-        double xn = x - f / d;
+        const double dn = f / ((3.0 * x + 2.0 * q2) * x + q1);
+        // converged (checked before the safeguard: a correction that rounds to x itself
+        // fails the open-bracket test and would send the iterate to the bracket midpoint,
+        // possibly towards another root)
+        if (__builtin_fabs(dn) <= 2e-16 * tmax(1.0, __builtin_fabs(x))) return x - dn;
+        double xn = x - dn;
         if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-        double step = xn - x;
         x = xn;
-        if (__builtin_fabs(step) <= 2e-16 * tmax(1.0, __builtin_fabs(x)) || hi - lo <= 4e-16 * tmax(1.0, __builtin_fabs(x)))
-            break;
+        if (hi - lo <= 4e-16 * tmax(1.0, __builtin_fabs(x))) break;
     }
     return x;
 }
@@ -186,6 +193,9 @@ template <typename T> __device__ void fill_lane(LaneConst<T> &L, const LaneConst
     L.om1s12 = T(D.om1s12); L.op1s3 = T(D.op1s3); L.om1s0 = T(D.om1s0);
     L.d02re = T(D.d02re); L.d02im = T(D.d02im);
     L.dpath = T(D.dpath);
+    L.iyt2 = T(D.iyt2); L.iw0 = T(D.iw0); L.iw1re = T(D.iw1re); L.iw1im = T(D.iw1im); L.iw2 = T(D.iw2);
+    L.hinv = T(D.hinv);
+    L.beta = T(D.beta);
 }
 
 // dP/dtheta at x for theta = Om, OL, Or (Ok eliminated)
@@ -337,6 +347,16 @@ __device__ void setup_cosmo(const double *prm, CosmoRec &rec) {
     } else {
         D.y1re = __builtin_sqrt(D.w1re); D.y1im = 0.0; D.y2 = __builtin_sqrt(D.w2); D.y1abs2 = 0.0;
     }
+    D.iyt2 = 1.0 / D.yt2;
+    D.iw0 = 1.0 / D.w0;
+    if (pair) {
+        cx<double> iw1 = cdiv(mkc(1.0, 0.0), mkc(D.w1re, D.w1im));
+        D.iw1re = iw1.re; D.iw1im = iw1.im; D.iw2 = 0.0;
+    } else {
+        D.iw1re = 1.0 / D.w1re; D.iw1im = 0.0; D.iw2 = 1.0 / D.w2;
+    }
+    D.hinv = 1.0 / H0;
+    D.beta = beta;
     D.pre = 1.0 / __builtin_sqrt(beta);
     D.ok = Ok;
     D.sk = __builtin_sqrt(__builtin_fabs(Ok));

@@ -41,13 +41,13 @@ def test_argument_errors_are_synchronous(lib):
     # unknown kind / dtype
     assert lib.cosmo_distance(99, 1, dummy, 1, dummy, 1, 0, dummy, null, null, 0, null) == E_KIND
     assert lib.cosmo_distance(0, 7, dummy, 1, dummy, 1, 0, dummy, null, null, 0, null) == E_DTYPE
-    assert lib.cosmo_distance_vjp(-1, 1, dummy, 1, dummy, 1, 0, dummy, null, null, null, null, 0, null) == E_KIND
+    assert lib.cosmo_distance_vjp(-1, 1, dummy, 1, dummy, 1, 0, dummy, null, null, null, null, null, 0, null) == E_KIND
     # NULL pointers and negative sizes
     assert lib.cosmo_distance(0, 1, null, 1, dummy, 1, 0, dummy, null, null, 0, null) == E_ARG
     assert lib.cosmo_distance(0, 1, dummy, -1, dummy, 1, 0, dummy, null, null, 0, null) == E_ARG
     assert lib.cosmo_distance(0, 1, dummy, 1, dummy, 1, -5, dummy, null, null, 0, null) == E_ARG
     assert lib.cosmo_distance(0, 1, dummy, 1, null, 1, 0, dummy, null, null, 0, null) == E_ARG
-    assert lib.cosmo_distance_vjp(0, 1, dummy, 1, dummy, 1, 0, null, null, null, null, null, 0, null) == E_ARG
+    assert lib.cosmo_distance_vjp(0, 1, dummy, 1, dummy, 1, 0, null, dummy, null, null, null, null, 0, null) == E_ARG
     assert lib.cosmo_roots(null, 3, dummy, null, null) == E_ARG
     assert lib.cosmo_roots(dummy, -1, dummy, null, null) == E_ARG
     assert lib.carlson_rf(0, 4, dummy, dummy, null, dummy, null) == E_ARG
