@@ -121,9 +121,9 @@ def main():
     results, grads = {}, {}
     for path in args.paths.split(","):
         dt = torch.float32 if path == "f32" else torch.float64
-        gen.manual_seed(workloads.cotangent_seed())
+        gen.manual_seed(workloads.cotangent_seed())  # the same w (drawn in FP64) for both paths
         zt = torch.tensor(z, dtype=dt, device=dev)
-        w = torch.randn((n_c, n_z), dtype=dt, device=dev, generator=gen)
+        w = torch.randn((n_c, n_z), dtype=torch.float64, device=dev, generator=gen).to(dt)
 
         def step():  # mu and the gradient of (w * mu).sum(), one pass
             return cosmo.cosmo_distance_vjp("MU", p, zt, w, want_value=True, workspace=ws)

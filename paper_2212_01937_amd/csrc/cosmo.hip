@@ -57,9 +57,10 @@ __global__ void k_roots(const double *__restrict__ params, int64_t n, double *__
 }
 
 template <typename T, int KIND, bool PAIR>
-__device__ __forceinline__ T eval_kind(const LaneConst<T> &k, T z, bool &used_gl) {
+__device__ __forceinline__ T eval_kind(const CosmoRec &r, T z, bool &used_gl) {
+    const LaneConst<T> &k = lane_of<T>(r);
     used_gl = false;
-    if (KIND == COSMO_T) return k.th * t_hat<T, PAIR>(k, z);
+    if (KIND == COSMO_T) return k.th * t_hat<T, PAIR>(r, z);
     if (KIND == COSMO_X) return k.dh * x_hat<T, PAIR>(k, z, used_gl);
     T chi = chi_hat<T, PAIR>(k, z);
     T a, b, c, d;
@@ -85,8 +86,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(const CosmoRec *__restrict__
         T v;
         bool used_gl = false;
         if (!r.valid) v = Fp<T>::nan();
-        else if (r.pair) v = eval_kind<T, KIND, true>(lane_of<T>(r), zz, used_gl);
-        else v = eval_kind<T, KIND, false>(lane_of<T>(r), zz, used_gl);
+        else if (r.pair) v = eval_kind<T, KIND, true>(r, zz, used_gl);
+        else v = eval_kind<T, KIND, false>(r, zz, used_gl);
         out[c * n_z + i] = v;
         if (KIND == COSMO_X && info) {
             unsigned long long m = __ballot(used_gl);
@@ -127,7 +128,7 @@ __device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kA
     if (KIND == COSMO_T && !direct_mode(KIND, r, fp32)) {
         // time coordinate: Carlson derivatives (eqs. 2.10, 2.11) and the root chain
         TGrad<T, PAIR> tg;
-        t_grad<T, PAIR>(k, z, tg);
+        t_grad<T, PAIR>(r, z, tg);
         const T w = cot * k.th;
         acc[0] += w * tg.t;
         acc[1] += w * tg.dsig;
@@ -140,14 +141,21 @@ __device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kA
         return;
     }
     if (KIND == COSMO_T || KIND == COSMO_X) {
-        T val, g[3];
-        gl_integral<T, PAIR>(k, z, KIND == COSMO_T ? 1 : 2, true, val, g);
+        T qv, g[3];
+        gl_integral<T, PAIR>(k, z, KIND == COSMO_T ? 1 : 2, true, qv, g);
         const T scale = KIND == COSMO_T ? k.th : k.dh;
         const T x = T(1) + z;
         const T e = Ez<T>(k, z);
         gz = cot * scale * (KIND == COSMO_T ? Fp<T>::rcp(x * e) : x * x * Fp<T>::rcp(e));
-        // value for the H0 derivative: recompute with the Carlson forward
-        T v = KIND == COSMO_T ? k.th * t_hat<T, PAIR>(k, z) : k.dh * x_hat<T, PAIR>(k, z, used_gl);
+        // the value (also needed for the H0 derivative) by the forward's route: for X
+        // in FP32 with radiation that route is this same quadrature
+        T v;
+        if (KIND == COSMO_X && sizeof(T) == 4 && k.sigma != T(0)) {
+            v = k.dh * qv;
+            used_gl = true;
+        } else {
+            v = KIND == COSMO_T ? k.th * t_hat<T, PAIR>(r, z) : k.dh * x_hat<T, PAIR>(k, z, used_gl);
+        }
         acc[0] += cot * scale * g[0];
         acc[1] += cot * scale * g[1];
         acc[2] += cot * scale * g[2];

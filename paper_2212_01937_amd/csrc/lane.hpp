@@ -92,18 +92,77 @@ template <typename T, bool PAIR> __device__ __forceinline__ T chi_hat(const Lane
     return k.pre * T(2) * z * rf_s<T, PAIR>(g.U0 * g.U0, g.va, g.vb);
 }
 
-// t / (1/H0), eqs. 3.8 / B.2
-template <typename T, bool PAIR> __device__ __forceinline__ T t_hat(const LaneConst<T> &k, T z) {
+// Arguments of the time coordinate's integrals (eqs. 3.8 / B.2): the U_m of build_u,
+// V0 = U_0^2, W5, Q5 = x2 W5 / ((1 - s)(1 - s x2)) and S5 = Q5 - dz^2 rho_0 rho_1 rho_2.
+// W5 = U_j^2 + dz^2 (1 - s rho_k)(1 - s rho_l) rho_j is the same for every j; its terms
+// cancel when rho_j < 0 (at large z, by up to the ratio of the terms), so the j with
+// the smallest terms is used (for a pair, the real part of the slot-1 form).
+template <typename Q, bool PAIR>
+__device__ __forceinline__ void t_args_in(const LaneConst<Q> &k, Q z, Geo<Q, PAIR> &g, Q &V0, Q &W, Q &Qv, Q &S) {
+    build_u<Q, PAIR>(k, z, g);
+    V0 = g.U0 * g.U0;
+    const Q z2 = z * z;
+    W = V0 + z2 * k.c5;
+    Q m0 = V0 + Fp<Q>::abs(z2 * k.c5);
+    const Q w1 = g.va + z2 * k.c5b;
+    const Q m1 = (PAIR ? g.U1re * g.U1re + g.U1im * g.U1im : g.va) + Fp<Q>::abs(z2 * k.c5b);
+    if (m1 < m0) { W = w1; m0 = m1; }
+    if (!PAIR) {
+        const Q w2 = g.vb + z2 * k.c5c, m2 = g.vb + Fp<Q>::abs(z2 * k.c5c);
+        if (m2 < m0) W = w2;
+    }
+    Qv = (Q(1) + z) * W * Fp<Q>::rcp(k.yt2 * g.Xt2);
+    S = Qv - z2 * k.rprod;
+}
+
+template <typename T, bool PAIR> struct TArgs {
     Geo<T, PAIR> g;
-    build_u<T, PAIR>(k, z, g);
-    T V0 = g.U0 * g.U0;
-    T z2 = z * z;
-    T W5 = V0 + z2 * k.c5;
-    T Q5 = (T(1) + z) * W5 * Fp<T>::rcp(k.yt2 * g.Xt2);
-    T S5 = Q5 - z2 * k.rprod;
+    T V0, W, Q, S;
+};
+
+template <typename A, typename B, bool PAIR> __device__ __forceinline__ void geo_cast(const Geo<A, PAIR> &a, Geo<B, PAIR> &b) {
+    b.Xt = B(a.Xt); b.Xt2 = B(a.Xt2); b.X0 = B(a.X0); b.X02 = B(a.X02);
+    b.X1re = B(a.X1re); b.X1im = B(a.X1im); b.X1abs = B(a.X1abs); b.X2 = B(a.X2);
+    b.U0 = B(a.U0); b.U1re = B(a.U1re); b.U1im = B(a.U1im); b.U2 = B(a.U2);
+    b.T1_0 = B(a.T1_0); b.T2_0 = B(a.T2_0);
+    b.T1_1re = B(a.T1_1re); b.T1_1im = B(a.T1_1im); b.T2_1re = B(a.T2_1re); b.T2_1im = B(a.T2_1im);
+    b.T1_2 = B(a.T1_2); b.T2_2 = B(a.T2_2); b.va = B(a.va); b.vb = B(a.vb);
+}
+
+// The FP32 path forms these arguments in FP64 from the FP64 lane constants and rounds
+// once: in FP32 the products of square roots making U_m, and W5, accumulate a dozen
+// roundings, which at large z is the leading error of t (FP64 multiplies and FMAs
+// issue at the FP32 rate on this hardware; the Carlson iterations stay in FP32).
+template <typename T, bool PAIR> __device__ __forceinline__ void t_args(const CosmoRec &r, T z, TArgs<T, PAIR> &a);
+template <> __device__ __forceinline__ void t_args<double, true>(const CosmoRec &r, double z, TArgs<double, true> &a) {
+    t_args_in<double, true>(r.d, z, a.g, a.V0, a.W, a.Q, a.S);
+}
+template <> __device__ __forceinline__ void t_args<double, false>(const CosmoRec &r, double z, TArgs<double, false> &a) {
+    t_args_in<double, false>(r.d, z, a.g, a.V0, a.W, a.Q, a.S);
+}
+template <bool PAIR> __device__ __forceinline__ void t_args_f32(const CosmoRec &r, float z, TArgs<float, PAIR> &a) {
+    Geo<double, PAIR> gd;
+    double V0, W, Qv, S;
+    t_args_in<double, PAIR>(r.d, (double)z, gd, V0, W, Qv, S);
+    geo_cast<double, float, PAIR>(gd, a.g);
+    a.V0 = float(V0); a.W = float(W); a.Q = float(Qv); a.S = float(S);
+}
+template <> __device__ __forceinline__ void t_args<float, true>(const CosmoRec &r, float z, TArgs<float, true> &a) {
+    t_args_f32<true>(r, z, a);
+}
+template <> __device__ __forceinline__ void t_args<float, false>(const CosmoRec &r, float z, TArgs<float, false> &a) {
+    t_args_f32<false>(r, z, a);
+}
+
+// t / (1/H0), eqs. 3.8 / B.2
+template <typename T, bool PAIR> __device__ __forceinline__ T t_hat(const CosmoRec &r, T z) {
+    const LaneConst<T> &k = lane_of<T>(r);
+    TArgs<T, PAIR> a;
+    t_args<T, PAIR>(r, z, a);
+    const T z2 = z * z;
     T rf, rj;
-    rfj_s<T, PAIR>(V0, g.va, g.vb, W5, rf, rj);
-    T rc = rc_r(S5, Q5);
+    rfj_s<T, PAIR>(a.V0, a.g.va, a.g.vb, a.W, rf, rj);
+    T rc = rc_r(a.S, a.Q);
     return k.pre * T(2) * z * (z2 * T(1.0 / 3.0) * k.pre3 * rj + rc + k.sigma * rf);
 }
 
@@ -212,7 +271,18 @@ template <typename T, bool PAIR> __device__ T x_hat(const LaneConst<T> &k, T z, 
         const T A1 = DQ * Fp<T>::rcp(f2 + f1);
         const T rf = rf_s<T, PAIR>(V0, g.va, g.vb);
         const T br = z2 * T(1.0 / 3.0) * k.d0102 * rd + g.X0 * k.y0 * Fp<T>::rcp(g.U0);
-        return k.pre * T(2.0 / 3.0) * z * (A1 + k.xc3 * rf + T(2) * k.xs3 * br);
+        const T t2 = k.xc3 * rf, t3 = T(2) * k.xs3 * br;
+        const T sum = A1 + t2 + t3;
+        // the terms cancel at small z (by ~60 on the near-cubic workload): beyond a
+        // factor 4 in FP32 (64 in FP64) the quadrature route is taken
+        const T lim = fp32 ? T(4) : T(64);
+        if (!(Fp<T>::abs(A1) + Fp<T>::abs(t2) + Fp<T>::abs(t3) <= lim * Fp<T>::abs(sum))) {
+            used_gl = true;
+            T v, gd[3];
+            gl_integral<T, PAIR>(k, z, 2, false, v, gd);
+            return v;
+        }
+        return k.pre * T(2.0 / 3.0) * z * sum;
     }
     // eq. 3.9, normalised (i = 0 real root of Q, (j, k) = slots (1, 2), l = radiation root)
     const T yt2x = k.yt2 * g.Xt2;
@@ -416,16 +486,15 @@ template <typename T, bool PAIR> struct TGrad {
 };
 
 template <typename T, bool PAIR>
-__device__ void t_grad(const LaneConst<T> &k, T z, TGrad<T, PAIR> &o) {
-    Geo<T, PAIR> g;
-    build_u<T, PAIR>(k, z, g);
-    const T V0 = g.U0 * g.U0;
+__device__ void t_grad(const CosmoRec &r, T z, TGrad<T, PAIR> &o) {
+    const LaneConst<T> &k = lane_of<T>(r);
+    TArgs<T, PAIR> ta;
+    t_args<T, PAIR>(r, z, ta);
+    const Geo<T, PAIR> &g = ta.g;
+    const T V0 = ta.V0, W = ta.W, Qv = ta.Q, S = ta.S;
     const T z2 = z * z, x2 = T(1) + z;
     const T C5 = k.c5;
-    const T W = V0 + z2 * C5;
     const T iD = Fp<T>::rcp(k.yt2 * g.Xt2);
-    const T Qv = x2 * W * iD;
-    const T S = Qv - z2 * k.rprod;
     T rf, rj, rdx, rdz;
     cx<T> rdy;
     rfjd_s<T, PAIR>(V0, g.va, g.vb, W, rf, rj, rdx, rdy, rdz);

@@ -57,6 +57,7 @@ template <typename T> struct LaneConst {
     T Or, Om, OL;           // for E(z) in the z-gradient
     T q0, q1, q2;           // cubic factor coefficients
     T c5, pre3, rprod;      // T: (1-s r1)(1-s r2) r0, prod(1 - s r_n), r0 r1 r2
+    T c5b, c5c;             // T: the same coefficient for root slot 1 (real part for a pair) and slot 2
     T xc3, xc2, xs3;        // X: 3 r0^2 - d01 d02, 2 r0^2 - d01 d02, S3 = sum r_n
     T d0102;                // X: (r1 - r0)(r2 - r0)
     T om1s12, op1s3, om1s0; // X: (1-s r1)(1-s r2), 1 + s S3, 1 - s r0
@@ -188,7 +189,7 @@ template <typename T> __device__ void fill_lane(LaneConst<T> &L, const LaneConst
     L.y1abs2 = T(D.y1abs2); L.pre = T(D.pre); L.ok = T(D.ok); L.sk = T(D.sk);
     L.dh = T(D.dh); L.th = T(D.th); L.Or = T(D.Or); L.Om = T(D.Om); L.OL = T(D.OL);
     L.q0 = T(D.q0); L.q1 = T(D.q1); L.q2 = T(D.q2);
-    L.c5 = T(D.c5); L.pre3 = T(D.pre3); L.rprod = T(D.rprod);
+    L.c5 = T(D.c5); L.pre3 = T(D.pre3); L.rprod = T(D.rprod); L.c5b = T(D.c5b); L.c5c = T(D.c5c);
     L.xc3 = T(D.xc3); L.xc2 = T(D.xc2); L.xs3 = T(D.xs3); L.d0102 = T(D.d0102);
     L.om1s12 = T(D.om1s12); L.op1s3 = T(D.op1s3); L.om1s0 = T(D.om1s0);
     L.d02re = T(D.d02re); L.d02im = T(D.d02im);
@@ -250,14 +251,23 @@ __device__ void setup_cosmo(const double *prm, CosmoRec &rec) {
 
     // --- roots of the cubic factor.  Deflate by the real root that is best
     // isolated (largest |Q'(r)|): deflating one member of a near-double pair would
-    // pass its ~eps/separation error on to the quadratic.
-    int it_r = 0, it_r2 = 0;
-    double rl_ = cubic_real_root(q2, q1, q0, true, it_r);
-    double rr_ = cubic_real_root(q2, q1, q0, false, it_r2);
-    if (it_r >= 300 || it_r2 >= 300) info |= COSMO_INFO_ROOT_NOCONV;
-    double dl_ = __builtin_fabs((3.0 * rl_ + 2.0 * q2) * rl_ + q1);
-    double dr_ = __builtin_fabs((3.0 * rr_ + 2.0 * q2) * rr_ + q1);
-    double r = dl_ >= dr_ ? rl_ : rr_;
+    // pass its ~eps/separation error on to the quadratic.  The leftmost real root
+    // comes from Newton started left of every root; when the quadratic left by it
+    // has real roots, the best isolated of the three (by the product of distances,
+    // |Q'|) is polished on Q and taken instead.
+    int it_r = 0;
+    double r = cubic_real_root(q2, q1, q0, true, it_r);
+    if (it_r >= 300) info |= COSMO_INFO_ROOT_NOCONV;
+    {
+        cx<double> a, b;
+        const double l1 = q2 + r, l0 = q1 + r * l1;
+        if (!quad_roots(l1, l0, a, b)) {
+            const double gr = __builtin_fabs((r - a.re) * (r - b.re));
+            const double ga = __builtin_fabs((a.re - r) * (a.re - b.re));
+            const double gb = __builtin_fabs((b.re - r) * (b.re - a.re));
+            if (tmax(ga, gb) > gr) r = newton_polish(q2, q1, q0, mkc(ga >= gb ? a.re : b.re, 0.0)).re;
+        }
+    }
     // forward deflation: b1 = q2 + r, b0 = q1 + r b1;  backward: b0 = -q0/r, b1 = (b0 - q1)/r
     cx<double> u1, v1, u2, v2;
     double fb1 = q2 + r, fb0 = q1 + r * fb1;
@@ -367,6 +377,11 @@ __device__ void setup_cosmo(const double *prm, CosmoRec &rec) {
     cx<double> o1 = mkc(1.0, 0.0) - rho[1] * sigma, o2 = mkc(1.0, 0.0) - rho[2] * sigma;
     double o12 = (o1 * o2).re;
     D.c5 = o12 * s0;
+    {   // (1 - s r_a)(1 - s r_b) r_m for m = 1, 2 ({a, b} the other slots); real parts
+        cx<double> o0 = mkc(1.0 - sigma * s0, 0.0);
+        D.c5b = (o0 * o2 * rho[1]).re;
+        D.c5c = (o0 * o1 * rho[2]).re;
+    }
     D.pre3 = o12 * (1.0 - sigma * s0);
     D.rprod = (rho[0] * rho[1] * rho[2]).re;
     cx<double> d01 = rho[1] - rho[0], d02 = rho[2] - rho[0];
@@ -384,15 +399,16 @@ __device__ void setup_cosmo(const double *prm, CosmoRec &rec) {
     // singularity to that half-line sizes the quadrature panels.
     {
         double dmin = 1e300;
+        // (a panel-sizing heuristic: single precision is ample)
         for (int n = 0; n < 3; ++n) {
             double mag = cabs(rho[n]);
             if (!(mag > 0.0)) continue;
-            double lr = ::log(mag), li = ::atan2(rho[n].im, rho[n].re);
+            double lr = logf((float)mag), li = atan2f((float)rho[n].im, (float)rho[n].re);
             double d = lr >= 0.0 ? __builtin_fabs(li) : __builtin_sqrt(lr * lr + li * li);
             dmin = d < dmin ? d : dmin;
         }
         if (Or > 0.0) { // radiation root rho_l = 1/sigma < 0: ln rho_l = ln|rho_l| + i pi
-            double lr = -::log(-sigma);
+            double lr = -logf((float)(-sigma));
             double d = lr >= 0.0 ? M_PI : __builtin_sqrt(lr * lr + M_PI * M_PI);
             dmin = d < dmin ? d : dmin;
         }

@@ -1,0 +1,28 @@
+// Host build of the per-lane forward formulas (D_C, T, X) for tests.
+#include "../../paper_2212_01937_amd/csrc/lane.hpp"
+using namespace cosmo;
+namespace cosmo {
+double c_gl64_x[kGlN64], c_gl64_w[kGlN64];
+float c_gl32_x[kGlN32], c_gl32_w[kGlN32];
+}
+extern "C" void host_set_gl(const double *x64, const double *w64, const float *x32, const float *w32) {
+    for (int i = 0; i < kGlN64; ++i) { c_gl64_x[i] = x64[i]; c_gl64_w[i] = w64[i]; }
+    for (int i = 0; i < kGlN32; ++i) { c_gl32_x[i] = x32[i]; c_gl32_w[i] = w32[i]; }
+}
+template <typename T, bool PAIR> static double one(const CosmoRec &r, int kind, T z) {
+    const LaneConst<T> &k = lane_of<T>(r);
+    bool ugl = false;
+    if (kind == COSMO_T) return k.th * t_hat<T, PAIR>(r, z);
+    if (kind == COSMO_X) return k.dh * x_hat<T, PAIR>(k, z, ugl);
+    return k.dh * chi_hat<T, PAIR>(k, z);
+}
+// kind: COSMO_DC, COSMO_T or COSMO_X; dt: 0 FP32, 1 FP64.  NaN for invalid cosmologies.
+extern "C" void host_eval(const double *prm, int kind, int dt, const double *z, long n, double *out) {
+    CosmoRec r;
+    setup_cosmo(prm, r);
+    for (long i = 0; i < n; ++i) {
+        if (!r.valid) { out[i] = __builtin_nan(""); continue; }
+        if (dt == 0) out[i] = r.pair ? one<float, true>(r, kind, (float)z[i]) : one<float, false>(r, kind, (float)z[i]);
+        else out[i] = r.pair ? one<double, true>(r, kind, z[i]) : one<double, false>(r, kind, z[i]);
+    }
+}
