@@ -8,8 +8,11 @@ with a fixed random cotangent w that also writes mu (the value and the adjoint o
 per cosmology and d/dz per redshift.  Roots are found inside every step.  Inputs
 are resident in device memory before the timed region.
 
-Also timed, reported under "paths": the forward alone (cosmo_distance) and the
-two-call forward + adjoint sequence, for the FP32 and the FP64 path.
+Also timed, reported under "paths": the forward alone (cosmo_distance), the
+two-call forward + adjoint sequence and the materialised per-evaluation Jacobian
+(cosmo_distance_jac), for the FP32 and the FP64 path.  "mu_err_as_DL_rel" is the
+sampled mu error expressed as a relative D_L error; it includes the FP32 rounding
+of mu itself (1 ulp = 3.8e-6 mag at mu ~ 40).
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -134,6 +137,9 @@ def main():
         def vjp():
             return cosmo.cosmo_distance_vjp("MU", p, zt, w, workspace=ws)
 
+        def jacobian():  # materialised per-evaluation d mu / d(H0, Om0, OL0, Or0, z)
+            return cosmo.cosmo_distance_jac("MU", p, zt, workspace=ws)
+
         for _ in range(args.warmup):
             step()
             fwd()
@@ -142,6 +148,9 @@ def main():
         step_ev, step_wall, (mu, gp, gz) = timed(step, args.steps, stream, torch)
         fwd_ev, _, _ = timed(fwd, args.steps, stream, torch)
         vjp_ev, _, _ = timed(vjp, args.steps, stream, torch)
+        jacobian()
+        jac_ev, _, _ = timed(jacobian, max(1, args.steps // 4), stream, torch)
+        torch.cuda.empty_cache()
         # sampled error of mu vs the FP64 oracle at this size
         import oracle
         ci, zi = workloads.subsample(n_c, n_z, 200, seed=99)
@@ -155,8 +164,10 @@ def main():
                          "step_event_ms_median": med, "step_event_ms_mean": float(np.mean(step_ev)),
                          "fwd_ms": float(np.median(fwd_ev)), "fwd_evals_per_s": evals / (np.median(fwd_ev) * 1e-3),
                          "two_call_fwd_plus_vjp_ms": float(np.median(fwd_ev) + np.median(vjp_ev)),
+                         "jacobian_ms": float(np.median(jac_ev)),
+                         "jacobian_evals_per_s": evals / (np.median(jac_ev) * 1e-3),
                          "max_abs_err_mu_mag": float(np.max(np.abs(mu_s - ref))),
-                         "max_rel_err_DL": float(dl_rel)}
+                         "mu_err_as_DL_rel": float(dl_rel)}
         del mu, gp, gz, w, zt
         torch.cuda.empty_cache()
     if "f32" in grads and "f64" in grads:

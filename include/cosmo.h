@@ -128,6 +128,18 @@ int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params,
                        const void *cot, void *out, double *grad_params, void *grad_z,
                        int32_t *info, void *workspace, size_t workspace_bytes, void *stream);
 
+/* cosmo_distance_jac -- the observable with its materialised per-evaluation
+ * Jacobian: the same derivatives as cosmo_distance_vjp (Carlson derivatives,
+ * eqs. 2.10-2.12; root Jacobian, app. A; z by the fundamental theorem of
+ * calculus), not summed.
+ * out : [n_cosmo][n_z] of dtype, nullable (the observable, as cosmo_distance).
+ * jac : [5][n_cosmo][n_z] of dtype, five planes d out/d(H0, Om0, OL0, Or0, z);
+ *       NaN rows for cosmologies outside the method.
+ * info, workspace, workspace_bytes: as cosmo_distance.                          */
+int cosmo_distance_jac(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo,
+                       const void *z, int64_t n_z, int64_t z_cosmo_stride, void *out, void *jac,
+                       int32_t *info, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Library version string (static storage). */
 const char *cosmo_version(void);
 

@@ -2,7 +2,7 @@
 
 Argument marshalling only: every step of the computation runs in the HIP
 kernels of csrc/.  Entry points keep the C names (cosmo_roots, carlson_rf,
-carlson_rd, carlson_rj, carlson_rc, cosmo_distance, cosmo_distance_vjp);
+carlson_rd, carlson_rj, carlson_rc, cosmo_distance, cosmo_distance_vjp, cosmo_distance_jac);
 `distance` wraps the forward/adjoint pair in a torch.autograd.Function.
 
 Device tensors are passed as raw pointers together with the current torch
@@ -27,7 +27,7 @@ INFO = {"CUBIC": 0x1, "QUARTIC": 0x2, "THREE_REAL": 0x4, "YELLOW": 0x8, "RED": 0
 
 # every function declared in include/cosmo.h
 EXPORTS = ("cosmo_workspace_size", "cosmo_roots", "carlson_rf", "carlson_rd", "carlson_rj",
-           "carlson_rc", "cosmo_distance", "cosmo_distance_vjp", "cosmo_version")
+           "carlson_rc", "cosmo_distance", "cosmo_distance_vjp", "cosmo_distance_jac", "cosmo_version")
 
 _lib = None
 
@@ -55,6 +55,8 @@ def load():
                                    ctypes.c_size_t, vp]
     lib.cosmo_distance_vjp.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, vp, vp,
                                        i32p, vp, ctypes.c_size_t, vp]
+    lib.cosmo_distance_jac.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, i32p, vp,
+                                       ctypes.c_size_t, vp]
     for n in EXPORTS[:-1]:
         getattr(lib, n).restype = ctypes.c_int
     lib.cosmo_version.restype = ctypes.c_char_p
@@ -209,6 +211,26 @@ def cosmo_distance_vjp(kind, params, z, cot, want_params=True, want_z=True, info
     _check(rc, "cosmo_distance_vjp")
     res = ((val,) if want_value else ()) + (gp, gz)
     return res + (inf,) if info else res
+
+
+def cosmo_distance_jac(kind, params, z, want_value=True, info=False, workspace=None):
+    """Materialised Jacobian: (value [n_cosmo, n_z] or None, jac [5, n_cosmo, n_z]) with
+    jac[q] = d value / d(H0, Om0, OL0, Or0, z)[q], in z's dtype."""
+    lib = load()
+    p = _params(params)
+    n_c = p.shape[0]
+    zc, n_z, stride, _ = _z_layout(z, n_c)
+    if zc.device != p.device:
+        raise CosmoError("params and z must be on the same device")
+    val = torch.empty((n_c, n_z), dtype=zc.dtype, device=p.device) if want_value else None
+    jac = torch.empty((5, n_c, n_z), dtype=zc.dtype, device=p.device)
+    inf = torch.empty(n_c, dtype=torch.int32, device=p.device) if info else None
+    ws = workspace if workspace is not None else _workspace(n_c, n_z, p.device)
+    with torch.cuda.device(p.device):
+        rc = lib.cosmo_distance_jac(KINDS[kind], DTYPES[zc.dtype], _ptr(p), n_c, _ptr(zc), n_z, stride,
+                                    _ptr(val), _ptr(jac), _ptr(inf), _ptr(ws), ws.numel(), _stream(p.device))
+    _check(rc, "cosmo_distance_jac")
+    return (val, jac, inf) if info else (val, jac)
 
 
 class _Distance(torch.autograd.Function):

@@ -96,101 +96,169 @@ __global__ __launch_bounds__(kBlock) void k_forward(const CosmoRec *__restrict__
     }
 }
 
-// Accumulator slots of the adjoint (per lane, then per block, then per cosmology)
-//   root mode:   0 sum w chi, 1 sum w dchi/dsigma, 2 sum w dchi/drho0,
-//                3/4 sum w dchi/drho1 (re, im) [pair] or drho1, drho2 [real],
-//                5 sum cot dout/dOk, 6 sum cot dout/dH0
-//   direct mode: 0..2 sum w dI/d(Om, OL, Or) (Leibniz quadrature), 5, 6 as above
-constexpr int kAcc = 8;
+// Accumulator slots of the adjoint (per lane, then per wave, then per cosmology),
+// w = cot dout/dbase:
+//   0 sum w base, 1 sum w dbase/dsigma, 2 sum w dbase/drho0,
+//   3/4 sum w dbase/drho1 (re, im) [pair] or drho1, drho2 [real]   (root-chain lanes),
+//   5 sum cot dout/dOk, 6 sum cot dout/dH0,
+//   7..9 sum w dbase/d(Om, OL, Or)                                  (quadrature lanes).
+constexpr int kAcc = 10;
 
 __device__ __forceinline__ bool direct_mode(int kind, const CosmoRec &r, bool fp32) {
     if (kind == COSMO_X) return true;
     return r.minsep < (fp32 ? 2e-2 : 1e-4);
 }
 
-// Kept out of line: a rarely taken FP64 branch whose registers should not
-// count against the hot adjoint kernels.
-template <bool PAIR>
-__device__ __attribute__((noinline)) void gl_chi_grad(const CosmoRec &r, double z, double &chi, double g[3]) {
+// Kept out of line: a rarely taken FP64 branch whose registers should not count
+// against the hot adjoint kernels.  Results come back by value (in registers): an
+// output array whose address escapes into the call would move the caller's
+// per-lane state to scratch memory.
+struct GlChi {
+    double chi, g0, g1, g2;
+};
+template <bool PAIR> __device__ __attribute__((noinline)) GlChi gl_chi_grad(const CosmoRec &r, double z) {
+    double chi, g[3];
     gl_integral<double, PAIR>(r.d, z, 0, true, chi, g);
+    return GlChi{chi, g[0], g[1], g[2]};
 }
 
-// One (cosmology, redshift) lane of the adjoint: accumulates the parameter
-// partials into acc, returns the z-gradient in gz and the observable in val
-// (the same quantity cosmo_distance evaluates; used_gl flags the quadrature
-// route of X).
+// FP32 small-z lanes.  There the partials in the root parameters are O(z) while the
+// parameter derivatives they contract to are O(z^2) (E(0) = 1 for every theta), so
+// FP32 partials lose about eps_32 / z in the contraction.  Below kSmallZ32 the FP32
+// path takes the Leibniz-rule quadrature in the lane's precision instead, which has
+// no such cancellation; one 8-node panel suffices there (the panel is a fraction of
+// the distance to the nearest singularity of the integrand).
+constexpr float kSmallZ32 = 0.02f;
+
+// Derivatives of one (cosmology, redshift) lane.  The observable is out = F(base, Ok, z,
+// H0) with base = chi (D_C family), t (T) or X; s = dF/dbase.
+//   root mode:   p[0..4] = base and its partials in the root parameters (sigma,
+//                rho_0, rho_1 re/im for a pair or rho_1, rho_2), all at fixed beta:
+//                dbase/dtheta = -p0/(2 beta) dbeta/dtheta + sum p_k drho_k/dtheta;
+//   quadrature:  q[0..2] = dbase/d(Om, OL, Or) by Leibniz-rule quadrature (near-multiple
+//                roots and X: FP64 / lane precision; FP32 lanes at z < kSmallZ32).
+// dok = dF/dOk at fixed base (the curvature transform; dOk/dtheta = -1), dh = dF/dH0,
+// dz = dF/dz (fundamental theorem of calculus).
+template <typename T> struct LaneGrad {
+    T val, s, dok, dh, dz;
+    T p[5];
+    double q[3];
+    bool quad; // this lane's parameter partials are q (quadrature) rather than p
+};
+
 template <typename T, int KIND, bool PAIR>
-__device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kAcc], T &gz, T &val,
-                                         bool &used_gl) {
+__device__ __forceinline__ void lane_grad(const CosmoRec &r, T z, LaneGrad<T> &o, bool &used_gl) {
     const LaneConst<T> &k = lane_of<T>(r);
     const bool fp32 = sizeof(T) == 4;
     const T H0inv = k.hinv;
+    o.dok = T(0);
+    o.quad = false;
+    const bool small = fp32 && z < T(kSmallZ32);
     if (KIND == COSMO_T && !direct_mode(KIND, r, fp32)) {
         // time coordinate: Carlson derivatives (eqs. 2.10, 2.11) and the root chain
-        TGrad<T, PAIR> tg;
-        t_grad<T, PAIR>(r, z, tg);
-        const T w = cot * k.th;
-        acc[0] += w * tg.t;
-        acc[1] += w * tg.dsig;
-        acc[2] += w * tg.dr0;
-        acc[3] += w * tg.dr1re;
-        acc[4] += w * (PAIR ? tg.dr1im : tg.dr2);
-        acc[6] += -w * tg.t * H0inv;
-        gz = w * Fp<T>::rcp(T(1) + z) * iEz<T>(k, z);
-        val = k.th * tg.t;
+        if (small) {
+            T tv, g[3];
+            gl_integral<T, PAIR>(k, z, 1, true, tv, g, 1);
+            o.p[0] = tv;
+            o.q[0] = g[0]; o.q[1] = g[1]; o.q[2] = g[2];
+            o.quad = true;
+        } else {
+            TGrad<T, PAIR> tg;
+            t_grad<T, PAIR>(r, z, tg);
+            o.p[0] = tg.t; o.p[1] = tg.dsig; o.p[2] = tg.dr0; o.p[3] = tg.dr1re; o.p[4] = PAIR ? tg.dr1im : tg.dr2;
+        }
+        o.s = k.th;
+        o.val = k.th * o.p[0];
+        o.dh = -o.val * H0inv;
+        o.dz = k.th * Fp<T>::rcp(T(1) + z) * iEz<T>(k, z);
         return;
     }
     if (KIND == COSMO_T || KIND == COSMO_X) {
         T qv, g[3];
         gl_integral<T, PAIR>(k, z, KIND == COSMO_T ? 1 : 2, true, qv, g);
-        const T scale = KIND == COSMO_T ? k.th : k.dh;
+        o.s = KIND == COSMO_T ? k.th : k.dh;
         const T x = T(1) + z;
         const T e = Ez<T>(k, z);
-        gz = cot * scale * (KIND == COSMO_T ? Fp<T>::rcp(x * e) : x * x * Fp<T>::rcp(e));
+        o.dz = o.s * (KIND == COSMO_T ? Fp<T>::rcp(x * e) : x * x * Fp<T>::rcp(e));
         // the value (also needed for the H0 derivative) by the forward's route: for X
         // in FP32 with radiation that route is this same quadrature
-        T v;
         if (KIND == COSMO_X && sizeof(T) == 4 && k.sigma != T(0)) {
-            v = k.dh * qv;
+            o.val = k.dh * qv;
             used_gl = true;
         } else {
-            v = KIND == COSMO_T ? k.th * t_hat<T, PAIR>(r, z) : k.dh * x_hat<T, PAIR>(k, z, used_gl);
+            o.val = KIND == COSMO_T ? k.th * t_hat<T, PAIR>(r, z) : k.dh * x_hat<T, PAIR>(k, z, used_gl);
         }
-        acc[0] += cot * scale * g[0];
-        acc[1] += cot * scale * g[1];
-        acc[2] += cot * scale * g[2];
-        acc[6] += -cot * v * H0inv;
-        val = v;
+        o.q[0] = g[0]; o.q[1] = g[1]; o.q[2] = g[2];
+        o.quad = true;
+        o.dh = -o.val * H0inv;
         return;
     }
+    T dzz;
     if (direct_mode(KIND, r, fp32)) {
         // near-multiple roots: chi and its parameter gradient by FP64 quadrature
-        double chi, g[3];
-        gl_chi_grad<PAIR>(r, (double)z, chi, g);
-        T dchi, dok, dzz, dh;
-        val = observable<T>(KIND, k, T(chi), z, H0inv, dchi, dok, dzz, dh);
-        const double w = (double)cot * (double)dchi;
-        acc[0] += T(w * g[0]);
-        acc[1] += T(w * g[1]);
-        acc[2] += T(w * g[2]);
-        acc[5] += cot * dok;
-        acc[6] += cot * dh;
-        gz = cot * (dzz + dchi * iEz<T>(k, z));
-        return;
+        const GlChi gc = gl_chi_grad<PAIR>(r, (double)z);
+        o.q[0] = gc.g0; o.q[1] = gc.g1; o.q[2] = gc.g2;
+        o.quad = true;
+        o.val = observable<T>(KIND, k, T(gc.chi), z, H0inv, o.s, o.dok, dzz, o.dh);
+    } else {
+        if (small) {
+            T cv, g[3];
+            gl_integral<T, PAIR>(k, z, 0, true, cv, g, 1);
+            o.p[0] = cv;
+            o.q[0] = g[0]; o.q[1] = g[1]; o.q[2] = g[2];
+            o.quad = true;
+        } else {
+            ChiGrad<T, PAIR> cg;
+            chi_grad<T, PAIR>(k, z, cg);
+            o.p[0] = cg.chi; o.p[1] = cg.dsig; o.p[2] = cg.dr0; o.p[3] = cg.dr1re; o.p[4] = PAIR ? cg.dr1im : cg.dr2;
+        }
+        o.val = observable<T>(KIND, k, o.p[0], z, H0inv, o.s, o.dok, dzz, o.dh);
     }
-    ChiGrad<T, PAIR> cg;
-    chi_grad<T, PAIR>(k, z, cg);
-    T dchi, dok, dzz, dh;
-    val = observable<T>(KIND, k, cg.chi, z, H0inv, dchi, dok, dzz, dh);
-    const T w = cot * dchi;
-    acc[0] += w * cg.chi;
-    acc[1] += w * cg.dsig;
-    acc[2] += w * cg.dr0;
-    acc[3] += w * cg.dr1re;
-    acc[4] += w * (PAIR ? cg.dr1im : cg.dr2);
-    acc[5] += cot * dok;
-    acc[6] += cot * dh;
-    gz = cot * (dzz + dchi * iEz<T>(k, z));
+    o.dz = dzz + o.s * iEz<T>(k, z);
+}
+
+// One lane of the adjoint: accumulates the cotangent-weighted partials into acc,
+// returns the z-gradient in gz and the observable in val (the quantity
+// cosmo_distance evaluates; used_gl flags the quadrature route of X).
+template <typename T, int KIND, bool PAIR>
+__device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kAcc], T &gz, T &val,
+                                         bool &used_gl) {
+    LaneGrad<T> o;
+    lane_grad<T, KIND, PAIR>(r, z, o, used_gl);
+    val = o.val;
+    gz = cot * o.dz;
+    // increments formed per route, then added to every slot unconditionally (keeps
+    // the accumulators in registers)
+    T d[5], e[3];
+    if (o.quad) {
+        const double w = (double)cot * (double)o.s;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) d[i] = T(0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) e[i] = T(w * o.q[i]);
+    } else {
+        const T w = cot * o.s;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) d[i] = w * o.p[i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) e[i] = T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) acc[i] += d[i];
+    acc[5] += cot * o.dok;
+    acc[6] += cot * o.dh;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc[7 + i] += e[i];
+}
+
+// Contraction of root-space partials with the root Jacobian (app. A), FP64:
+// d base / d theta for theta = (Om, OL, Or).  a[0..4] as LaneGrad::p (or their
+// cotangent-weighted sums).
+__device__ __forceinline__ double root_contract(const CosmoRec &r, const double a[5], int th) {
+    double v = -a[0] / (2.0 * r.beta) * r.dbeta[th] + a[1] * r.dsigma[th] + a[2] * r.drho_re[0][th];
+    if (r.pair) v += 2.0 * (a[3] * r.drho_re[1][th] - a[4] * r.drho_im[1][th]);
+    else v += a[3] * r.drho_re[1][th] + a[4] * r.drho_re[2][th];
+    return v;
 }
 
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
@@ -273,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp(const CosmoRec *__restrict__ rec
         }
         if (pacc) {
 #pragma unroll
-            for (int s = 0; s < kAcc - 1; ++s) {
+            for (int s = 0; s < kAcc; ++s) {
                 T v = wave_sum(acc[s]);
                 if (lane == 0) pacc[(c * nwz + gw) * kAcc + s] = (double)v;
             }
@@ -290,16 +358,71 @@ __global__ __launch_bounds__(kBlock) void k_vjp(const CosmoRec *__restrict__ rec
     }
 }
 
+// Materialised Jacobian: per lane the observable and d out / d(H0, Om0, OL0, Or0, z),
+// written as five planes jac[q][c][i]; the root-space partials are contracted with the
+// root Jacobian per lane, in FP64.  Grid as k_forward.
+template <typename T, int KIND>
+__global__ __launch_bounds__(kBlock) void k_jac(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
+                                                 const T *__restrict__ z, int64_t n_z, int64_t zstride,
+                                                 T *__restrict__ out, T *__restrict__ jac, int32_t *__restrict__ info,
+                                                 int ct, int64_t nzb) {
+    const int64_t b = blockIdx.x;
+    const int64_t tile = b / nzb, zb = b - tile * nzb;
+    const int64_t i = zb * kBlock + threadIdx.x;
+    const bool active = i < n_z;
+    const int64_t c0 = tile * ct;
+    const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
+    const int64_t plane = n_cosmo * n_z;
+    const T zshared = (zstride == 0 && active) ? z[i] : T(0);
+    for (int64_t c = c0; c < c1; ++c) {
+        const CosmoRec &r = recs[c];
+        if (!active) continue;
+        const T zz = zstride == 0 ? zshared : z[c * zstride + i];
+        T v, J[5];
+        bool used_gl = false;
+        if (!r.valid) {
+            v = Fp<T>::nan();
+#pragma unroll
+            for (int q = 0; q < 5; ++q) J[q] = Fp<T>::nan();
+        } else {
+            LaneGrad<T> o;
+            if (r.pair) lane_grad<T, KIND, true>(r, zz, o, used_gl);
+            else lane_grad<T, KIND, false>(r, zz, o, used_gl);
+            v = o.val;
+            J[0] = o.dh;
+            J[4] = o.dz;
+            double pd[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) pd[q] = o.quad ? 0.0 : (double)o.p[q];
+#pragma unroll
+            for (int th = 0; th < 3; ++th) {
+                const double d = o.quad ? o.q[th] : root_contract(r, pd, th);
+                J[1 + th] = T((double)o.s * d - (double)o.dok);
+            }
+        }
+        const int64_t e = c * n_z + i;
+        if (out) out[e] = v;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) jac[q * plane + e] = J[q];
+        if (KIND == COSMO_X && info) {
+            unsigned long long m = __ballot(used_gl);
+            if (m && (int)__lane_id() == __ffsll((long long)m) - 1) atomicOr(info + c, COSMO_INFO_X_QUADRATURE);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_finalize_params(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
                                                             const double *__restrict__ pacc, int64_t nwz,
                                                             int kind, int fp32, double *__restrict__ grad) {
     __shared__ double red[kBlock / 64][kAcc];
     const int64_t c = blockIdx.x;
     if (c >= n_cosmo) return;
-    double acc[kAcc] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[kAcc];
+#pragma unroll
+    for (int s = 0; s < kAcc; ++s) acc[s] = 0.0;
     for (int64_t q = threadIdx.x; q < nwz; q += kBlock)
 #pragma unroll
-        for (int s = 0; s < kAcc - 1; ++s) acc[s] += pacc[(c * nwz + q) * kAcc + s];
+        for (int s = 0; s < kAcc; ++s) acc[s] += pacc[(c * nwz + q) * kAcc + s];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
     for (int s = 0; s < kAcc; ++s) {
@@ -322,13 +445,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize_params(const CosmoRec *__re
     g[0] = a[6];
     for (int th = 0; th < 3; ++th) {
         double v;
-        if (direct_mode(kind, r, fp32 != 0)) {
-            v = a[th];
-        } else {
-            v = -a[0] / (2.0 * r.beta) * r.dbeta[th] + a[1] * r.dsigma[th] + a[2] * r.drho_re[0][th];
-            if (r.pair) v += 2.0 * (a[3] * r.drho_re[1][th] - a[4] * r.drho_im[1][th]);
-            else v += a[3] * r.drho_re[1][th] + a[4] * r.drho_re[2][th];
-        }
+        // root-chain lanes (none on cosmologies whose gradient is all quadrature) plus
+        // the quadrature lanes
+        v = (direct_mode(kind, r, fp32 != 0) ? 0.0 : root_contract(r, a, th)) + a[7 + th];
         g[1 + th] = v - a[5]; // explicit Ok in the curvature transform: dOk/dtheta = -1
     }
 }
@@ -506,6 +625,26 @@ int launch_forward(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, 
 }
 
 template <typename T>
+int launch_jac(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int64_t n_z, int64_t zstride, T *out,
+               T *jac, int32_t *info, hipStream_t s) {
+    Tiling t = tiling(n_cosmo, n_z);
+    dim3 grid((unsigned)t.nblocks), block(kBlock);
+#define COSMO_JAC(K) \
+    hipLaunchKernelGGL((k_jac<T, K>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, out, jac, info, t.ct, t.nzb)
+    switch (kind) {
+    case COSMO_DC: COSMO_JAC(COSMO_DC); break;
+    case COSMO_DM: COSMO_JAC(COSMO_DM); break;
+    case COSMO_DL: COSMO_JAC(COSMO_DL); break;
+    case COSMO_MU: COSMO_JAC(COSMO_MU); break;
+    case COSMO_T: COSMO_JAC(COSMO_T); break;
+    case COSMO_X: COSMO_JAC(COSMO_X); break;
+    case COSMO_DA: COSMO_JAC(COSMO_DA); break;
+    }
+#undef COSMO_JAC
+    return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
+}
+
+template <typename T>
 int launch_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int64_t n_z, int64_t zstride,
                const T *cot, T *out, double *grad_params, T *grad_z, int32_t *info, const WsLayout &L, char *ws,
                hipStream_t s) {
@@ -675,6 +814,33 @@ int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params, in
                                  (float *)out, grad_params, (float *)grad_z, info, L, (char *)ws.ptr, s);
     return launch_vjp<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, (const double *)cot,
                               (double *)out, grad_params, (double *)grad_z, info, L, (char *)ws.ptr, s);
+}
+
+int cosmo_distance_jac(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo, const void *z,
+                       int64_t n_z, int64_t z_cosmo_stride, void *out, void *jac, int32_t *info, void *workspace,
+                       size_t workspace_bytes, void *stream) {
+    if (!valid_kind(kind)) return COSMO_E_KIND;
+    if (!valid_dtype(dt)) return COSMO_E_DTYPE;
+    if (n_cosmo < 0 || n_z < 0 || z_cosmo_stride < 0) return COSMO_E_ARG;
+    if (n_cosmo > 0 && !params) return COSMO_E_ARG;
+    if (n_cosmo > 0 && n_z > 0 && (!z || !jac)) return COSMO_E_ARG;
+    if (check_grid(n_cosmo, n_z) != COSMO_OK) return COSMO_E_ARG;
+    if (n_cosmo == 0) return COSMO_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_init();
+    if (rc != COSMO_OK) return rc;
+    WsLayout L = ws_layout(n_cosmo, 0);
+    Workspace ws;
+    rc = ws.acquire(workspace, workspace_bytes, L.pacc, s);
+    if (rc != COSMO_OK) return rc;
+    CosmoRec *recs = (CosmoRec *)ws.ptr;
+    rc = launch_setup(params, n_cosmo, recs, info, s);
+    if (rc != COSMO_OK || n_z == 0) return rc;
+    if (dt == COSMO_F32)
+        return launch_jac<float>(kind, recs, n_cosmo, (const float *)z, n_z, z_cosmo_stride, (float *)out,
+                                 (float *)jac, info, s);
+    return launch_jac<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, (double *)out,
+                              (double *)jac, info, s);
 }
 
 } // extern "C"

@@ -201,18 +201,18 @@ template <> struct GlRule<float> {
 // (eqs. 2.3-2.5): power 0 -> int x/E du (D_C), 1 -> int 1/E du (T), 2 -> int x^3/E du
 // (X).  With grad, also the Leibniz derivatives -1/2 int f dP/dtheta / E^3 du for
 // theta = (Om, OL, Or).  E^2 = beta (1 - sigma x) Q(x) in factored form.
-// The number of equal panels is max(4, U / dpath) (capped at 64): every panel is then
-// no wider than the distance of the nearest singularity of the integrand, which keeps
-// the Bernstein-ellipse parameter of each panel above 3.7 (error below 1e-20 with 20
-// nodes, 1e-9 with 8).
+// The number of equal panels is max(min_np, U / dpath) (capped at 64; min_np = 4 by
+// default): every panel is then no wider than the distance of the nearest
+// singularity of the integrand, which keeps the Bernstein-ellipse parameter of each
+// panel above 3.7 (error below 1e-20 with 20 nodes, 1e-9 with 8).
 // Nodes are placed from the upper limit down, x = (1+z) exp(-(U - u)): the integrands
 // grow with x, and measuring from the top keeps the rounding of the node abscissae
 // (absolute, ~eps times the distance from the anchor) smallest where the weight is.
 template <typename Q, bool PAIR>
-__device__ void gl_integral(const LaneConst<Q> &k, Q z, int power, bool grad, Q &val, Q gth[3]) {
+__device__ void gl_integral(const LaneConst<Q> &k, Q z, int power, bool grad, Q &val, Q gth[3], int min_np = kGlNp) {
     const Q U = Fp<Q>::log1p(z);
     const Q want = U * Fp<Q>::rcp(k.dpath);
-    const int np = want > Q(64) ? 64 : (want > Q(kGlNp) ? (int)__builtin_ceil((double)want) : kGlNp);
+    const int np = want > Q(64) ? 64 : (want > Q(min_np) ? (int)__builtin_ceil((double)want) : min_np);
     const Q h = U * Fp<Q>::rcp(Q(np));
     const Q x2 = Q(1) + z;
     Q s = Q(0), g0 = Q(0), g1 = Q(0), g2 = Q(0);

@@ -225,3 +225,78 @@ def test_config3_full_size_likelihood(dev):
     assert abs(l32 - l64) <= 5e-4 * abs(l64)
     assert np.max(np.abs(g32[:, :3] - g64[:, :3]) / np.maximum(np.abs(g64[:, :3]), 1e-3 * np.abs(g64[:, :3]).max())) < 1e-2
     assert np.max(np.abs(z32 - z64)) <= 1e-3 * np.max(np.abs(z64))
+
+
+def jac_check(kind, dt, params, z, shared, label, dev):
+    """Materialised Jacobian (cosmo_distance_jac) element by element against the
+    oracle's Leibniz-rule derivatives d out/d(H0, Om0, OL0, Or0, z)."""
+    p = torch.tensor(params, device=dev)
+    zt = torch.tensor(z, dtype=dt, device=dev)
+    val, jac = cosmo.cosmo_distance_jac(kind, p, zt)
+    zr = zt.double().cpu().numpy()
+    out, g = oracle.distance(kind, params, zr, shared_z=shared, grad=True)
+    jac = np.moveaxis(jac.double().cpu().numpy(), 0, -1)  # [c, z, 5]
+    undef = np.isnan(out)
+    assert np.array_equal(np.isnan(val.double().cpu().numpy()), undef), label
+    # per-element scale: the size of the derivative, floored at a small fraction of its
+    # row maximum (derivatives that cross zero along z), and for the sinn-transformed
+    # observables the conditioning term of ref_vjp for d/dz
+    gm = np.where(undef[..., None], 0.0, np.abs(g))
+    scale = np.maximum(gm, 1e-3 * gm.max(axis=1, keepdims=True))
+    if kind in ("DM", "DL", "DA", "MU"):
+        w = np.where(undef, 0.0, 1.0)
+        zfull = np.ascontiguousarray(np.broadcast_to(zr, out.shape)) if shared else zr
+        _, _, _, agz = ref_vjp(kind, params, zfull, w, False)
+        scale[..., 4] = np.maximum(scale[..., 4], agz)
+    e = np.where(undef[..., None], 0.0, np.abs(jac - g) / np.maximum(scale, 1e-300))
+    tol = np.array([TOL[dt]] * 3 + [5 * TOL[dt] if dt == torch.float32 else TOL[dt], TOL[dt]])
+    worst = e.reshape(-1, 5).max(0)
+    assert np.all(worst <= tol), f"{label} {kind} {dt} jac err per component {worst}"
+    return jac
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_jacobian_config2_subset(dev, dt):
+    params, z = workloads.config2(n_cosmo=12, n_z=160, seed=9)
+    for kind in KINDS:
+        jac_check(kind, dt, params, z, False, "config2-subset", dev)
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_jacobian_config4_families(dev, dt):
+    params, z, fam = workloads.config4(n_per_family=3, n_z=200, seed=17)
+    for kind in ("DC", "MU", "T", "X"):
+        jac_check(kind, dt, params, z, True, "config4", dev)
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_jacobian_sums_to_the_vjp(dev, dt):
+    """sum_z w jac equals the adjoint's output (the same lanes, contracted per lane in
+    FP64 instead of per cosmology)."""
+    params, z = workloads.config5(n_cosmo=6, n_z=5000)
+    p = torch.tensor(params, device=dev)
+    zt = torch.tensor(z, dtype=dt, device=dev)
+    w = torch.tensor(np.random.default_rng(12).normal(size=(6, 5000)), dtype=dt, device=dev)
+    for kind in ("MU", "T", "DA"):
+        val, jac = cosmo.cosmo_distance_jac(kind, p, zt)
+        v2, gp, gz = cosmo.cosmo_distance_vjp(kind, p, zt, w, want_value=True)
+        assert torch.equal(val, v2), kind
+        j = jac.double()
+        wd = w.double()
+        sgp = torch.stack([(j[q] * wd).sum(1) for q in range(4)], 1)
+        sc = torch.stack([(j[q] * wd).abs().sum(1) for q in range(4)], 1)
+        tol = 1e-12 if dt == torch.float64 else 2e-6
+        assert ((sgp - gp).abs() <= tol * sc).all(), (kind, ((sgp - gp).abs() / sc).max().item())
+        sgz = (j[4] * wd).sum(0)
+        assert ((sgz - gz.double()).abs() <= tol * (j[4] * wd).abs().sum(0) + 1e-30).all(), kind
+
+
+def test_jacobian_nan_rows_and_empty(dev):
+    params = np.array([[70.0, 0.05, 1.3, 0.0], [70.0, 0.3, 0.7, 9e-5]])
+    p = torch.tensor(params, device=dev)
+    zt = torch.tensor([0.5, 1.0, 2.0], dtype=torch.float64, device=dev)
+    val, jac = cosmo.cosmo_distance_jac("DL", p, zt)
+    assert torch.isnan(val[0]).all() and torch.isnan(jac[:, 0]).all()
+    assert torch.isfinite(val[1]).all() and torch.isfinite(jac[:, 1]).all()
+    val, jac = cosmo.cosmo_distance_jac("DL", p, torch.empty(0, dtype=torch.float64, device=dev))
+    assert jac.shape == (5, 2, 0)
