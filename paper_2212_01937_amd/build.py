@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "cosmo.hip")
 LIB = os.path.join(HERE, "libcosmo.so")
-DEPS = [os.path.join(HERE, "csrc", f) for f in ("cmath.hpp", "carlson.hpp", "setup.hpp", "lane.hpp", "cosmo.hip")] + [
+DEPS = [os.path.join(HERE, "csrc", f) for f in ("cmath.hpp", "carlson.hpp", "setup.hpp", "lane.hpp", "adjoint.hpp", "cosmo.hip")] + [
     os.path.join(ROOT, "include", "cosmo.h")]
 ARCH = os.environ.get("COSMO_OFFLOAD_ARCH", "gfx950")
 

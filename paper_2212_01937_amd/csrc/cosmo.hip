@@ -15,7 +15,7 @@
 #include <string.h>
 
 #include "../../include/cosmo.h"
-#include "lane.hpp"
+#include "adjoint.hpp"
 
 namespace cosmo {
 
@@ -104,119 +104,6 @@ __global__ __launch_bounds__(kBlock) void k_forward(const CosmoRec *__restrict__
 //   7..9 sum w dbase/d(Om, OL, Or)                                  (quadrature lanes).
 constexpr int kAcc = 10;
 
-__device__ __forceinline__ bool direct_mode(int kind, const CosmoRec &r, bool fp32) {
-    if (kind == COSMO_X) return true;
-    return r.minsep < (fp32 ? 2e-2 : 1e-4);
-}
-
-// Kept out of line: a rarely taken FP64 branch whose registers should not count
-// against the hot adjoint kernels.  Results come back by value (in registers): an
-// output array whose address escapes into the call would move the caller's
-// per-lane state to scratch memory.
-struct GlChi {
-    double chi, g0, g1, g2;
-};
-template <bool PAIR> __device__ __attribute__((noinline)) GlChi gl_chi_grad(const CosmoRec &r, double z) {
-    double chi, g[3];
-    gl_integral<double, PAIR>(r.d, z, 0, true, chi, g);
-    return GlChi{chi, g[0], g[1], g[2]};
-}
-
-// FP32 small-z lanes.  There the partials in the root parameters are O(z) while the
-// parameter derivatives they contract to are O(z^2) (E(0) = 1 for every theta), so
-// FP32 partials lose about eps_32 / z in the contraction.  Below kSmallZ32 the FP32
-// path takes the Leibniz-rule quadrature in the lane's precision instead, which has
-// no such cancellation; one 8-node panel suffices there (the panel is a fraction of
-// the distance to the nearest singularity of the integrand).
-constexpr float kSmallZ32 = 0.02f;
-
-// Derivatives of one (cosmology, redshift) lane.  The observable is out = F(base, Ok, z,
-// H0) with base = chi (D_C family), t (T) or X; s = dF/dbase.
-//   root mode:   p[0..4] = base and its partials in the root parameters (sigma,
-//                rho_0, rho_1 re/im for a pair or rho_1, rho_2), all at fixed beta:
-//                dbase/dtheta = -p0/(2 beta) dbeta/dtheta + sum p_k drho_k/dtheta;
-//   quadrature:  q[0..2] = dbase/d(Om, OL, Or) by Leibniz-rule quadrature (near-multiple
-//                roots and X: FP64 / lane precision; FP32 lanes at z < kSmallZ32).
-// dok = dF/dOk at fixed base (the curvature transform; dOk/dtheta = -1), dh = dF/dH0,
-// dz = dF/dz (fundamental theorem of calculus).
-template <typename T> struct LaneGrad {
-    T val, s, dok, dh, dz;
-    T p[5];
-    double q[3];
-    bool quad; // this lane's parameter partials are q (quadrature) rather than p
-};
-
-template <typename T, int KIND, bool PAIR>
-__device__ __forceinline__ void lane_grad(const CosmoRec &r, T z, LaneGrad<T> &o, bool &used_gl) {
-    const LaneConst<T> &k = lane_of<T>(r);
-    const bool fp32 = sizeof(T) == 4;
-    const T H0inv = k.hinv;
-    o.dok = T(0);
-    o.quad = false;
-    const bool small = fp32 && z < T(kSmallZ32);
-    if (KIND == COSMO_T && !direct_mode(KIND, r, fp32)) {
-        // time coordinate: Carlson derivatives (eqs. 2.10, 2.11) and the root chain
-        if (small) {
-            T tv, g[3];
-            gl_integral<T, PAIR>(k, z, 1, true, tv, g, 1);
-            o.p[0] = tv;
-            o.q[0] = g[0]; o.q[1] = g[1]; o.q[2] = g[2];
-            o.quad = true;
-        } else {
-            TGrad<T, PAIR> tg;
-            t_grad<T, PAIR>(r, z, tg);
-            o.p[0] = tg.t; o.p[1] = tg.dsig; o.p[2] = tg.dr0; o.p[3] = tg.dr1re; o.p[4] = PAIR ? tg.dr1im : tg.dr2;
-        }
-        o.s = k.th;
-        o.val = k.th * o.p[0];
-        o.dh = -o.val * H0inv;
-        o.dz = k.th * Fp<T>::rcp(T(1) + z) * iEz<T>(k, z);
-        return;
-    }
-    if (KIND == COSMO_T || KIND == COSMO_X) {
-        T qv, g[3];
-        gl_integral<T, PAIR>(k, z, KIND == COSMO_T ? 1 : 2, true, qv, g);
-        o.s = KIND == COSMO_T ? k.th : k.dh;
-        const T x = T(1) + z;
-        const T e = Ez<T>(k, z);
-        o.dz = o.s * (KIND == COSMO_T ? Fp<T>::rcp(x * e) : x * x * Fp<T>::rcp(e));
-        // the value (also needed for the H0 derivative) by the forward's route: for X
-        // in FP32 with radiation that route is this same quadrature
-        if (KIND == COSMO_X && sizeof(T) == 4 && k.sigma != T(0)) {
-            o.val = k.dh * qv;
-            used_gl = true;
-        } else {
-            o.val = KIND == COSMO_T ? k.th * t_hat<T, PAIR>(r, z) : k.dh * x_hat<T, PAIR>(k, z, used_gl);
-        }
-        o.q[0] = g[0]; o.q[1] = g[1]; o.q[2] = g[2];
-        o.quad = true;
-        o.dh = -o.val * H0inv;
-        return;
-    }
-    T dzz;
-    if (direct_mode(KIND, r, fp32)) {
-        // near-multiple roots: chi and its parameter gradient by FP64 quadrature
-        const GlChi gc = gl_chi_grad<PAIR>(r, (double)z);
-        o.q[0] = gc.g0; o.q[1] = gc.g1; o.q[2] = gc.g2;
-        o.quad = true;
-        o.val = observable<T>(KIND, k, T(gc.chi), z, H0inv, o.s, o.dok, dzz, o.dh);
-    } else {
-        if (small) {
-            T cv, g[3];
-            gl_integral<T, PAIR>(k, z, 0, true, cv, g, 1);
-            o.p[0] = cv;
-            o.q[0] = g[0]; o.q[1] = g[1]; o.q[2] = g[2];
-            o.quad = true;
-        } else {
-            ChiGrad<T, PAIR> cg;
-            chi_grad<T, PAIR>(k, z, cg);
-            o.p[0] = cg.chi; o.p[1] = cg.dsig; o.p[2] = cg.dr0; o.p[3] = cg.dr1re; o.p[4] = PAIR ? cg.dr1im : cg.dr2;
-        }
-        o.val = observable<T>(KIND, k, o.p[0], z, H0inv, o.s, o.dok, dzz, o.dh);
-    }
-    o.dz = dzz + o.s * iEz<T>(k, z);
-}
-
 // One lane of the adjoint: accumulates the cotangent-weighted partials into acc,
 // returns the z-gradient in gz and the observable in val (the quantity
 // cosmo_distance evaluates; used_gl flags the quadrature route of X).
@@ -249,16 +136,6 @@ __device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kA
     acc[6] += cot * o.dh;
 #pragma unroll
     for (int i = 0; i < 3; ++i) acc[7 + i] += e[i];
-}
-
-// Contraction of root-space partials with the root Jacobian (app. A), FP64:
-// d base / d theta for theta = (Om, OL, Or).  a[0..4] as LaneGrad::p (or their
-// cotangent-weighted sums).
-__device__ __forceinline__ double root_contract(const CosmoRec &r, const double a[5], int th) {
-    double v = -a[0] / (2.0 * r.beta) * r.dbeta[th] + a[1] * r.dsigma[th] + a[2] * r.drho_re[0][th];
-    if (r.pair) v += 2.0 * (a[3] * r.drho_re[1][th] - a[4] * r.drho_im[1][th]);
-    else v += a[3] * r.drho_re[1][th] + a[4] * r.drho_re[2][th];
-    return v;
 }
 
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
@@ -391,14 +268,31 @@ __global__ __launch_bounds__(kBlock) void k_jac(const CosmoRec *__restrict__ rec
             v = o.val;
             J[0] = o.dh;
             J[4] = o.dz;
-            double pd[5];
+            double d[3];
+            if (o.quad) {
 #pragma unroll
-            for (int q = 0; q < 5; ++q) pd[q] = o.quad ? 0.0 : (double)o.p[q];
+                for (int th = 0; th < 3; ++th) d[th] = o.q[th];
+            } else {
+                double pd[5];
 #pragma unroll
-            for (int th = 0; th < 3; ++th) {
-                const double d = o.quad ? o.q[th] : root_contract(r, pd, th);
-                J[1 + th] = T((double)o.s * d - (double)o.dok);
+                for (int q = 0; q < 5; ++q) pd[q] = (double)o.p[q];
+                bool bad = false;
+#pragma unroll
+                for (int th = 0; th < 3; ++th) {
+                    double mag;
+                    d[th] = root_contract(r, pd, th, &mag);
+                    bad = bad || !(mag <= kJacCancel32 * __builtin_fabs(d[th]));
+                }
+                if (sizeof(T) == 4 && bad && KIND != COSMO_X) {
+                    T bv, g[3];
+                    if (r.pair) gl_integral<T, true>(lane_of<T>(r), zz, KIND == COSMO_T ? 1 : 0, true, bv, g, 1);
+                    else gl_integral<T, false>(lane_of<T>(r), zz, KIND == COSMO_T ? 1 : 0, true, bv, g, 1);
+#pragma unroll
+                    for (int th = 0; th < 3; ++th) d[th] = g[th];
+                }
             }
+#pragma unroll
+            for (int th = 0; th < 3; ++th) J[1 + th] = T((double)o.s * d[th] - (double)o.dok);
         }
         const int64_t e = c * n_z + i;
         if (out) out[e] = v;

@@ -244,6 +244,25 @@ def jac_check(kind, dt, params, z, shared, label, dev):
     gm = np.where(undef[..., None], 0.0, np.abs(g))
     scale = np.maximum(gm, 1e-3 * gm.max(axis=1, keepdims=True))
     if kind in ("DM", "DL", "DA", "MU"):
+        # d out/dtheta = (d out/dchi)(dchi/dtheta) - d out/dOk: near a zero of the sum its
+        # error is set by the size of the two terms
+        zfull = np.ascontiguousarray(np.broadcast_to(zr, out.shape)) if shared else zr
+        dc, gdc = oracle.distance("DC", params, zfull, shared_z=False, grad=True)
+        dh = 299792.458 / params[:, :1]
+        ok = (1 - params[:, 1] - params[:, 2] - params[:, 3])[:, None]
+        chi = dc / dh
+        t = ok * chi ** 2
+        sk = np.sqrt(np.abs(ok))
+        with np.errstate(all="ignore"):
+            S = np.where(np.abs(t) < 1e-8, chi, np.where(ok < 0, np.sin(sk * chi), np.sinh(sk * chi)) / np.where(sk > 0, sk, 1))
+            C = np.where(ok < 0, np.cos(sk * chi), np.cosh(sk * chi))
+            dS = np.where(np.abs(t) < 1e-2, chi ** 3 / 6 + ok * chi ** 5 / 60 + ok ** 2 * chi ** 7 / 2520,
+                          (chi * C - S) / (2 * np.where(ok != 0, ok, 1)))
+            x = 1 + zfull
+            f = {"DM": (dh * C, dh * dS), "DL": (x * dh * C, x * dh * dS), "DA": (dh * C / x, dh * dS / x),
+                 "MU": (2.1714724095162591 * C / S, 2.1714724095162591 * dS / S)}[kind]
+        curv = np.abs(f[0][..., None] * gdc[..., 1:4] / dh[..., None]) + np.abs(f[1])[..., None]
+        scale[..., 1:4] = np.maximum(scale[..., 1:4], np.where(undef[..., None], 0.0, curv))
         w = np.where(undef, 0.0, 1.0)
         zfull = np.ascontiguousarray(np.broadcast_to(zr, out.shape)) if shared else zr
         _, _, _, agz = ref_vjp(kind, params, zfull, w, False)
