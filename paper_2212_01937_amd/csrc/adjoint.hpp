@@ -16,10 +16,14 @@ __device__ __forceinline__ bool direct_mode(int kind, const CosmoRec &r, bool fp
     return r.minsep < (fp32 ? 2e-2 : 1e-4);
 }
 
-// Kept out of line: a rarely taken FP64 branch whose registers should not count
-// against the hot adjoint kernels.  Results come back by value (in registers): an
-// output array whose address escapes into the call would move the caller's
-// per-lane state to scratch memory.
+// Near-multiple roots (direct mode): chi and its parameter gradient by quadrature in
+// the lane's precision (no cancellation on this route, so FP32 lanes keep FP32
+// accuracy).  The FP32 kernels inline the FP32 quadrature: an out-of-line call makes a
+// kernel reserve the callee's registers on every lane, which for the FP64 quadrature
+// would cost the FP32 adjoint two fifths of its occupancy.  The FP64 kernels keep the
+// quadrature out of line (their own register use is higher).  Results come back by
+// value: an output array whose address escapes into the call would move the
+// caller's per-lane state to scratch memory.
 struct GlChi {
     double chi, g0, g1, g2;
 };
@@ -103,10 +107,18 @@ __device__ __forceinline__ void lane_grad(const CosmoRec &r, T z, LaneGrad<T> &o
     T dzz;
     if (direct_mode(KIND, r, fp32)) {
         // near-multiple roots: chi and its parameter gradient by FP64 quadrature
-        const GlChi gc = gl_chi_grad<PAIR>(r, (double)z);
-        o.q[0] = gc.g0; o.q[1] = gc.g1; o.q[2] = gc.g2;
+        T chi;
+        if (fp32) {
+            T g[3];
+            gl_integral<T, PAIR>(k, z, 0, true, chi, g);
+            o.q[0] = g[0]; o.q[1] = g[1]; o.q[2] = g[2];
+        } else {
+            const GlChi gc = gl_chi_grad<PAIR>(r, (double)z);
+            chi = T(gc.chi);
+            o.q[0] = gc.g0; o.q[1] = gc.g1; o.q[2] = gc.g2;
+        }
         o.quad = true;
-        o.val = observable<T>(KIND, k, T(gc.chi), z, H0inv, o.s, o.dok, dzz, o.dh);
+        o.val = observable<T>(KIND, k, chi, z, H0inv, o.s, o.dok, dzz, o.dh);
     } else {
         if (small) {
             T cv, g[3];
