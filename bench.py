@@ -117,6 +117,7 @@ def main():
     ap.add_argument("--n-cosmo", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="f32,f64")
+    ap.add_argument("--skip-likelihood", action="store_true", help="skip the SN likelihood workload timing")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run one 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -188,6 +189,30 @@ def main():
         (g32, z32), (g64, z64) = grads["f32"], grads["f64"]
         results["f32"]["grad_params_max_rel_diff_vs_f64"] = float(np.max(np.abs(g32 - g64) / np.abs(g64).max(0)))
         results["f32"]["grad_z_max_rel_diff_vs_f64"] = float(np.max(np.abs(z32 - z64)) / np.max(np.abs(z64)))
+
+    # the SN Ia likelihood workload (64 parameter samples x 1e6 SNe, Or0 = 0): the fused
+    # Gaussian log-likelihood and its gradient per step; mock magnitudes from the FP64
+    # path at the fiducial cosmology plus the seeded noise
+    if not args.skip_likelihood:
+        fid, zs, noise, th = workloads.config3()
+        like = {}
+        for path in args.paths.split(","):
+            dt = torch.float32 if path == "f32" else torch.float64
+            zt3 = torch.tensor(zs, dtype=dt, device=dev)
+            mu_fid = cosmo.cosmo_distance("MU", torch.tensor(fid, device=dev), torch.tensor(zs, device=dev))[0]
+            obs = (mu_fid + torch.tensor(noise, device=dev)).to(dt)
+            pt = torch.tensor(th, device=dev)
+            ws3 = torch.empty(cosmo.workspace_size(pt.shape[0], zs.size), dtype=torch.uint8, device=dev)
+
+            def lstep():
+                return cosmo.cosmo_gaussian_loglike("MU", pt, zt3, obs, sigma=0.1, workspace=ws3)
+            for _ in range(args.warmup):
+                lstep()
+            lev, lwall, (ll, _, _) = timed(lstep, args.steps, stream, torch)
+            like[path] = {"ms_per_step": float(np.median(lev)), "evals_per_s": th.shape[0] * zs.size / (np.median(lev) * 1e-3),
+                          "loglike_c0": float(ll[0].item())}
+        results["config3_loglike"] = {"workload": f"Gaussian log-likelihood of {zs.size} SN magnitudes for "
+                                                  f"{th.shape[0]} parameter samples, value + gradient per step", **like}
 
     if args.copy_check:
         a = torch.empty(2 ** 28, dtype=torch.float32, device=dev)

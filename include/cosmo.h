@@ -140,6 +140,24 @@ int cosmo_distance_jac(cosmo_kind kind, cosmo_dtype dt, const double *params, in
                        const void *z, int64_t n_z, int64_t z_cosmo_stride, void *out, void *jac,
                        int32_t *info, void *workspace, size_t workspace_bytes, void *stream);
 
+/* cosmo_gaussian_loglike -- Gaussian log-likelihood of observed values of the
+ * observable (sec. 4: the SN Ia likelihood, mu with Gaussian magnitude errors) and
+ * its gradient, from one pass over the lanes:
+ *   loglike[c] = -1/2 sum_i ivar_ci (obs_ci - out_ci)^2,
+ * the gradient being that of cosmo_distance_vjp with the cotangent formed in each
+ * lane, cot_ci = wc[c] ivar_ci (obs_ci - out_ci).
+ * obs, ivar : dtype, laid out as z (element (c, i) at [c * z_cosmo_stride + i]: one
+ *             row shared by every cosmology when z_cosmo_stride == 0); ivar = 1/sigma^2.
+ * wc        : [n_cosmo] FP64 weights of the cosmologies in the gradient, nullable (1).
+ * loglike   : [n_cosmo] FP64 out, nullable (unweighted; NaN for cosmologies outside
+ *             the method and where out is undefined).
+ * grad_params, grad_z, info, workspace, workspace_bytes: as cosmo_distance_vjp.    */
+int cosmo_gaussian_loglike(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo,
+                           const void *z, int64_t n_z, int64_t z_cosmo_stride, const void *obs,
+                           const void *ivar, const double *wc, double *loglike, double *grad_params,
+                           void *grad_z, int32_t *info, void *workspace, size_t workspace_bytes,
+                           void *stream);
+
 /* Library version string (static storage). */
 const char *cosmo_version(void);
 

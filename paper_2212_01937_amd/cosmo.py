@@ -27,7 +27,8 @@ INFO = {"CUBIC": 0x1, "QUARTIC": 0x2, "THREE_REAL": 0x4, "YELLOW": 0x8, "RED": 0
 
 # every function declared in include/cosmo.h
 EXPORTS = ("cosmo_workspace_size", "cosmo_roots", "carlson_rf", "carlson_rd", "carlson_rj",
-           "carlson_rc", "cosmo_distance", "cosmo_distance_vjp", "cosmo_distance_jac", "cosmo_version")
+           "carlson_rc", "cosmo_distance", "cosmo_distance_vjp", "cosmo_distance_jac", "cosmo_gaussian_loglike",
+           "cosmo_version")
 
 _lib = None
 
@@ -57,6 +58,8 @@ def load():
                                        i32p, vp, ctypes.c_size_t, vp]
     lib.cosmo_distance_jac.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, i32p, vp,
                                        ctypes.c_size_t, vp]
+    lib.cosmo_gaussian_loglike.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, vp, vp, vp,
+                                           vp, i32p, vp, ctypes.c_size_t, vp]
     for n in EXPORTS[:-1]:
         getattr(lib, n).restype = ctypes.c_int
     lib.cosmo_version.restype = ctypes.c_char_p
@@ -231,6 +234,77 @@ def cosmo_distance_jac(kind, params, z, want_value=True, info=False, workspace=N
                                     _ptr(val), _ptr(jac), _ptr(inf), _ptr(ws), ws.numel(), _stream(p.device))
     _check(rc, "cosmo_distance_jac")
     return (val, jac, inf) if info else (val, jac)
+
+
+def cosmo_gaussian_loglike(kind, params, z, obs, sigma=None, ivar=None, weights=None, want_params=True,
+                           want_z=True, info=False, workspace=None):
+    """Fused Gaussian log-likelihood: loglike[c] = -1/2 sum_i (obs_i - out_ci)^2 / sigma_i^2
+    with its gradient (d/d(H0, Om0, OL0, Or0) per cosmology [n_cosmo, 4] float64, and
+    d/dz like cosmo_distance_vjp's grad_z), from one pass.  obs and sigma (or ivar =
+    1/sigma^2; a scalar broadcasts) are laid out as z; weights [n_cosmo] scale each
+    cosmology's term in the gradient.  Returns (loglike, grad_params, grad_z)."""
+    lib = load()
+    p = _params(params)
+    n_c = p.shape[0]
+    zc, n_z, stride, shared = _z_layout(z, n_c)
+    if (sigma is None) == (ivar is None):
+        raise CosmoError("give exactly one of sigma and ivar")
+    iv = ivar if ivar is not None else 1.0 / torch.as_tensor(sigma, device=p.device) ** 2
+    shape = zc.shape
+    ob = torch.as_tensor(obs, device=p.device).to(zc.dtype).expand(shape).contiguous()
+    iv = torch.as_tensor(iv, device=p.device).to(zc.dtype).expand(shape).contiguous()
+    wc = None
+    if weights is not None:
+        wc = torch.as_tensor(weights, dtype=torch.float64, device=p.device).reshape(n_c).contiguous()
+    ll = torch.empty(n_c, dtype=torch.float64, device=p.device)
+    gp = torch.empty((n_c, 4), dtype=torch.float64, device=p.device) if want_params else None
+    gz = None
+    if want_z:
+        gz = torch.empty(n_z if shared else (n_c, n_z), dtype=zc.dtype, device=p.device)
+    inf = torch.empty(n_c, dtype=torch.int32, device=p.device) if info else None
+    ws = workspace if workspace is not None else _workspace(n_c, n_z, p.device)
+    with torch.cuda.device(p.device):
+        rc = lib.cosmo_gaussian_loglike(KINDS[kind], DTYPES[zc.dtype], _ptr(p), n_c, _ptr(zc), n_z, stride,
+                                        _ptr(ob), _ptr(iv), _ptr(wc), _ptr(ll), _ptr(gp), _ptr(gz), _ptr(inf),
+                                        _ptr(ws), ws.numel(), _stream(p.device))
+    _check(rc, "cosmo_gaussian_loglike")
+    return (ll, gp, gz, inf) if info else (ll, gp, gz)
+
+
+class _GaussianLogLike(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, kind, params, z, obs, ivar):
+        need_p, need_z = ctx.needs_input_grad[1], ctx.needs_input_grad[2]
+        ll, gp, gz = cosmo_gaussian_loglike(kind, params.detach(), z.detach(), obs, ivar=ivar,
+                                            want_params=need_p, want_z=need_z)
+        ctx.kind = kind
+        ctx.save_for_backward(params, z, obs, ivar)
+        ctx.grads = (gp, gz)
+        return ll
+
+    @staticmethod
+    def backward(ctx, g):
+        params, z, obs, ivar = ctx.saved_tensors
+        gp, gz = ctx.grads
+        if bool((g == g[0]).all()):
+            # equal weights (e.g. loss = loglike.sum()): rescale the gradients of the forward pass
+            s = g[0]
+            gp = gp * s if gp is not None else None
+            gz = gz * s.to(gz.dtype) if gz is not None else None
+        else:
+            _, gp, gz = cosmo_gaussian_loglike(ctx.kind, params.detach(), z.detach(), obs, ivar=ivar, weights=g,
+                                               want_params=gp is not None, want_z=gz is not None)
+        if gz is not None:
+            gz = gz.reshape(z.shape)
+        return None, gp.reshape(params.shape) if gp is not None else None, gz, None, None
+
+
+def gaussian_loglike(kind, params, z, obs, sigma):
+    """Differentiable fused Gaussian log-likelihood per cosmology (see cosmo_gaussian_loglike)."""
+    zc = z.detach()
+    iv = (1.0 / torch.as_tensor(sigma, device=zc.device, dtype=torch.float64) ** 2).to(zc.dtype)
+    return _GaussianLogLike.apply(kind, params, z, torch.as_tensor(obs, device=zc.device).to(zc.dtype),
+                                  iv.expand(zc.shape[-1:] if zc.dim() == 1 else zc.shape).contiguous())
 
 
 class _Distance(torch.autograd.Function):

@@ -101,18 +101,30 @@ __global__ __launch_bounds__(kBlock) void k_forward(const CosmoRec *__restrict__
 //   0 sum w base, 1 sum w dbase/dsigma, 2 sum w dbase/drho0,
 //   3/4 sum w dbase/drho1 (re, im) [pair] or drho1, drho2 [real]   (root-chain lanes),
 //   5 sum cot dout/dOk, 6 sum cot dout/dH0,
-//   7..9 sum w dbase/d(Om, OL, Or)                                  (quadrature lanes).
-constexpr int kAcc = 10;
+//   7..9 sum w dbase/d(Om, OL, Or)                                  (quadrature lanes),
+//   10   sum -ivar (obs - out)^2 / 2                                (likelihood mode).
+constexpr int kAcc = 11;
+constexpr int kAccLoss = 10;
 
 // One lane of the adjoint: accumulates the cotangent-weighted partials into acc,
 // returns the z-gradient in gz and the observable in val (the quantity
 // cosmo_distance evaluates; used_gl flags the quadrature route of X).
-template <typename T, int KIND, bool PAIR>
-__device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cot, T acc[kAcc], T &gz, T &val,
+// LIKE (Gaussian likelihood): cin is the observed value, the residual res = obs - out
+// adds -ivar res^2 / 2 to the loss slot and the cotangent is wc ivar res;
+// otherwise cin is the cotangent.
+template <typename T, int KIND, bool PAIR, bool LIKE>
+__device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cin, T ivar, T wc, T acc[kAcc], T &gz, T &val,
                                          bool &used_gl) {
     LaneGrad<T> o;
     lane_grad<T, KIND, PAIR>(r, z, o, used_gl);
     val = o.val;
+    T cot = cin;
+    if (LIKE) {
+        const T res = cin - o.val;
+        const T rv = res * ivar;
+        acc[kAccLoss] += T(-0.5) * res * rv;
+        cot = wc * rv;
+    }
     gz = cot * o.dz;
     // increments formed per route, then added to every slot unconditionally (keeps
     // the accumulators in registers)
@@ -151,11 +163,11 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 // barrier).  The shared-z gradient is summed over the tile's cosmologies in
 // thread-private LDS slots (gzl[k][t]), which keeps the rolled k-loop free of
 // dynamically indexed register arrays.
-template <typename T, int KIND, bool PAIR, int ZPT>
+template <typename T, int KIND, bool PAIR, int ZPT, bool LIKE>
 __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T *__restrict__ z, int64_t n_z,
-                                          int64_t zstride, const T *__restrict__ cot, int64_t base,
-                                          T acc[kAcc], T *gzl, T *__restrict__ gz_out, T *__restrict__ out,
-                                          int32_t *__restrict__ info) {
+                                          int64_t zstride, const T *__restrict__ cot, const T *__restrict__ ivar,
+                                          T wc, int64_t base, T acc[kAcc], T *gzl, T *__restrict__ gz_out,
+                                          T *__restrict__ out, int32_t *__restrict__ info) {
 #pragma unroll 1
     for (int k = 0; k < ZPT; ++k) {
         const int64_t i = base + (int64_t)k * kBlock;
@@ -163,7 +175,8 @@ __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T 
         const T zz = z[c * zstride + i];
         T gz, val;
         bool used_gl = false;
-        vjp_lane<T, KIND, PAIR>(r, zz, cot[c * n_z + i], acc, gz, val, used_gl);
+        if (LIKE) vjp_lane<T, KIND, PAIR, true>(r, zz, cot[c * zstride + i], ivar[c * zstride + i], wc, acc, gz, val, used_gl);
+        else vjp_lane<T, KIND, PAIR, false>(r, zz, cot[c * n_z + i], T(0), T(0), acc, gz, val, used_gl);
         if (out) {
             out[c * n_z + i] = val;
             if (KIND == COSMO_X && info) {
@@ -186,10 +199,11 @@ template <typename T, int KIND> constexpr int adjoint_min_waves() {
     return (sizeof(T) == 4 && KIND != COSMO_T) ? 6 : 1;
 }
 
-template <typename T, int KIND, int ZPT>
+template <typename T, int KIND, int ZPT, bool LIKE>
 __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_vjp(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
                                                  const T *__restrict__ z, int64_t n_z, int64_t zstride,
-                                                 const T *__restrict__ cot, double *__restrict__ pacc,
+                                                 const T *__restrict__ cot, const T *__restrict__ ivar,
+                                                 const double *__restrict__ wcs, double *__restrict__ pacc,
                                                  T *__restrict__ gz_out, double *__restrict__ gz_part,
                                                  T *__restrict__ out, int32_t *__restrict__ info,
                                                  int ct, int64_t nzb) {
@@ -209,8 +223,9 @@ __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_vjp(
 #pragma unroll
         for (int s = 0; s < kAcc; ++s) acc[s] = T(0);
         if (r.valid) {
-            if (r.pair) vjp_cosmo<T, KIND, true, ZPT>(r, c, z, n_z, zstride, cot, base, acc, gzl, gz_out, out, info);
-            else vjp_cosmo<T, KIND, false, ZPT>(r, c, z, n_z, zstride, cot, base, acc, gzl, gz_out, out, info);
+            const T wc = LIKE ? (wcs ? T(wcs[c]) : T(1)) : T(0);
+            if (r.pair) vjp_cosmo<T, KIND, true, ZPT, LIKE>(r, c, z, n_z, zstride, cot, ivar, wc, base, acc, gzl, gz_out, out, info);
+            else vjp_cosmo<T, KIND, false, ZPT, LIKE>(r, c, z, n_z, zstride, cot, ivar, wc, base, acc, gzl, gz_out, out, info);
         } else {
             for (int k = 0; k < ZPT; ++k) {
                 const int64_t i = base + (int64_t)k * kBlock;
@@ -314,7 +329,8 @@ __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_jac(
 
 __global__ __launch_bounds__(kBlock) void k_finalize_params(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
                                                             const double *__restrict__ pacc, int64_t nwz,
-                                                            int kind, int fp32, double *__restrict__ grad) {
+                                                            int kind, int fp32, double *__restrict__ grad,
+                                                            double *__restrict__ loglike) {
     __shared__ double red[kBlock / 64][kAcc];
     const int64_t c = blockIdx.x;
     if (c >= n_cosmo) return;
@@ -338,6 +354,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize_params(const CosmoRec *__re
         for (int w2 = 0; w2 < kBlock / 64; ++w2) a[s] += red[w2][s];
     }
     const CosmoRec &r = recs[c];
+    if (loglike) loglike[c] = r.valid ? a[kAccLoss] : __builtin_nan("");
+    if (!grad) return;
     double *g = grad + 4 * c;
     if (!r.valid) {
         for (int q = 0; q < 4; ++q) g[q] = __builtin_nan("");
@@ -546,21 +564,29 @@ int launch_jac(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int6
 }
 
 template <typename T>
+// Adjoint launch.  Likelihood mode when ivar is given: cot then holds the observed
+// values (laid out as z), wc the per-cosmology weights (nullable) and loglike
+// receives the per-cosmology log-likelihood.
 int launch_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int64_t n_z, int64_t zstride,
-               const T *cot, T *out, double *grad_params, T *grad_z, int32_t *info, const WsLayout &L, char *ws,
-               hipStream_t s) {
+               const T *cot, const T *ivar, const double *wc, double *loglike, T *out, double *grad_params,
+               T *grad_z, int32_t *info, const WsLayout &L, char *ws, hipStream_t s) {
     const int zpt = vjp_zpt(n_z);
     Tiling t = tiling(n_cosmo, n_z, zpt);
-    double *pacc = grad_params ? (double *)(ws + L.pacc) : nullptr;
+    const bool like = ivar != nullptr;
+    double *pacc = (grad_params || loglike) ? (double *)(ws + L.pacc) : nullptr;
     double *gzp = (grad_z && zstride == 0 && t.ntile > 1) ? (double *)(ws + L.gzp) : nullptr;
     dim3 grid((unsigned)t.nblocks), block(kBlock);
+#define COSMO_VJP_Z(K, Z, LK)                                                                                   \
+    hipLaunchKernelGGL((k_vjp<T, K, Z, LK>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, cot, ivar, wc,  \
+                       pacc, grad_z, gzp, out, info, t.ct, t.nzb)
 #define COSMO_VJP(K)                                                                                            \
-    if (zpt == 8)                                                                                               \
-        hipLaunchKernelGGL((k_vjp<T, K, 8>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, cot, pacc,     \
-                           grad_z, gzp, out, info, t.ct, t.nzb);                                                \
-    else                                                                                                        \
-        hipLaunchKernelGGL((k_vjp<T, K, 1>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, cot, pacc,     \
-                           grad_z, gzp, out, info, t.ct, t.nzb)
+    if (like) {                                                                                                 \
+        if (zpt == 8) COSMO_VJP_Z(K, 8, true);                                                                  \
+        else COSMO_VJP_Z(K, 1, true);                                                                           \
+    } else {                                                                                                    \
+        if (zpt == 8) COSMO_VJP_Z(K, 8, false);                                                                 \
+        else COSMO_VJP_Z(K, 1, false);                                                                          \
+    }
     switch (kind) {
     case COSMO_DC: COSMO_VJP(COSMO_DC); break;
     case COSMO_DM: COSMO_VJP(COSMO_DM); break;
@@ -571,10 +597,11 @@ int launch_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int6
     case COSMO_DA: COSMO_VJP(COSMO_DA); break;
     }
 #undef COSMO_VJP
+#undef COSMO_VJP_Z
     if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
-    if (grad_params) {
+    if (pacc) {
         hipLaunchKernelGGL(k_finalize_params, dim3((unsigned)n_cosmo), dim3(kBlock), 0, s, recs, n_cosmo, pacc,
-                           t.nzb * (kBlock / 64), kind, (int)(sizeof(T) == 4), grad_params);
+                           t.nzb * (kBlock / 64), kind, (int)(sizeof(T) == 4), grad_params, loglike);
         if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
     }
     if (gzp) {
@@ -712,9 +739,11 @@ int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params, in
     if (rc != COSMO_OK) return rc;
     if (dt == COSMO_F32)
         return launch_vjp<float>(kind, recs, n_cosmo, (const float *)z, n_z, z_cosmo_stride, (const float *)cot,
-                                 (float *)out, grad_params, (float *)grad_z, info, L, (char *)ws.ptr, s);
+                                 nullptr, nullptr, nullptr, (float *)out, grad_params, (float *)grad_z, info, L,
+                                 (char *)ws.ptr, s);
     return launch_vjp<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, (const double *)cot,
-                              (double *)out, grad_params, (double *)grad_z, info, L, (char *)ws.ptr, s);
+                              nullptr, nullptr, nullptr, (double *)out, grad_params, (double *)grad_z, info, L,
+                              (char *)ws.ptr, s);
 }
 
 int cosmo_distance_jac(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo, const void *z,
@@ -742,6 +771,49 @@ int cosmo_distance_jac(cosmo_kind kind, cosmo_dtype dt, const double *params, in
                                  (float *)jac, info, s);
     return launch_jac<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, (double *)out,
                               (double *)jac, info, s);
+}
+
+int cosmo_gaussian_loglike(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo, const void *z,
+                           int64_t n_z, int64_t z_cosmo_stride, const void *obs, const void *ivar, const double *wc,
+                           double *loglike, double *grad_params, void *grad_z, int32_t *info, void *workspace,
+                           size_t workspace_bytes, void *stream) {
+    if (!valid_kind(kind)) return COSMO_E_KIND;
+    if (!valid_dtype(dt)) return COSMO_E_DTYPE;
+    if (n_cosmo < 0 || n_z < 0 || z_cosmo_stride < 0) return COSMO_E_ARG;
+    if (n_cosmo > 0 && !params) return COSMO_E_ARG;
+    if (n_cosmo > 0 && n_z > 0 && (!z || !obs || !ivar)) return COSMO_E_ARG;
+    if (check_grid(n_cosmo, n_z) != COSMO_OK) return COSMO_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_cosmo == 0 || n_z == 0) {
+        // empty sums: zero log-likelihoods and gradients (fill kernels, no memset)
+        if (n_cosmo > 0) {
+            unsigned nb = (unsigned)((4 * n_cosmo + kBlock - 1) / kBlock);
+            if (loglike) hipLaunchKernelGGL(k_fill_zero<double>, dim3(nb), dim3(kBlock), 0, s, loglike, n_cosmo);
+            if (grad_params) hipLaunchKernelGGL(k_fill_zero<double>, dim3(nb), dim3(kBlock), 0, s, grad_params, 4 * n_cosmo);
+        }
+        if (grad_z && n_z > 0 && z_cosmo_stride == 0) {
+            unsigned nb = (unsigned)((n_z + kBlock - 1) / kBlock);
+            if (dt == COSMO_F32) hipLaunchKernelGGL(k_fill_zero<float>, dim3(nb), dim3(kBlock), 0, s, (float *)grad_z, n_z);
+            else hipLaunchKernelGGL(k_fill_zero<double>, dim3(nb), dim3(kBlock), 0, s, (double *)grad_z, n_z);
+        }
+        return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
+    }
+    int rc = ensure_init();
+    if (rc != COSMO_OK) return rc;
+    WsLayout L = ws_layout(n_cosmo, n_z);
+    Workspace ws;
+    rc = ws.acquire(workspace, workspace_bytes, L.total, s);
+    if (rc != COSMO_OK) return rc;
+    CosmoRec *recs = (CosmoRec *)ws.ptr;
+    rc = launch_setup(params, n_cosmo, recs, info, s);
+    if (rc != COSMO_OK) return rc;
+    if (dt == COSMO_F32)
+        return launch_vjp<float>(kind, recs, n_cosmo, (const float *)z, n_z, z_cosmo_stride, (const float *)obs,
+                                 (const float *)ivar, wc, loglike, nullptr, grad_params, (float *)grad_z, info, L,
+                                 (char *)ws.ptr, s);
+    return launch_vjp<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, (const double *)obs,
+                              (const double *)ivar, wc, loglike, nullptr, grad_params, (double *)grad_z, info, L,
+                              (char *)ws.ptr, s);
 }
 
 } // extern "C"

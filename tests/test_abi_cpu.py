@@ -64,3 +64,19 @@ def test_workspace_size_monotone(lib):
     assert sz[0] > 0 and sz[0] <= sz[1] <= sz[2]
     b = ctypes.c_size_t(0)
     assert lib.cosmo_workspace_size(-1, 3, ctypes.byref(b)) == -1
+
+
+def test_loglike_and_jacobian_argument_errors(lib):
+    E_ARG, E_KIND = -1, -2
+    dummy = ctypes.c_void_p(0x1000)
+    null = None
+    assert lib.cosmo_gaussian_loglike(42, 1, dummy, 1, dummy, 1, 0, dummy, dummy, null, null, null, null, null,
+                                      null, 0, null) == E_KIND
+    # missing observations / inverse variances
+    assert lib.cosmo_gaussian_loglike(3, 1, dummy, 1, dummy, 1, 0, null, dummy, null, null, null, null, null,
+                                      null, 0, null) == E_ARG
+    assert lib.cosmo_gaussian_loglike(3, 1, dummy, 1, dummy, 1, 0, dummy, null, null, null, null, null, null,
+                                      null, 0, null) == E_ARG
+    # missing Jacobian buffer
+    assert lib.cosmo_distance_jac(0, 1, dummy, 1, dummy, 1, 0, null, null, null, null, 0, null) == E_ARG
+    assert lib.cosmo_distance_jac(0, 1, dummy, -1, dummy, 1, 0, null, dummy, null, null, 0, null) == E_ARG

@@ -319,3 +319,68 @@ def test_jacobian_nan_rows_and_empty(dev):
     assert torch.isfinite(val[1]).all() and torch.isfinite(jac[:, 1]).all()
     val, jac = cosmo.cosmo_distance_jac("DL", p, torch.empty(0, dtype=torch.float64, device=dev))
     assert jac.shape == (5, 2, 0)
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_gaussian_loglike_config3_small(dev, dt):
+    """Fused Gaussian log-likelihood of mock SN magnitudes (sec. 4) and its gradient
+    against the oracle's mu and Leibniz-rule derivatives."""
+    fid, zs, noise, th = workloads.config3(n_sn=3000, n_samples=8, seed=4)
+    mu_obs = oracle.distance("MU", fid, zs)[0] + noise
+    p = torch.tensor(th, device=dev)
+    zt = torch.tensor(zs, dtype=dt, device=dev)
+    ll, gp, gz = cosmo.cosmo_gaussian_loglike("MU", p, zt, torch.tensor(mu_obs, device=dev), sigma=0.1)
+    zr = zt.double().cpu().numpy()
+    ref_mu, g = oracle.distance("MU", th, zr, grad=True)
+    obs = torch.tensor(mu_obs, dtype=dt).double().numpy()
+    r = (obs[None, :] - ref_mu) / 0.1 ** 2
+    ref_ll = -0.5 * (r * (obs[None, :] - ref_mu)).sum(1)
+    tol_ll = 1e-10 if dt == torch.float64 else 1e-5
+    assert np.all(np.abs(ll.cpu().numpy() - ref_ll) <= tol_ll * np.abs(ref_ll)), (ll, ref_ll)
+    rgp = np.einsum("cz,czk->ck", r, g[..., :4])
+    sp = np.einsum("cz,czk->ck", np.abs(r), np.abs(g[..., :4]))
+    ep = np.abs(gp.cpu().numpy() - rgp) / sp
+    assert ep[:, :3].max() <= TOL[dt] * 10, ep
+    rgz = (r * g[..., 4]).sum(0)
+    sz = np.abs(r * g[..., 4]).sum(0)
+    ez = np.abs(gz.double().cpu().numpy() - rgz) / sz
+    assert ez.max() <= TOL[dt] * 10, ez.max()
+
+
+def test_gaussian_loglike_matches_composition(dev):
+    """FP64: the fused likelihood equals cosmo_distance + the loss in torch + the adjoint,
+    with per-cosmology weights in the gradient and per-SN errors; also through the
+    autograd wrapper."""
+    fid, zs, noise, th = workloads.config3(n_sn=2000, n_samples=5, seed=8)
+    mu_obs = torch.tensor(oracle.distance("MU", fid, zs)[0] + noise, device=dev)
+    sig = torch.tensor(0.08 + 0.05 * np.random.default_rng(1).random(zs.size), device=dev)
+    p = torch.tensor(th, device=dev, requires_grad=True)
+    zt = torch.tensor(zs, device=dev, requires_grad=True)
+    wts = torch.tensor([1.0, 0.5, -2.0, 3.0, 0.25], device=dev)
+    mu = cosmo.distance("MU", p, zt)
+    ll_c = (-(mu_obs[None, :] - mu) ** 2 / (2 * sig[None, :] ** 2)).sum(1)
+    (ll_c * wts).sum().backward()
+    ll, gp, gz = cosmo.cosmo_gaussian_loglike("MU", p.detach(), zt.detach(), mu_obs, sigma=sig, weights=wts)
+    assert torch.allclose(ll, ll_c.detach(), rtol=1e-12, atol=0)
+    assert torch.allclose(gp, p.grad, rtol=1e-10, atol=1e-10 * p.grad.abs().max().item())
+    assert torch.allclose(gz, zt.grad, rtol=1e-10, atol=1e-10 * zt.grad.abs().max().item())
+    # autograd wrapper, non-uniform upstream gradient (recomputed with weights)
+    p2 = p.detach().clone().requires_grad_(True)
+    z2 = zt.detach().clone().requires_grad_(True)
+    (cosmo.gaussian_loglike("MU", p2, z2, mu_obs, sig) * wts).sum().backward()
+    assert torch.allclose(p2.grad, gp, rtol=1e-12, atol=0) and torch.allclose(z2.grad, gz, rtol=1e-12, atol=0)
+    # uniform upstream gradient (rescaled forward gradients)
+    p3 = p.detach().clone().requires_grad_(True)
+    (3.0 * cosmo.gaussian_loglike("MU", p3, zt.detach(), mu_obs, sig)).sum().backward()
+    _, gp1, _ = cosmo.cosmo_gaussian_loglike("MU", p.detach(), zt.detach(), mu_obs, sigma=sig)
+    assert torch.allclose(p3.grad, 3.0 * gp1, rtol=1e-14, atol=0)
+
+
+def test_gaussian_loglike_edge_cases(dev):
+    f64 = dict(dtype=torch.float64, device=dev)
+    p = torch.tensor([[70.0, 0.3, 0.7, 0.0], [70.0, 0.05, 1.3, 0.0]], **f64)  # second: no Big Bang
+    z = torch.tensor([0.1, 0.5, 1.0], **f64)
+    ll, gp, gz = cosmo.cosmo_gaussian_loglike("MU", p, z, torch.full((3,), 40.0, **f64), sigma=0.1)
+    assert torch.isfinite(ll[0]) and torch.isnan(ll[1]) and torch.isnan(gp[1]).all() and torch.isfinite(gp[0]).all()
+    ll, gp, gz = cosmo.cosmo_gaussian_loglike("MU", p[:1], torch.empty(0, **f64), torch.empty(0, **f64), sigma=0.1)
+    assert torch.all(ll == 0) and torch.all(gp == 0) and gz.shape == (0,)
