@@ -249,7 +249,7 @@ def cosmo_gaussian_loglike(kind, params, z, obs, sigma=None, ivar=None, weights=
     zc, n_z, stride, shared = _z_layout(z, n_c)
     if (sigma is None) == (ivar is None):
         raise CosmoError("give exactly one of sigma and ivar")
-    iv = ivar if ivar is not None else 1.0 / torch.as_tensor(sigma, device=p.device) ** 2
+    iv = ivar if ivar is not None else 1.0 / torch.as_tensor(sigma, dtype=torch.float64, device=p.device) ** 2
     shape = zc.shape
     ob = torch.as_tensor(obs, device=p.device).to(zc.dtype).expand(shape).contiguous()
     iv = torch.as_tensor(iv, device=p.device).to(zc.dtype).expand(shape).contiguous()
