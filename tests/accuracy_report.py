@@ -1,0 +1,107 @@
+"""Accuracy report (run by hand on a GPU machine; not collected by pytest): the
+maximum and median errors of every output against the oracle on each workload,
+for the FP64 and the FP32 path.
+
+    python tests/accuracy_report.py [--out report.md]
+
+Relative errors for D_C, D_M, T, X; mu as absolute magnitudes.  Workloads 1, 2
+and 4 in full; the large workloads 3 and 5 on 1e6 seeded (cosmology, z) pairs of
+the full-size launch.  For the FP32 path the oracle is evaluated at the redshifts
+rounded to FP32 (the errors are those of the path, not of the input rounding).
+"""
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import torch  # noqa: E402
+
+import oracle  # noqa: E402
+from paper_2212_01937_amd import cosmo, workloads  # noqa: E402
+
+KINDS = ["DC", "DM", "T", "X", "MU"]
+
+
+def errors(kind, got, ref, finite_ref):
+    got = np.asarray(got, dtype=np.float64)[finite_ref]
+    ref = np.asarray(ref, dtype=np.float64)[finite_ref]
+    if kind == "MU":
+        return np.abs(got - ref)
+    return np.abs(got - ref) / np.abs(ref)
+
+
+def full(label, params, z, shared, dev, rows):
+    p = torch.tensor(params, device=dev)
+    for dt, name in ((torch.float64, "FP64"), (torch.float32, "FP32")):
+        zt = torch.tensor(z, dtype=dt, device=dev)
+        zr = zt.double().cpu().numpy()
+        cells = []
+        for kind in KINDS:
+            out = cosmo.cosmo_distance(kind, p, zt).double().cpu().numpy()
+            ref = oracle.distance(kind, params, zr, shared_z=shared)
+            fin = np.isfinite(ref)
+            e = errors(kind, out, ref, fin)
+            cells.append((e.max(), np.median(e)))
+        rows.append((label, name, int(np.prod(out.shape)), cells))
+        print(label, name, cells, flush=True)
+
+
+def sampled(label, params, z, dev, rows, n=10 ** 6, seed=31):
+    p = torch.tensor(params, device=dev)
+    ci, zi = workloads.subsample(params.shape[0], z.shape[0], n, seed=seed)
+    order = np.argsort(ci, kind="stable")
+    ci, zi = ci[order], zi[order]
+    for dt, name in ((torch.float64, "FP64"), (torch.float32, "FP32")):
+        zt = torch.tensor(z, dtype=dt, device=dev)
+        zr = zt.double().cpu().numpy()
+        cells = []
+        for kind in KINDS:
+            out = cosmo.cosmo_distance(kind, p, zt)
+            got = out[torch.tensor(ci, device=dev), torch.tensor(zi, device=dev)].double().cpu().numpy()
+            del out
+            ref = np.empty(n)
+            for c in np.unique(ci):
+                m = ci == c
+                ref[m] = oracle.distance(kind, params[c:c + 1], zr[zi[m]])[0]
+            fin = np.isfinite(ref)
+            e = errors(kind, got, ref, fin)
+            cells.append((e.max(), np.median(e)))
+        rows.append((label + f" ({n} sampled pairs)", name, n, cells))
+        print(label, name, cells, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+    dev = torch.device("cuda:0")
+    rows = []
+    t0 = time.time()
+    p1, z1 = workloads.config1()
+    full("1: flat LCDM+radiation, 1 x 1000", p1, z1, True, dev, rows)
+    p2, z2 = workloads.config2()
+    full("2: non-flat, 4096 x 1024", p2, z2, False, dev, rows)
+    p4, z4, _ = workloads.config4()
+    full("4: near-degenerate, 1024 x 4096", p4, z4, True, dev, rows)
+    _, z3, _, th3 = workloads.config3()
+    sampled("3: SN likelihood cosmologies, 64 x 1e6", th3, z3, dev, rows)
+    p5, z5 = workloads.config5()
+    sampled("5: large batch, 256 x 1e6", p5, z5, dev, rows)
+    lines = ["| workload | path | evals | " + " | ".join(f"{k} max / median" for k in KINDS) + " |",
+             "|---|---|---|" + "---|" * len(KINDS)]
+    for label, name, n, cells in rows:
+        lines.append(f"| {label} | {name} | {n} | " + " | ".join(f"{a:.1e} / {b:.1e}" for a, b in cells) + " |")
+    text = "\n".join(lines) + f"\n\n(relative errors; MU in mag; {time.time() - t0:.0f} s)\n"
+    print(text)
+    if args.out:
+        with open(args.out, "w") as fh:
+            fh.write(text)
+
+
+if __name__ == "__main__":
+    main()
