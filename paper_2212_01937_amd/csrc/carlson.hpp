@@ -368,10 +368,15 @@ __device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
     const T AF0 = mean3<T, PAIR>(x, a, b);
     const T x0 = x, a0 = a, b0 = b;
     const T QF = spread3<T, PAIR>(AF0, x, a, b);
-    // The R_D means (3 A_F + 2 x_k)/5 deviate from the arguments by at most 1.4 QF.
+    // Stopping: R_F's criterion.  The R_D means (3 A_F + 2 x_k)/5 deviate from the
+    // arguments by at most 1.4 QF, so at that point the R_D tails run at deviations up
+    // to 1.4 tau7 (0.19 FP32, 0.017 FP64), where their truncation, ~(1.4 tau7)^6 / 10,
+    // is 5e-6 (FP32) / 2.4e-12 (FP64) relative.  The R_D values enter only derivatives,
+    // whose accuracy targets (1e-4 FP32, 1e-10 FP64) this meets; the R_F value keeps
+    // its own tolerance.
     T AF = AF0, f = T(1), accz = T(0);
     cx<T> accy = mkc(T(0), T(0));
-    for (int m = 0; m < kMaxDup && T(1.4) * QF * f > Fp<T>::tau5 * Fp<T>::abs(AF); ++m) {
+    for (int m = 0; m < kMaxDup && QF * f > Fp<T>::tau7 * Fp<T>::abs(AF); ++m) {
         T sx = Fp<T>::sqrt(x);
         T lam;
         if (PAIR) {

@@ -4,9 +4,10 @@ for the FP64 and the FP32 path.
 
     python tests/accuracy_report.py [--out report.md]
 
-Relative errors for D_C, D_M, T, X; mu as absolute magnitudes.  Workloads 1, 2
-and 4 in full; the large workloads 3 and 5 on 1e6 seeded (cosmology, z) pairs of
-the full-size launch.  For the FP32 path the oracle is evaluated at the redshifts
+Relative errors for D_C, T, X; D_M relative to its conditioning scale (it crosses
+zero beyond the antipode of a closed universe); mu in magnitudes, per the same
+conditioning.  Workloads 1, 2 and 4 in full; the large workloads 3 and 5 on 1e6
+seeded (cosmology, z) pairs of the full-size launch.  For the FP32 path the oracle is evaluated at the redshifts
 rounded to FP32 (the errors are those of the path, not of the input rounding).
 """
 import argparse
@@ -24,15 +25,25 @@ import torch  # noqa: E402
 import oracle  # noqa: E402
 from paper_2212_01937_amd import cosmo, workloads  # noqa: E402
 
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from test_gpu_forward import cond_scale  # noqa: E402
+
 KINDS = ["DC", "DM", "T", "X", "MU"]
 
 
-def errors(kind, got, ref, finite_ref):
-    got = np.asarray(got, dtype=np.float64)[finite_ref]
-    ref = np.asarray(ref, dtype=np.float64)[finite_ref]
-    if kind == "MU":
-        return np.abs(got - ref)
-    return np.abs(got - ref) / np.abs(ref)
+def errors(kind, got, ref, finite_ref, params=None, z=None):
+    """Relative error (D_C, T, X), for D_M relative to the conditioning scale |D_M| +
+    |dD_M/dchi| chi (D_M crosses zero beyond the antipode of a closed universe, where a
+    relative error of chi moves it by that much), and for mu in mag, divided by
+    1 + |C chi / S| (the same conditioning in units of 5/ln 10)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    if kind in ("DM", "MU"):
+        with np.errstate(invalid="ignore"):
+            e = np.abs(got - ref) / cond_scale(kind, params, z, ref)
+    else:
+        e = np.abs(got - ref) / np.abs(ref)
+    return e[finite_ref]
 
 
 def full(label, params, z, shared, dev, rows):
@@ -45,7 +56,7 @@ def full(label, params, z, shared, dev, rows):
             out = cosmo.cosmo_distance(kind, p, zt).double().cpu().numpy()
             ref = oracle.distance(kind, params, zr, shared_z=shared)
             fin = np.isfinite(ref)
-            e = errors(kind, out, ref, fin)
+            e = errors(kind, out, ref, fin, params, zr)
             cells.append((e.max(), np.median(e)))
         rows.append((label, name, int(np.prod(out.shape)), cells))
         print(label, name, cells, flush=True)
@@ -69,7 +80,7 @@ def sampled(label, params, z, dev, rows, n=10 ** 6, seed=31):
                 m = ci == c
                 ref[m] = oracle.distance(kind, params[c:c + 1], zr[zi[m]])[0]
             fin = np.isfinite(ref)
-            e = errors(kind, got, ref, fin)
+            e = errors(kind, got, ref, fin, params[ci], zr[zi][:, None])
             cells.append((e.max(), np.median(e)))
         rows.append((label + f" ({n} sampled pairs)", name, n, cells))
         print(label, name, cells, flush=True)
@@ -96,7 +107,8 @@ def main():
              "|---|---|---|" + "---|" * len(KINDS)]
     for label, name, n, cells in rows:
         lines.append(f"| {label} | {name} | {n} | " + " | ".join(f"{a:.1e} / {b:.1e}" for a, b in cells) + " |")
-    text = "\n".join(lines) + f"\n\n(relative errors; MU in mag; {time.time() - t0:.0f} s)\n"
+    text = "\n".join(lines) + (f"\n\n(relative errors; D_M relative to |D_M| + |dD_M/dchi| chi; MU in mag per "
+                                f"1 + |C chi / S|; {time.time() - t0:.0f} s)\n")
     print(text)
     if args.out:
         with open(args.out, "w") as fh:
