@@ -118,6 +118,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="f32,f64")
     ap.add_argument("--skip-likelihood", action="store_true", help="skip the SN likelihood workload timing")
+    ap.add_argument("--skip-workloads", action="store_true", help="skip the timing of the other workloads")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run one 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -213,6 +214,38 @@ def main():
                           "loglike_c0": float(ll[0].item())}
         results["config3_loglike"] = {"workload": f"Gaussian log-likelihood of {zs.size} SN magnitudes for "
                                                   f"{th.shape[0]} parameter samples, value + gradient per step", **like}
+
+    # the other workloads, forward and value + gradient per call (gradient of the sum of
+    # the output with a unit cotangent), each output kind the workload names
+    if not args.skip_workloads:
+        others = {}
+        gen_o = torch.Generator(device=dev)
+        for name, (pp, zz, kinds) in {
+                "config1_flat_1x1000": (*workloads.config1(), ("DC", "DL", "MU")),
+                "config2_nonflat_4096x1024": (*workloads.config2(), ("DC", "DM", "T", "X")),
+                "config4_neardegenerate_1024x4096": (*workloads.config4()[:2], ("DC", "DM", "T", "X"))}.items():
+            rec = {"evals": int(pp.shape[0] * zz.shape[-1])}
+            pt = torch.tensor(pp, device=dev)
+            for path in args.paths.split(","):
+                dt = torch.float32 if path == "f32" else torch.float64
+                zt_o = torch.tensor(zz, dtype=dt, device=dev)
+                gen_o.manual_seed(7)
+                w_o = torch.randn((pp.shape[0], zz.shape[-1]), dtype=torch.float64, device=dev, generator=gen_o).to(dt)
+                ws_o = torch.empty(cosmo.workspace_size(pp.shape[0], zz.shape[-1]), dtype=torch.uint8, device=dev)
+                for kind in kinds:
+                    def f1():
+                        return cosmo.cosmo_distance(kind, pt, zt_o, workspace=ws_o)
+
+                    def f2():
+                        return cosmo.cosmo_distance_vjp(kind, pt, zt_o, w_o, want_value=True, workspace=ws_o)
+                    f1()
+                    f2()
+                    e1, _, _ = timed(f1, 10, stream, torch)
+                    e2, _, _ = timed(f2, 10, stream, torch)
+                    rec[f"{path}_{kind}_fwd_evals_per_s"] = rec["evals"] / (np.median(e1) * 1e-3)
+                    rec[f"{path}_{kind}_fwd_grad_evals_per_s"] = rec["evals"] / (np.median(e2) * 1e-3)
+            others[name] = rec
+        results["other_workloads"] = others
 
     if args.copy_check:
         a = torch.empty(2 ** 28, dtype=torch.float32, device=dev)
