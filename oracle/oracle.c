@@ -136,13 +136,14 @@ static double E2_of_x(const struct cosmo *c, double x)
 
 /* Partial derivative of E^2 with respect to parameter a (1: Om, 2: OL, 3: Or) with
  * Ok = 1 - Om - OL - Or eliminated, i.e. dE2/dOm = x^3 - x^2, dE2/dOL = 1 - x^2,
- * dE2/dOr = x^4 - x^2. */
-static double dE2_dparam(int a, double x)
+ * dE2/dOr = x^4 - x^2.  Each has the factor x - 1, passed in as xm1 = expm1(u) so
+ * that the differences do not cancel near x = 1 (low z). */
+static double dE2_dparam(int a, double x, double xm1)
 {
     switch (a) {
-    case 1: return x * x * x - x * x;
-    case 2: return 1.0 - x * x;
-    case 3: return x * x * x * x - x * x;
+    case 1: return x * x * xm1;
+    case 2: return -xm1 * (x + 1.0);
+    case 3: return x * x * xm1 * (x + 1.0);
     }
     return 0.0;
 }
@@ -167,7 +168,7 @@ static double dist_integrand(double u, const void *vctx)
     double e = sqrt(e2);
     double g = pow(x, integrand_power(k->which)) * x; /* (1+z)^p * dz/du */
     if (k->dparam == 0) return g / e;
-    return -0.5 * g * dE2_dparam(k->dparam, x) / (e2 * e);
+    return -0.5 * g * dE2_dparam(k->dparam, x, expm1(u)) / (e2 * e);
 }
 
 static const double EPSREL = 1e-14;
