@@ -7,7 +7,9 @@
 // the normalised deviations X_i = (A_0 - x_i) 4^-m / A_m (taken from the
 // initial arguments, which avoids the rounding of the iterated ones).  The
 // expansions used are the seventh-order one for R_F and R_C and the
-// fifth-order one for R_D and R_J (DLMF 19.36.1-2).
+// fifth-order one for R_D and R_J (DLMF 19.36.1-2); where a structured routine
+// needs R_D next to R_F from one sequence, the R_D tails are the derivatives of
+// the R_F expansion (rfd_tails).
 //
 // Two families:
 //  * general complex (rf_c, rd_c, rj_c, rc_c) -- the C-ABI carlson_* entry points;
@@ -33,6 +35,11 @@ template <typename T> __device__ __forceinline__ cx<T> rf_tail(cx<T> E2, cx<T> E
     cx<T> b = (E2 * a) + T(-0.1);
     cx<T> c = (E3 * T(3.0 / 104.0)) - (E2 * T(3.0 / 44.0)) + (E2 * E2 * T(1.0 / 16.0)) + T(1.0 / 14.0);
     return (E2 * b) + (E3 * c) + T(1);
+}
+// Partial derivatives of rf_tail in E2 and E3.
+template <typename T> __device__ __forceinline__ void rf_tail_grad(T E2, T E3, T &t2, T &t3) {
+    t2 = T(-0.1) + E2 * (T(1.0 / 12.0) - T(15.0 / 208.0) * E2) + E3 * (T(-3.0 / 44.0) + T(0.125) * E2);
+    t3 = T(1.0 / 14.0) + T(3.0 / 52.0) * E3 + E2 * (T(-3.0 / 44.0) + T(1.0 / 16.0) * E2);
 }
 // 1 - 3E2/14 + E3/6 + 9E2^2/88 - 3E4/22 - 9E2E3/52 + 3E5/26
 template <typename T> __device__ __forceinline__ T rj_tail(T E2, T E3, T E4, T E5) {
@@ -363,18 +370,53 @@ template <typename T, bool PAIR> __device__ T rd_last_x(T x, T a, T b) {
 // rdx is not accumulated: it follows from the cyclic identity
 // R_D(x,y,z) + R_D(y,z,x) + R_D(z,x,y) = 3/sqrt(xyz) (DLMF 19.21.7), whose terms are
 // of one size on these argument triples (cancellation below a factor 5).
+// End of a structured duplication sequence for R_F and the three R_D(., ., x_k):
+// R_F from its seventh-order expansion about the final mean A, and the R_D tails
+// 4^-m R_D(x_m, y_m, z_m; last x_k) from the derivative of that same expansion
+// through dR_F/dx_k = -R_D(., ., x_k)/6 (eq. 2.10).  With X_k = 1 - x_k/A
+// (sum 0), E2, E3 their symmetric functions, P_k the product of the two
+// deviations other than X_k, T(E2, E3) the expansion and T2, T3 its partials:
+//   dE2/dx_k = (X_k - 2E2/3)/A,  dE3/dx_k = (E2/3 - E3 - P_k)/A,
+//   R_D(., ., x_k) = A^(-3/2) [T - 6 T2 (X_k - 2E2/3) - 6 T3 (E2/3 - E3 - P_k)].
+// At R_F's stopping deviation (tau7: 0.136 FP32, 0.0121 FP64) the truncation of
+// this derivative is below 4e-7 (FP32) / 2e-14 (FP64) relative.
+// Outputs: rf; tx, ty (PAIR: complex, last argument y = a + i b), tz (not PAIR).
+template <typename T, bool PAIR>
+__device__ __forceinline__ void rfd_tails(T AF0, T x0, T a0, T b0, T AF, T f, T &rf, T &tx, cx<T> &ty, T &tz) {
+    const T g = f * Fp<T>::rcp(AF);
+    const T X = (AF0 - x0) * g;
+    T s, q;
+    yz_sym<T, PAIR>(AF0, a0, b0, g, s, q);
+    const T E2 = q - X * X, E3 = X * q;
+    const T tF = rf_tail(E2, E3);
+    const T ra = Fp<T>::rsqrt(AF);
+    rf = tF * ra;
+    T t2, t3;
+    rf_tail_grad(E2, E3, t2, t3);
+    const T sc = g * ra; // 4^-m A^(-3/2)
+    const T c0 = tF + E2 * (T(4) * t2 - T(2) * t3) + T(6) * t3 * E3;
+    const T m2 = T(-6) * t2, m3 = T(6) * t3;
+    tx = sc * (c0 + m2 * X + m3 * q); // P_x = Y Z = q
+    if (PAIR) {
+        // Y = u - i v, Z = conj(Y); P_y = X Z
+        const T u = (AF0 - a0) * g, v = b0 * g;
+        ty = mkc(sc * (c0 + u * (m2 + m3 * X)), sc * v * (m3 * X - m2));
+        tz = T(0);
+    } else {
+        const T Y = (AF0 - a0) * g, Z = (AF0 - b0) * g;
+        ty = mkc(sc * (c0 + m2 * Y + m3 * X * Z), T(0));
+        tz = sc * (c0 + m2 * Z + m3 * X * Y);
+    }
+}
+
 template <typename T, bool PAIR>
 __device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
     const T AF0 = mean3<T, PAIR>(x, a, b);
     const T x0 = x, a0 = a, b0 = b;
     const T QF = spread3<T, PAIR>(AF0, x, a, b);
-    // Stopping: R_F's criterion.  The R_D means (3 A_F + 2 x_k)/5 deviate from the
-    // arguments by at most 1.4 QF, so at that point the R_D tails run at deviations up
-    // to 1.4 tau7 (0.19 FP32, 0.017 FP64), where their truncation, ~(1.4 tau7)^6 / 10,
-    // is 5e-6 (FP32) / 2.4e-12 (FP64) relative.  The R_D values enter only derivatives,
-    // whose accuracy targets (1e-4 FP32, 1e-10 FP64) this meets; the R_F value keeps
-    // its own tolerance.
-    T AF = AF0, f = T(1), accz = T(0);
+    // One duplication sequence, stopped on R_F's criterion; each R_D(., ., x_k) is
+    // 3 sum_m 4^-m / (sqrt(x_k,m) (x_k,m + lambda_m)) plus the tail of rfd_tails.
+    T AF = AF0, f = T(1), accx = T(0), accz = T(0);
     cx<T> accy = mkc(T(0), T(0));
     for (int m = 0; m < kMaxDup && QF * f > Fp<T>::tau7 * Fp<T>::abs(AF); ++m) {
         T sx = Fp<T>::sqrt(x);
@@ -390,52 +432,19 @@ __device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
             accy.re += f * Fp<T>::rcp(sy * (a + lam));
             accz += f * Fp<T>::rcp(sz * (b + lam));
         }
+        accx += f * Fp<T>::rcp(sx * (x + lam));
         x = (x + lam) * T(0.25);
         a = (a + lam) * T(0.25);
         b = PAIR ? b * T(0.25) : (b + lam) * T(0.25);
         AF = (AF + lam) * T(0.25);
         f *= T(0.25);
     }
-    {
-        T g = f * Fp<T>::rcp(AF);
-        T X = (AF0 - x0) * g, s, q;
-        yz_sym<T, PAIR>(AF0, a0, b0, g, s, q);
-        rf = rf_tail(q - X * X, X * q) * Fp<T>::rsqrt(AF);
-    }
-    if (PAIR) {
-        // R_D(x, z, y) with y = a + i b last, z = conj(y)
-        cx<T> y0 = mkc(a0, b0), y = mkc(a, b);
-        cx<T> A0 = (y0 * T(2) + T(3) * AF0) * T(0.2), A = (y * T(2) + T(3) * AF) * T(0.2);
-        cx<T> g = crcp(A) * f;
-        cx<T> X = (A0 - x0) * g, Y = (A0 - conj(y0)) * g;
-        cx<T> Z = (X + Y) * T(-1.0 / 3.0);
-        cx<T> XY = X * Y, Z2 = Z * Z;
-        cx<T> E2 = XY - Z2 * T(6), E3 = (XY * T(3) - Z2 * T(8)) * Z;
-        cx<T> E4 = (XY - Z2) * Z2 * T(3), E5 = XY * Z2 * Z;
-        rdy = rj_tail(E2, E3, E4, E5) * crcp(A * csqrt(A)) * f + accy * T(3);
-        rdz = T(0);
-        // 3/sqrt(x y conj(y)) = 3 / (sqrt(x) |y|)
-        rdx = T(3) * Fp<T>::rsqrt(x0) * Fp<T>::rsqrt(a0 * a0 + b0 * b0) - T(2) * rdy.re;
-    } else {
-        // R_D(x, z, y) and R_D(x, y, z)
-        T A0 = (T(3) * AF0 + T(2) * a0) * T(0.2), A = (T(3) * AF + T(2) * a) * T(0.2);
-        T g = f * Fp<T>::rcp(A);
-        T X = (A0 - x0) * g, Y = (A0 - b0) * g, Z = (X + Y) * T(-1.0 / 3.0);
-        T XY = X * Y, Z2 = Z * Z;
-        rdy = mkc(rj_tail(XY - T(6) * Z2, (T(3) * XY - T(8) * Z2) * Z, T(3) * (XY - Z2) * Z2, XY * Z2 * Z) *
-                          f * Fp<T>::rcp(A) * Fp<T>::rsqrt(A) + T(3) * accy.re, T(0));
-        A0 = (T(3) * AF0 + T(2) * b0) * T(0.2);
-        A = (T(3) * AF + T(2) * b) * T(0.2);
-        g = f * Fp<T>::rcp(A);
-        X = (A0 - x0) * g;
-        Y = (A0 - a0) * g;
-        Z = (X + Y) * T(-1.0 / 3.0);
-        XY = X * Y;
-        Z2 = Z * Z;
-        rdz = rj_tail(XY - T(6) * Z2, (T(3) * XY - T(8) * Z2) * Z, T(3) * (XY - Z2) * Z2, XY * Z2 * Z) *
-                  f * Fp<T>::rcp(A) * Fp<T>::rsqrt(A) + T(3) * accz;
-        rdx = T(3) * Fp<T>::rsqrt(x0 * a0 * b0) - rdy.re - rdz;
-    }
+    T tx, tz;
+    cx<T> ty;
+    rfd_tails<T, PAIR>(AF0, x0, a0, b0, AF, f, rf, tx, ty, tz);
+    rdx = T(3) * accx + tx;
+    rdy = accy * T(3) + ty;
+    rdz = T(3) * accz + tz;
 }
 
 // R_F, R_J(x, y, z, p) and the R_D(., ., x_k) of the triple, from one duplication
@@ -449,9 +458,9 @@ __device__ void rfjd_s(T x, T a, T b, T p, T &rf, T &rj, T &rdx, cx<T> &rdy, T &
     const T QF = spread3<T, PAIR>(AF0, x, a, b);
     const T QJ = tmax(spread3<T, PAIR>(AJ0, x, a, b), Fp<T>::abs(AJ0 - p));
     const T delta = PAIR ? (p - x) * ((p - a) * (p - a) + b * b) : (p - x) * (p - a) * (p - b);
-    T AF = AF0, AJ = AJ0, f = T(1), acc = T(0), accz = T(0);
+    T AF = AF0, AJ = AJ0, f = T(1), acc = T(0), accx = T(0), accz = T(0);
     cx<T> accy = mkc(T(0), T(0));
-    for (int m = 0; m < kMaxDup && (T(1.4) * QF * f > Fp<T>::tau5 * Fp<T>::abs(AF) ||
+    for (int m = 0; m < kMaxDup && (QF * f > Fp<T>::tau7 * Fp<T>::abs(AF) ||
                                    QJ * f > Fp<T>::tau5 * Fp<T>::abs(AJ)); ++m) {
         T sx = Fp<T>::sqrt(x), sp = Fp<T>::sqrt(p);
         T lam, d;
@@ -468,6 +477,7 @@ __device__ void rfjd_s(T x, T a, T b, T p, T &rf, T &rj, T &rdx, cx<T> &rdy, T &
             accy.re += f * Fp<T>::rcp(sy * (a + lam));
             accz += f * Fp<T>::rcp(sz * (b + lam));
         }
+        accx += f * Fp<T>::rcp(sx * (x + lam));
         T rdd = Fp<T>::rcp(d);
         acc += f * rc1_r(delta * rdd * rdd * (f * f * f)) * rdd;
         x = (x + lam) * T(0.25);
@@ -478,12 +488,12 @@ __device__ void rfjd_s(T x, T a, T b, T p, T &rf, T &rj, T &rdx, cx<T> &rdy, T &
         AJ = (AJ + lam) * T(0.25);
         f *= T(0.25);
     }
-    {
-        T g = f * Fp<T>::rcp(AF);
-        T X = (AF0 - x0) * g, s, q;
-        yz_sym<T, PAIR>(AF0, a0, b0, g, s, q);
-        rf = rf_tail(q - X * X, X * q) * Fp<T>::rsqrt(AF);
-    }
+    T tx, tz;
+    cx<T> ty;
+    rfd_tails<T, PAIR>(AF0, x0, a0, b0, AF, f, rf, tx, ty, tz);
+    rdx = T(3) * accx + tx;
+    rdy = accy * T(3) + ty;
+    rdz = T(3) * accz + tz;
     {
         T g = f * Fp<T>::rcp(AJ);
         T X = (AJ0 - x0) * g, s, q;
@@ -495,37 +505,6 @@ __device__ void rfjd_s(T x, T a, T b, T p, T &rf, T &rj, T &rdx, cx<T> &rdy, T &
         T E4 = (T(2) * xyz + E2 * P + T(3) * P2 * P) * P;
         T E5 = xyz * P2;
         rj = rj_tail(E2, E3, E4, E5) * f * Fp<T>::rcp(AJ) * Fp<T>::rsqrt(AJ) + T(6) * acc;
-    }
-    if (PAIR) {
-        cx<T> y0 = mkc(a0, b0), y = mkc(a, b);
-        cx<T> A0 = (y0 * T(2) + T(3) * AF0) * T(0.2), A = (y * T(2) + T(3) * AF) * T(0.2);
-        cx<T> g = crcp(A) * f;
-        cx<T> X = (A0 - x0) * g, Y = (A0 - conj(y0)) * g;
-        cx<T> Z = (X + Y) * T(-1.0 / 3.0);
-        cx<T> XY = X * Y, Z2 = Z * Z;
-        cx<T> E2 = XY - Z2 * T(6), E3 = (XY * T(3) - Z2 * T(8)) * Z;
-        cx<T> E4 = (XY - Z2) * Z2 * T(3), E5 = XY * Z2 * Z;
-        rdy = rj_tail(E2, E3, E4, E5) * crcp(A * csqrt(A)) * f + accy * T(3);
-        rdz = T(0);
-        rdx = T(3) * Fp<T>::rsqrt(x0) * Fp<T>::rsqrt(a0 * a0 + b0 * b0) - T(2) * rdy.re;
-    } else {
-        T A0 = (T(3) * AF0 + T(2) * a0) * T(0.2), A = (T(3) * AF + T(2) * a) * T(0.2);
-        T g = f * Fp<T>::rcp(A);
-        T X = (A0 - x0) * g, Y = (A0 - b0) * g, Z = (X + Y) * T(-1.0 / 3.0);
-        T XY = X * Y, Z2 = Z * Z;
-        rdy = mkc(rj_tail(XY - T(6) * Z2, (T(3) * XY - T(8) * Z2) * Z, T(3) * (XY - Z2) * Z2, XY * Z2 * Z) *
-                          f * Fp<T>::rcp(A) * Fp<T>::rsqrt(A) + T(3) * accy.re, T(0));
-        A0 = (T(3) * AF0 + T(2) * b0) * T(0.2);
-        A = (T(3) * AF + T(2) * b) * T(0.2);
-        g = f * Fp<T>::rcp(A);
-        X = (A0 - x0) * g;
-        Y = (A0 - a0) * g;
-        Z = (X + Y) * T(-1.0 / 3.0);
-        XY = X * Y;
-        Z2 = Z * Z;
-        rdz = rj_tail(XY - T(6) * Z2, (T(3) * XY - T(8) * Z2) * Z, T(3) * (XY - Z2) * Z2, XY * Z2 * Z) *
-                  f * Fp<T>::rcp(A) * Fp<T>::rsqrt(A) + T(3) * accz;
-        rdx = T(3) * Fp<T>::rsqrt(x0 * a0 * b0) - rdy.re - rdz;
     }
     if (!(p0 > T(0))) rj = Fp<T>::nan();
 }

@@ -26,3 +26,22 @@ extern "C" void host_eval(const double *prm, int kind, int dt, const double *z, 
         else out[i] = r.pair ? one<double, true>(r, kind, z[i]) : one<double, false>(r, kind, z[i]);
     }
 }
+
+// Structured R_F and R_D(., ., x_k) from one duplication sequence (rfd_s), for a
+// triple (x, a, b): pair != 0 -> (x, a + i b, a - i b), else (x, a, b).
+// out: rf, rdx, rdy.re, rdy.im, rdz.  dt: 0 FP32, 1 FP64.
+extern "C" void host_rfd(int dt, int pair, double x, double a, double b, double *out) {
+    if (dt == 0) {
+        float rf, rdx, rdz;
+        cx<float> rdy;
+        if (pair) rfd_s<float, true>((float)x, (float)a, (float)b, rf, rdx, rdy, rdz);
+        else rfd_s<float, false>((float)x, (float)a, (float)b, rf, rdx, rdy, rdz);
+        out[0] = rf; out[1] = rdx; out[2] = rdy.re; out[3] = rdy.im; out[4] = rdz;
+    } else {
+        double rf, rdx, rdz;
+        cx<double> rdy;
+        if (pair) rfd_s<double, true>(x, a, b, rf, rdx, rdy, rdz);
+        else rfd_s<double, false>(x, a, b, rf, rdx, rdy, rdz);
+        out[0] = rf; out[1] = rdx; out[2] = rdy.re; out[3] = rdy.im; out[4] = rdz;
+    }
+}

@@ -78,3 +78,51 @@ def test_fp32_formulas_within_bound(libs, kind, model):
             got = host_eval(libs[model], p[c], kind, 0, z32[c])
             e = np.abs(got / ref - 1)
             assert e.max() <= 1e-6, (label, kind, model, c, e.max(), z32[c][np.argmax(e)])
+
+
+def _triples(rng, n):
+    """Structured Carlson triples like the distance kernels': x > 0 with a
+    conjugate pair (a +- i b, any sign of a, b != 0) or two more positive reals;
+    magnitudes over four decades, so that the duplication runs from zero to many
+    steps."""
+    for _ in range(n):
+        pair = bool(rng.random() < 0.5)
+        x = 10.0 ** rng.uniform(-2, 2)
+        if pair:
+            r, th = 10.0 ** rng.uniform(-2, 2), rng.uniform(-0.95, 0.95) * np.pi
+            yield pair, x, r * np.cos(th), r * np.sin(th)
+        else:
+            yield pair, x, 10.0 ** rng.uniform(-2, 2), 10.0 ** rng.uniform(-2, 2)
+
+
+@pytest.mark.parametrize("model", ["exact", "noisy"])
+def test_structured_rf_rd_match_oracle(libs, model):
+    """rfd_s: R_F and the three R_D(., ., x_k) of one duplication sequence (the R_D
+    tails from the derivative of the R_F expansion, eq. 2.10) against the oracle's
+    quadrature of the defining integrals (eqs. 2.6, 2.9), FP64 and FP32 (the oracle
+    at the FP32-rounded arguments), plus the identity sum_k R_D(., ., x_k) =
+    3 / sqrt(x y z)."""
+    rng = np.random.default_rng(7)
+    worst = {0: 0.0, 1: 0.0}
+    for pair, x, a, b in _triples(rng, 300):
+        for dt, tol in ((1, 1e-13), (0, 2e-6 if model == "exact" else 4e-6)):
+            if dt == 0:
+                x, a, b = (float(np.float32(v)) for v in (x, a, b))
+            y, zc = (complex(a, b), complex(a, -b)) if pair else (complex(a), complex(b))
+            out = np.zeros(5)
+            libs[model].host_rfd(dt, int(pair), ctypes.c_double(x), ctypes.c_double(a), ctypes.c_double(b),
+                                 out.ctypes.data_as(ctypes.c_void_p))
+            rf = oracle.carlson("RF", x, y, zc)[0]
+            rdx = oracle.carlson("RD", y, zc, x)[0]
+            rdy = oracle.carlson("RD", x, zc, y)[0]
+            rdz = oracle.carlson("RD", x, y, zc)[0]
+            got_rdy = complex(out[2], out[3])
+            got_rdz = np.conj(got_rdy) if pair else complex(out[4])
+            errs = [abs(out[0] - rf) / abs(rf), abs(out[1] - rdx) / abs(rdx), abs(got_rdy - rdy) / abs(rdy),
+                    abs(got_rdz - rdz) / abs(rdz)]
+            assert max(errs) <= tol, (dt, pair, x, a, b, errs)
+            ident = 3.0 / np.sqrt(complex(x) * y * zc)
+            s = out[1] + got_rdy + got_rdz
+            assert abs(s - ident) <= 10 * tol * (abs(out[1]) + abs(got_rdy) + abs(got_rdz)), (dt, pair, x, a, b)
+            worst[dt] = max(worst[dt], max(errs))
+    print("max relative error", worst)
