@@ -150,10 +150,39 @@ __device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cin, T ivar, 
     for (int i = 0; i < 3; ++i) acc[7 + i] += e[i];
 }
 
+// Sum over the 64 lanes of a wave (all lanes active), with DPP lane moves instead of
+// LDS permutes: quad permutes (lane ^ 1, lane ^ 2) and row rotations by 4 and 8 leave
+// every lane with its 16-lane row sum; row broadcast 15 (into rows 1 and 3) and 31
+// (into rows 2 and 3) carry the row sums up, so lane 63 holds the total, which is
+// returned to every lane.  Lanes a move does not write receive zero.
+template <int CTRL, int ROWS> __device__ __forceinline__ uint32_t dpp_move(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS> __device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, dpp_move<CTRL, ROWS>(__builtin_bit_cast(uint32_t, v)));
+}
+template <int CTRL, int ROWS> __device__ __forceinline__ double dpp_move(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = dpp_move<CTRL, ROWS>((uint32_t)b), hi = dpp_move<CTRL, ROWS>((uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+__device__ __forceinline__ float lane63(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ double lane63(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+    return __builtin_bit_cast(double, (hi << 32) | lo);
+}
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_move<0xB1, 0xF>(v);  // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E, 0xF>(v);  // quad_perm [2,3,0,1]
+    v += dpp_move<0x124, 0xF>(v); // row_ror:4
+    v += dpp_move<0x128, 0xF>(v); // row_ror:8
+    v += dpp_move<0x142, 0xA>(v); // row_bcast:15
+    v += dpp_move<0x143, 0xC>(v); // row_bcast:31
+    return lane63(v);
 }
 
 // Redshifts per lane of the adjoint: lane t of z-block zb handles
