@@ -270,7 +270,10 @@ __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_vjp(
         if (pacc) {
 #pragma unroll
             for (int s = 0; s < kAcc; ++s) {
-                T v = wave_sum(acc[s]);
+                // slots no lane of the wave touched (the loss outside likelihood mode,
+                // the quadrature slots away from small z) skip the reduction
+                T v = T(0);
+                if (__ballot(acc[s] != T(0))) v = wave_sum(acc[s]);
                 if (lane == 0) pacc[(c * nwz + gw) * kAcc + s] = (double)v;
             }
         }
