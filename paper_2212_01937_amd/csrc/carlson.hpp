@@ -243,13 +243,21 @@ template <typename T, bool PAIR> __device__ __forceinline__ T mean3(T x, T a, T 
     return PAIR ? (x + T(2) * a) * T(1.0 / 3.0) : (x + a + b) * T(1.0 / 3.0);
 }
 
-// max_i |A0 - x_i| for a structured triple
+// Spread of a structured triple about A0, in the measure the duplication tests
+// compare: max_i |A0 - x_i| (not PAIR), or its square (PAIR: no square root).
 template <typename T, bool PAIR> __device__ __forceinline__ T spread3(T A0, T x, T a, T b) {
     if (PAIR) {
         T dx = A0 - x, da = A0 - a;
-        return Fp<T>::sqrt(tmax(dx * dx, da * da + b * b));
+        return tmax(dx * dx, da * da + b * b);
     }
     return tmax(tmax(Fp<T>::abs(A0 - x), Fp<T>::abs(A0 - a)), Fp<T>::abs(A0 - b));
+}
+// |d| in the same measure
+template <typename T, bool PAIR> __device__ __forceinline__ T spread1(T d) { return PAIR ? d * d : Fp<T>::abs(d); }
+// Duplication test: is the spread Q of the initial arguments, scaled by f = 4^-m,
+// still above tau |A| (A the current mean)?
+template <typename T, bool PAIR> __device__ __forceinline__ bool spread_above(T Q, T f, T tau, T A) {
+    return PAIR ? Q * (f * f) > (tau * tau) * (A * A) : Q * f > tau * Fp<T>::abs(A);
 }
 
 // Symmetric functions of the deviations of (y, z) about A0, scaled by g:
@@ -272,7 +280,7 @@ template <typename T, bool PAIR> __device__ T rf_s(T x, T a, T b) {
     const T x0 = x, a0 = a, b0 = b;
     const T Q = spread3<T, PAIR>(A0, x, a, b);
     T A = A0, f = T(1);
-    for (int m = 0; m < kMaxDup && Q * f > Fp<T>::tau7 * Fp<T>::abs(A); ++m) {
+    for (int m = 0; m < kMaxDup && spread_above<T, PAIR>(Q, f, Fp<T>::tau7, A); ++m) {
         T sx, syr, sya, sz;
         T lam = dup_lambda<T, PAIR>(x, a, b, sx, syr, sya, sz);
         x = (x + lam) * T(0.25);
@@ -296,11 +304,11 @@ __device__ void rfj_s(T x, T a, T b, T p, T &rf, T &rj) {
     const T AJ0 = (T(3) * AF0 + T(2) * p) * T(0.2);
     const T x0 = x, a0 = a, b0 = b, p0 = p;
     const T QF = spread3<T, PAIR>(AF0, x, a, b);
-    const T QJ = tmax(spread3<T, PAIR>(AJ0, x, a, b), Fp<T>::abs(AJ0 - p));
+    const T QJ = tmax(spread3<T, PAIR>(AJ0, x, a, b), spread1<T, PAIR>(AJ0 - p));
     T delta = PAIR ? (p - x) * ((p - a) * (p - a) + b * b) : (p - x) * (p - a) * (p - b);
     T AF = AF0, AJ = AJ0, f = T(1), acc = T(0);
-    for (int m = 0; m < kMaxDup && (QF * f > Fp<T>::tau7 * Fp<T>::abs(AF) ||
-                                   QJ * f > Fp<T>::tau5 * Fp<T>::abs(AJ)); ++m) {
+    for (int m = 0; m < kMaxDup && (spread_above<T, PAIR>(QF, f, Fp<T>::tau7, AF) ||
+                                   spread_above<T, PAIR>(QJ, f, Fp<T>::tau5, AJ)); ++m) {
         T sx, syr, sya, sz;
         T lam = dup_lambda<T, PAIR>(x, a, b, sx, syr, sya, sz);
         T sp = Fp<T>::sqrt(p);
@@ -343,7 +351,7 @@ template <typename T, bool PAIR> __device__ T rd_last_x(T x, T a, T b) {
     const T a0 = a, b0 = b;
     const T Q = spread3<T, PAIR>(A0, x, a, b);
     T A = A0, f = T(1), acc = T(0);
-    for (int m = 0; m < kMaxDup && Q * f > Fp<T>::tau5 * Fp<T>::abs(A); ++m) {
+    for (int m = 0; m < kMaxDup && spread_above<T, PAIR>(Q, f, Fp<T>::tau5, A); ++m) {
         T sx, syr, sya, sz;
         T lam = dup_lambda<T, PAIR>(x, a, b, sx, syr, sya, sz);
         acc += f * Fp<T>::rcp(sx * (x + lam));
@@ -418,7 +426,7 @@ __device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
     // 3 sum_m 4^-m / (sqrt(x_k,m) (x_k,m + lambda_m)) plus the tail of rfd_tails.
     T AF = AF0, f = T(1), accx = T(0), accz = T(0);
     cx<T> accy = mkc(T(0), T(0));
-    for (int m = 0; m < kMaxDup && QF * f > Fp<T>::tau7 * Fp<T>::abs(AF); ++m) {
+    for (int m = 0; m < kMaxDup && spread_above<T, PAIR>(QF, f, Fp<T>::tau7, AF); ++m) {
         T sx = Fp<T>::sqrt(x);
         T lam;
         if (PAIR) {
@@ -456,12 +464,12 @@ __device__ void rfjd_s(T x, T a, T b, T p, T &rf, T &rj, T &rdx, cx<T> &rdy, T &
     const T AJ0 = (T(3) * AF0 + T(2) * p) * T(0.2);
     const T x0 = x, a0 = a, b0 = b, p0 = p;
     const T QF = spread3<T, PAIR>(AF0, x, a, b);
-    const T QJ = tmax(spread3<T, PAIR>(AJ0, x, a, b), Fp<T>::abs(AJ0 - p));
+    const T QJ = tmax(spread3<T, PAIR>(AJ0, x, a, b), spread1<T, PAIR>(AJ0 - p));
     const T delta = PAIR ? (p - x) * ((p - a) * (p - a) + b * b) : (p - x) * (p - a) * (p - b);
     T AF = AF0, AJ = AJ0, f = T(1), acc = T(0), accx = T(0), accz = T(0);
     cx<T> accy = mkc(T(0), T(0));
-    for (int m = 0; m < kMaxDup && (QF * f > Fp<T>::tau7 * Fp<T>::abs(AF) ||
-                                   QJ * f > Fp<T>::tau5 * Fp<T>::abs(AJ)); ++m) {
+    for (int m = 0; m < kMaxDup && (spread_above<T, PAIR>(QF, f, Fp<T>::tau7, AF) ||
+                                   spread_above<T, PAIR>(QJ, f, Fp<T>::tau5, AJ)); ++m) {
         T sx = Fp<T>::sqrt(x), sp = Fp<T>::sqrt(p);
         T lam, d;
         if (PAIR) {

@@ -115,6 +115,22 @@ template <typename T> __device__ __forceinline__ cx<T> csqrt(cx<T> w, T &absw) {
     res.im = pos ? (w.im >= T(0) ? small : -small) : (w.im >= T(0) ? big : -big);
     return res;
 }
+// As csqrt, with |w| and 1/|w| from one reciprocal square root of |w|^2.
+template <typename T> __device__ __forceinline__ cx<T> csqrt_inv(cx<T> w, T &absw, T &iabsw) {
+    const T n = norm2(w);
+    const T ir = Fp<T>::rsqrt(n);
+    const T r = n * ir;
+    absw = r;
+    iabsw = ir;
+    bool pos = w.re >= T(0);
+    T t = T(0.5) * (r + Fp<T>::abs(w.re));
+    T q = (t > T(0)) ? Fp<T>::rsqrt(t) : T(0);
+    T big = t * q, small = T(0.5) * Fp<T>::abs(w.im) * q;
+    cx<T> res;
+    res.re = pos ? big : small;
+    res.im = pos ? (w.im >= T(0) ? small : -small) : (w.im >= T(0) ? big : -big);
+    return res;
+}
 template <typename T> __device__ __forceinline__ cx<T> csqrt(cx<T> w) {
     T r;
     return csqrt(w, r);

@@ -40,17 +40,37 @@ template <typename T, bool PAIR> struct Geo {
     T T1_1re, T1_1im, T2_1re, T2_1im; // same for U_1 (PAIR) ; REAL: T1_1re, T2_1re
     T T1_2, T2_2;          // REAL only
     T va, vb;              // structured second/third Carlson arguments
+    // INV builds only: 1/Xt^2, 1/X_0^2 and 1/X_1^2 (PAIR: complex; REAL: also 1/X_2^2)
+    T iXt2, iX02, iX1re, iX1im, iX2;
 };
 
-template <typename T, bool PAIR>
+// INV: the square roots come from reciprocal square roots (s = v rsqrt(v)), which
+// also give the reciprocals 1/v the adjoint's chain needs, one transcendental per
+// root instead of two.
+template <typename T, bool PAIR, bool INV = false>
 __device__ __forceinline__ void build_u(const LaneConst<T> &k, T z, Geo<T, PAIR> &g) {
     g.Xt2 = k.yt2 - k.sigma * z; // 1 - sigma (1 + z)
-    g.Xt = Fp<T>::sqrt(g.Xt2);
     g.X02 = z + k.w0;
-    g.X0 = Fp<T>::sqrt(g.X02);
+    if (INV) {
+        const T rt = Fp<T>::rsqrt(g.Xt2), r0 = Fp<T>::rsqrt(g.X02);
+        g.Xt = g.Xt2 * rt; g.iXt2 = rt * rt;
+        g.X0 = g.X02 * r0; g.iX02 = r0 * r0;
+    } else {
+        g.Xt = Fp<T>::sqrt(g.Xt2);
+        g.X0 = Fp<T>::sqrt(g.X02);
+    }
     if (PAIR) {
         T ab;
-        cx<T> X1 = csqrt(mkc(z + k.w1re, k.w1im), ab);
+        const cx<T> w1 = mkc(z + k.w1re, k.w1im);
+        cx<T> X1;
+        if (INV) {
+            T iab;
+            X1 = csqrt_inv(w1, ab, iab);
+            const T i2 = iab * iab;
+            g.iX1re = w1.re * i2; g.iX1im = -w1.im * i2;
+        } else {
+            X1 = csqrt(w1, ab);
+        }
         g.X1re = X1.re; g.X1im = X1.im; g.X1abs = ab;
         // U_0 = Xt X_0 |Y_1|^2 + Yt Y_0 |X_1|^2
         g.T1_0 = g.Xt * g.X0 * k.y1abs2;
@@ -66,8 +86,15 @@ __device__ __forceinline__ void build_u(const LaneConst<T> &k, T z, Geo<T, PAIR>
         g.va = g.U1re * g.U1re - g.U1im * g.U1im;
         g.vb = T(2) * g.U1re * g.U1im;
     } else {
-        g.X1re = Fp<T>::sqrt(z + k.w1re);
-        g.X2 = Fp<T>::sqrt(z + k.w2);
+        const T v1 = z + k.w1re, v2 = z + k.w2;
+        if (INV) {
+            const T r1 = Fp<T>::rsqrt(v1), r2 = Fp<T>::rsqrt(v2);
+            g.X1re = v1 * r1; g.iX1re = r1 * r1;
+            g.X2 = v2 * r2; g.iX2 = r2 * r2;
+        } else {
+            g.X1re = Fp<T>::sqrt(v1);
+            g.X2 = Fp<T>::sqrt(v2);
+        }
         g.X1im = T(0); g.X1abs = T(0);
         g.T1_0 = g.Xt * g.X0 * k.y1re * k.y2;
         g.T2_0 = k.yt * k.y0 * g.X1re * g.X2;
@@ -434,7 +461,7 @@ template <typename T, bool PAIR> struct ChiGrad {
 template <typename T, bool PAIR>
 __device__ __forceinline__ void chi_grad(const LaneConst<T> &k, T z, ChiGrad<T, PAIR> &o) {
     Geo<T, PAIR> g;
-    build_u<T, PAIR>(k, z, g);
+    build_u<T, PAIR, true>(k, z, g);
     T rf, rdx, rdz;
     cx<T> rdy;
     rfd_s<T, PAIR>(g.U0 * g.U0, g.va, g.vb, rf, rdx, rdy, rdz);
@@ -448,9 +475,9 @@ __device__ __forceinline__ void chi_grad(const LaneConst<T> &k, T z, ChiGrad<T, 
         cx<T> G1 = mkc(g.U1re, g.U1im) * rdy * T(-1.0 / 3.0);
         cx<T> a1 = G1 * mkc(g.T1_1re, g.T1_1im), b1 = G1 * mkc(g.T2_1re, g.T2_1im);
         const T A = a0 + T(2) * a1.re, B = b0 + T(2) * b1.re;
-        o.dsig = scale * T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * k.iyt2);
-        o.dr0 = scale * T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * k.iw0);
-        cx<T> iX1sq = crcp(mkc(z + k.w1re, k.w1im));
+        o.dsig = scale * T(-0.5) * ((T(1) + z) * A * g.iXt2 + B * k.iyt2);
+        o.dr0 = scale * T(-0.5) * ((a0 + B - b0) * g.iX02 + (b0 + A - a0) * k.iw0);
+        const cx<T> iX1sq = mkc(g.iX1re, g.iX1im);
         const cx<T> iW1 = mkc(k.iw1re, k.iw1im);
         // (a1 + B - b1)/X1^2 + (b1 + A - a1)/W1
         cx<T> d1 = (a1 + B - b1) * iX1sq + (b1 + A - a1) * iW1;
@@ -461,10 +488,10 @@ __device__ __forceinline__ void chi_grad(const LaneConst<T> &k, T z, ChiGrad<T, 
         const T G1 = -g.U1re * rdy.re * T(1.0 / 3.0), G2 = -g.U2 * rdz * T(1.0 / 3.0);
         const T a1 = G1 * g.T1_1re, b1 = G1 * g.T2_1re, a2 = G2 * g.T1_2, b2 = G2 * g.T2_2;
         const T A = a0 + a1 + a2, B = b0 + b1 + b2;
-        o.dsig = scale * T(-0.5) * ((T(1) + z) * A * Fp<T>::rcp(g.Xt2) + B * k.iyt2);
-        o.dr0 = scale * T(-0.5) * ((a0 + B - b0) * Fp<T>::rcp(g.X02) + (b0 + A - a0) * k.iw0);
-        o.dr1re = scale * T(-0.5) * ((a1 + B - b1) * Fp<T>::rcp(z + k.w1re) + (b1 + A - a1) * k.iw1re);
-        o.dr2 = scale * T(-0.5) * ((a2 + B - b2) * Fp<T>::rcp(z + k.w2) + (b2 + A - a2) * k.iw2);
+        o.dsig = scale * T(-0.5) * ((T(1) + z) * A * g.iXt2 + B * k.iyt2);
+        o.dr0 = scale * T(-0.5) * ((a0 + B - b0) * g.iX02 + (b0 + A - a0) * k.iw0);
+        o.dr1re = scale * T(-0.5) * ((a1 + B - b1) * g.iX1re + (b1 + A - a1) * k.iw1re);
+        o.dr2 = scale * T(-0.5) * ((a2 + B - b2) * g.iX2 + (b2 + A - a2) * k.iw2);
         o.dr1im = T(0);
     }
 }
