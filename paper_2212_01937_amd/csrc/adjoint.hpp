@@ -104,7 +104,7 @@ __device__ __forceinline__ void lane_grad(const CosmoRec &r, T z, LaneGrad<T> &o
         o.dh = -o.val * H0inv;
         return;
     }
-    T dzz;
+    T dzz, ie; // ie = 1/E(z)
     if (direct_mode(KIND, r, fp32)) {
         // near-multiple roots: chi and its parameter gradient by FP64 quadrature
         T chi;
@@ -118,6 +118,7 @@ __device__ __forceinline__ void lane_grad(const CosmoRec &r, T z, LaneGrad<T> &o
             o.q[0] = gc.g0; o.q[1] = gc.g1; o.q[2] = gc.g2;
         }
         o.quad = true;
+        ie = iEz<T>(k, z);
         o.val = observable<T>(KIND, k, chi, z, H0inv, o.s, o.dok, dzz, o.dh);
     } else {
         if (small) {
@@ -126,14 +127,16 @@ __device__ __forceinline__ void lane_grad(const CosmoRec &r, T z, LaneGrad<T> &o
             o.p[0] = cv;
             o.q[0] = g[0]; o.q[1] = g[1]; o.q[2] = g[2];
             o.quad = true;
+            ie = iEz<T>(k, z);
         } else {
             ChiGrad<T, PAIR> cg;
             chi_grad<T, PAIR>(k, z, cg);
             o.p[0] = cg.chi; o.p[1] = cg.dsig; o.p[2] = cg.dr0; o.p[3] = cg.dr1re; o.p[4] = PAIR ? cg.dr1im : cg.dr2;
+            ie = cg.iE;
         }
         o.val = observable<T>(KIND, k, o.p[0], z, H0inv, o.s, o.dok, dzz, o.dh);
     }
-    o.dz = dzz + o.s * iEz<T>(k, z);
+    o.dz = dzz + o.s * ie;
 }
 
 // Contraction of root-space partials with the root Jacobian (app. A), FP64:

@@ -289,11 +289,12 @@ template <typename T, bool PAIR> __device__ T rf_s(T x, T a, T b) {
         A = (A + lam) * T(0.25);
         f *= T(0.25);
     }
-    T g = f * Fp<T>::rcp(A);
+    const T ra = Fp<T>::rsqrt(A); // 1/A = ra^2 (A > 0 on the structured triples)
+    T g = f * (ra * ra);
     T X = (A0 - x0) * g, s, q;
     yz_sym<T, PAIR>(A0, a0, b0, g, s, q);
     // with X + s = 0: E2 = XY + XZ + YZ = q - X^2, E3 = XYZ = X q
-    return rf_tail(q - X * X, X * q) * Fp<T>::rsqrt(A);
+    return rf_tail(q - X * X, X * q) * ra;
 }
 
 // R_F(x, y, z) and R_J(x, y, z, p) from one shared duplication sequence
@@ -325,13 +326,15 @@ __device__ void rfj_s(T x, T a, T b, T p, T &rf, T &rj) {
         f *= T(0.25);
     }
     {
-        T g = f * Fp<T>::rcp(AF);
+        const T ra = Fp<T>::rsqrt(AF);
+        T g = f * (ra * ra);
         T X = (AF0 - x0) * g, s, q;
         yz_sym<T, PAIR>(AF0, a0, b0, g, s, q);
-        rf = rf_tail(q - X * X, X * q) * Fp<T>::rsqrt(AF);
+        rf = rf_tail(q - X * X, X * q) * ra;
     }
     {
-        T g = f * Fp<T>::rcp(AJ);
+        const T rj_a = Fp<T>::rsqrt(AJ);
+        T g = f * (rj_a * rj_a);
         T X = (AJ0 - x0) * g, s, q;
         yz_sym<T, PAIR>(AJ0, a0, b0, g, s, q);
         T P = (AJ0 - p0) * g;
@@ -340,7 +343,7 @@ __device__ void rfj_s(T x, T a, T b, T p, T &rf, T &rj) {
         T E3 = xyz + T(2) * E2 * P + T(4) * P2 * P;
         T E4 = (T(2) * xyz + E2 * P + T(3) * P2 * P) * P;
         T E5 = xyz * P2;
-        rj = rj_tail(E2, E3, E4, E5) * f * Fp<T>::rcp(AJ) * Fp<T>::rsqrt(AJ) + T(6) * acc;
+        rj = rj_tail(E2, E3, E4, E5) * g * rj_a + T(6) * acc;
     }
     if (!(p0 > T(0))) rj = Fp<T>::nan();
 }
@@ -361,14 +364,15 @@ template <typename T, bool PAIR> __device__ T rd_last_x(T x, T a, T b) {
         A = (A + lam) * T(0.25);
         f *= T(0.25);
     }
-    T g = f * Fp<T>::rcp(A);
+    const T ra = Fp<T>::rsqrt(A);
+    T g = f * (ra * ra);
     T s, q; // (Y + Z, Y Z) of the two leading arguments
     yz_sym<T, PAIR>(A0, a0, b0, g, s, q);
     T Z = s * T(-1.0 / 3.0);
     T Z2 = Z * Z;
     T E2 = q - T(6) * Z2, E3 = (T(3) * q - T(8) * Z2) * Z;
     T E4 = T(3) * (q - Z2) * Z2, E5 = q * Z2 * Z;
-    return rj_tail(E2, E3, E4, E5) * f * Fp<T>::rcp(A) * Fp<T>::rsqrt(A) + T(3) * acc;
+    return rj_tail(E2, E3, E4, E5) * g * ra + T(3) * acc;
 }
 
 // R_F together with the three R_D(., ., x_k) that give its partial derivatives,
@@ -391,13 +395,13 @@ template <typename T, bool PAIR> __device__ T rd_last_x(T x, T a, T b) {
 // Outputs: rf; tx, ty (PAIR: complex, last argument y = a + i b), tz (not PAIR).
 template <typename T, bool PAIR>
 __device__ __forceinline__ void rfd_tails(T AF0, T x0, T a0, T b0, T AF, T f, T &rf, T &tx, cx<T> &ty, T &tz) {
-    const T g = f * Fp<T>::rcp(AF);
+    const T ra = Fp<T>::rsqrt(AF);
+    const T g = f * (ra * ra);
     const T X = (AF0 - x0) * g;
     T s, q;
     yz_sym<T, PAIR>(AF0, a0, b0, g, s, q);
     const T E2 = q - X * X, E3 = X * q;
     const T tF = rf_tail(E2, E3);
-    const T ra = Fp<T>::rsqrt(AF);
     rf = tF * ra;
     T t2, t3;
     rf_tail_grad(E2, E3, t2, t3);
@@ -503,7 +507,8 @@ __device__ void rfjd_s(T x, T a, T b, T p, T &rf, T &rj, T &rdx, cx<T> &rdy, T &
     rdy = accy * T(3) + ty;
     rdz = T(3) * accz + tz;
     {
-        T g = f * Fp<T>::rcp(AJ);
+        const T rj_a = Fp<T>::rsqrt(AJ);
+        T g = f * (rj_a * rj_a);
         T X = (AJ0 - x0) * g, s, q;
         yz_sym<T, PAIR>(AJ0, a0, b0, g, s, q);
         T P = (AJ0 - p0) * g;
@@ -512,7 +517,7 @@ __device__ void rfjd_s(T x, T a, T b, T p, T &rf, T &rj, T &rdx, cx<T> &rdy, T &
         T E3 = xyz + T(2) * E2 * P + T(4) * P2 * P;
         T E4 = (T(2) * xyz + E2 * P + T(3) * P2 * P) * P;
         T E5 = xyz * P2;
-        rj = rj_tail(E2, E3, E4, E5) * f * Fp<T>::rcp(AJ) * Fp<T>::rsqrt(AJ) + T(6) * acc;
+        rj = rj_tail(E2, E3, E4, E5) * g * rj_a + T(6) * acc;
     }
     if (!(p0 > T(0))) rj = Fp<T>::nan();
 }

@@ -40,8 +40,9 @@ template <typename T, bool PAIR> struct Geo {
     T T1_1re, T1_1im, T2_1re, T2_1im; // same for U_1 (PAIR) ; REAL: T1_1re, T2_1re
     T T1_2, T2_2;          // REAL only
     T va, vb;              // structured second/third Carlson arguments
-    // INV builds only: 1/Xt^2, 1/X_0^2 and 1/X_1^2 (PAIR: complex; REAL: also 1/X_2^2)
-    T iXt2, iX02, iX1re, iX1im, iX2;
+    // INV builds only: 1/Xt^2, 1/X_0^2 and 1/X_1^2 (PAIR: complex; REAL: also 1/X_2^2),
+    // and 1/(Xt X_0 |X_1|^2) (REAL: 1/(Xt X_0 X_1 X_2)) = beta^(1/2) / E(z)
+    T iXt2, iX02, iX1re, iX1im, iX2, iXprod;
 };
 
 // INV: the square roots come from reciprocal square roots (s = v rsqrt(v)), which
@@ -55,6 +56,7 @@ __device__ __forceinline__ void build_u(const LaneConst<T> &k, T z, Geo<T, PAIR>
         const T rt = Fp<T>::rsqrt(g.Xt2), r0 = Fp<T>::rsqrt(g.X02);
         g.Xt = g.Xt2 * rt; g.iXt2 = rt * rt;
         g.X0 = g.X02 * r0; g.iX02 = r0 * r0;
+        g.iXprod = rt * r0;
     } else {
         g.Xt = Fp<T>::sqrt(g.Xt2);
         g.X0 = Fp<T>::sqrt(g.X02);
@@ -68,6 +70,7 @@ __device__ __forceinline__ void build_u(const LaneConst<T> &k, T z, Geo<T, PAIR>
             X1 = csqrt_inv(w1, ab, iab);
             const T i2 = iab * iab;
             g.iX1re = w1.re * i2; g.iX1im = -w1.im * i2;
+            g.iXprod *= iab;
         } else {
             X1 = csqrt(w1, ab);
         }
@@ -91,6 +94,7 @@ __device__ __forceinline__ void build_u(const LaneConst<T> &k, T z, Geo<T, PAIR>
             const T r1 = Fp<T>::rsqrt(v1), r2 = Fp<T>::rsqrt(v2);
             g.X1re = v1 * r1; g.iX1re = r1 * r1;
             g.X2 = v2 * r2; g.iX2 = r2 * r2;
+            g.iXprod *= r1 * r2;
         } else {
             g.X1re = Fp<T>::sqrt(v1);
             g.X2 = Fp<T>::sqrt(v2);
@@ -456,6 +460,7 @@ template <typename T> __device__ __forceinline__ T iEz(const LaneConst<T> &k, T 
 // arguments: dR_F/d(U_m^2) = -R_D(., ., U_m^2)/6 (eq. 2.10).
 template <typename T, bool PAIR> struct ChiGrad {
     T chi, dsig, dr0, dr1re, dr1im, dr2;
+    T iE; // 1/E(z), from the lane's geometry (E^2 = beta Xt^2 X_0^2 |X_1^2|^2)
 };
 
 template <typename T, bool PAIR>
@@ -467,6 +472,7 @@ __device__ __forceinline__ void chi_grad(const LaneConst<T> &k, T z, ChiGrad<T, 
     rfd_s<T, PAIR>(g.U0 * g.U0, g.va, g.vb, rf, rdx, rdy, rdz);
     const T scale = k.pre * T(2) * z;
     o.chi = scale * rf;
+    o.iE = k.pre * g.iXprod;
     // G_m = dR_F/dU_m = -U_m R_D(., ., U_m^2)/3 ; a_m = G_m T1_m, b_m = G_m T2_m
     const T G0 = -g.U0 * rdx * T(1.0 / 3.0);
     const T a0 = G0 * g.T1_0, b0 = G0 * g.T2_0;
