@@ -34,6 +34,7 @@ PEAK = {"f32": 157.3e12, "f64": 78.6e12}
 # counters on this workload (written with the hash of the kernel sources they
 # were taken on).
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_config5.json")
+CEILING_FILE = os.path.join(ROOT, "profiles", "valu_ceiling.json")
 
 
 def kernel_source_hash():
@@ -51,6 +52,16 @@ def load_counters():
             t = json.load(fh)
         t["current"] = t.get("src_sha256") == kernel_source_hash()
         return t
+    except (OSError, ValueError):
+        return None
+
+
+def load_ceiling():
+    """FMA-only vector-ALU rates measured by paper_2212_01937_amd/tools/valu_ceiling
+    (packed FP32 disabled, as in the library), if recorded."""
+    try:
+        with open(CEILING_FILE) as fh:
+            return json.load(fh)
     except (OSError, ValueError):
         return None
 
@@ -266,6 +277,12 @@ def main():
                          "flop_per_eval": k["flop_per_eval"], "valu_instr_per_eval": k["valu_per_eval"],
                          "traffic": k["hbm_bytes_per_launch"] if cnt["current"] else None,
                          "counters_current": cnt["current"]})
+        ceil = load_ceiling()
+        key = "fp32_fma_tflops" if head == "f32" else "fp64_fma_tflops"
+        if ceil and key in ceil:
+            # context, not the peak: what FMA-only code built without packed FP32 reached
+            roofline["fma_only_ceiling_measured"] = ceil[key]
+            roofline["frac_of_fma_only_ceiling"] = achieved / 1e12 / ceil[key]
     line = {"metric": METRIC, "value": r["evals_per_s"], "unit": "evals/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

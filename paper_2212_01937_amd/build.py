@@ -2,8 +2,9 @@
 
     python -m paper_2212_01937_amd.build     (or: python paper_2212_01937_amd/build.py)
 
-The library is built in-tree next to this file.  All device code is compiled with
-packed-FP32 instruction selection disabled.
+The library is built in-tree next to this file, and so is tools/valu_ceiling (a
+stand-alone measurement of the vector-ALU ceiling of code built this way).  All
+device code is compiled with packed-FP32 instruction selection disabled.
 """
 import os
 import subprocess
@@ -15,14 +16,16 @@ SRC = os.path.join(HERE, "csrc", "cosmo.hip")
 LIB = os.path.join(HERE, "libcosmo.so")
 DEPS = [os.path.join(HERE, "csrc", f) for f in ("cmath.hpp", "carlson.hpp", "setup.hpp", "lane.hpp", "adjoint.hpp", "cosmo.hip")] + [
     os.path.join(ROOT, "include", "cosmo.h")]
+TOOL_SRC = os.path.join(HERE, "tools", "valu_ceiling.hip")
+TOOL = os.path.join(HERE, "tools", "valu_ceiling")
 ARCH = os.environ.get("COSMO_OFFLOAD_ARCH", "gfx950")
+FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wall", "-Wno-unused-command-line-argument"]
 
 
 def command(out):
-    return ["hipcc", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wall", "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"),
-            "-o", out, SRC]
+    return ["hipcc"] + FLAGS + ["-fPIC", "-shared", "-I", os.path.join(ROOT, "include"), "-o", out, SRC]
 
 
 def build(verbose: bool = False) -> str:
@@ -32,7 +35,18 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_tool(verbose)
     return LIB
+
+
+def build_tool(verbose: bool = False) -> str:
+    tmp = TOOL + ".tmp"
+    cmd = ["hipcc"] + FLAGS + ["-o", tmp, TOOL_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, TOOL)
+    return TOOL
 
 
 def stale() -> bool:
