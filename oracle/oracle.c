@@ -16,6 +16,9 @@
  *   X      = (c/H0)  int_0^z (1+z')^2/E dz'  (absorption dist.)   (eq. 2.5)
  *   D_M    = curvature-modified comoving distance (sin/sinh of D_C), D_L = (1+z) D_M,
  *   D_A    = D_M/(1+z), mu = 5 log10(D_L / 10 pc)                  (sec. 2.1.1; fn. 22)
+ * between two redshifts (oracle_between): chi(z1, z2), t(z1, z2), d_abs(z1, z2) of eqs.
+ * 2.3-2.5 with both limits free (z2 = +inf for chi and t: the age t(z, inf), sec. 2.1),
+ * D_M(z1, z2) = sinn of chi(z1, z2) and D_A(z1, z2) = D_M(z1, z2)/(1+z2);
  * and their gradients with respect to (H0, Om, OL, Or, z) by the Leibniz
  * integral rule (differentiation under the integral sign, as the HMC analyses
  * quoted in sec. 4, fn. 23 do), Ok being eliminated through the closure.
@@ -183,6 +186,36 @@ static double dimless_integral(const struct cosmo *c, int which, int dparam, dou
     return adapt(dist_integrand, &k, 0.0, log1p(z), 0.0, EPSREL, abserr);
 }
 
+/* Integrand to an infinite upper limit.  With a = 1/x = s^2 (x = 1 + z):
+ *   dz / E          = da / sqrt(P(a))          = 2 s ds / sqrt(P(s^2)),
+ *   dz / ((1+z) E)  = a da / sqrt(P(a))        = 2 s^3 ds / sqrt(P(s^2)),
+ * P(a) = a^4 E^2(1/a) = Or + Om a + Ok a^2 + OL a^4; s runs over [0, 1/sqrt(1+z1)].
+ * (The s-form stays bounded at s -> 0 also for Or = 0.) */
+static double inf_integrand(double s, const void *vctx)
+{
+    const struct ictx *k = (const struct ictx *)vctx;
+    const struct cosmo *c = k->c;
+    double a = s * s;
+    double P = c->Or + c->Om * a + c->Ok * a * a + c->OL * a * a * a * a;
+    double num = k->which == INT_CHI ? 2.0 * s : 2.0 * s * s * s;
+    return num / sqrt(P);
+}
+
+/* Dimensionless integral from z1 to z2 (either order; z2 = +inf for the comoving
+ * distance and the time coordinate; the absorption distance diverges there). */
+static double dimless_between(const struct cosmo *c, int which, double z1, double z2, double *abserr)
+{
+    if (abserr) *abserr = 0.0;
+    if (isinf(z2) && z2 > 0.0) {
+        if (which == INT_ABS) return INFINITY;
+        struct ictx k = {c, which, 0};
+        return adapt(inf_integrand, &k, 0.0, 1.0 / sqrt(1.0 + z1), 0.0, EPSREL, abserr);
+    }
+    if (z1 == z2) return 0.0;
+    struct ictx k = {c, which, 0};
+    return adapt(dist_integrand, &k, log1p(z1), log1p(z2), 0.0, EPSREL, abserr);
+}
+
 /* ---------------------------------------------------------------------------
  * Output kinds (numbering matches the public ABI's enumeration of observables).
  * ------------------------------------------------------------------------- */
@@ -324,6 +357,45 @@ int oracle_eval(int kind, const double *params, long n_cosmo, const double *z, l
         out[idx] = eval_one(kind, params + 4 * ci, z[ci * z_stride + i],
                             grad ? grad + 5 * idx : NULL, &e);
         if (errest) errest[idx] = e;
+    }
+    (void)nthreads;
+    return 0;
+}
+
+/* Between two redshifts: kind K_DC, K_DM, K_DA, K_T or K_X at (z1, z2) of one
+ * cosmology.  D_M(z1, z2) = (c/H0) sinn(chi(z1, z2)), D_A(z1, z2) = D_M(z1, z2)/(1+z2). */
+static double between_one(int kind, const double *prm, double z1, double z2)
+{
+    struct cosmo c;
+    c.H0 = prm[0]; c.Om = prm[1]; c.OL = prm[2]; c.Or = prm[3];
+    c.Ok = 1.0 - c.Om - c.OL - c.Or;
+    double DH = C_KMS / c.H0;
+    double tH = MPC_KM / (c.H0 * GYR_S);
+    if (kind == K_T) return tH * dimless_between(&c, INT_T, z1, z2, NULL);
+    if (kind == K_X) return DH * dimless_between(&c, INT_ABS, z1, z2, NULL);
+    double chi = dimless_between(&c, INT_CHI, z1, z2, NULL);
+    if (kind == K_DC) return DH * chi;
+    double S, dS_dchi, dS_dok;
+    curvature_transform(c.Ok, chi, &S, &dS_dchi, &dS_dok);
+    if (kind == K_DM) return DH * S;
+    return isinf(z2) ? 0.0 : DH * S / (1.0 + z2); /* K_DA */
+}
+
+/* Batched: out[c*n_z + i] for the pair (z1[c*z_stride + i], z2[c*z_stride + i]).
+ * kind: K_DC, K_DM, K_DA, K_T or K_X.  Returns 0, or -1 on bad arguments. */
+int oracle_between(int kind, const double *params, long n_cosmo, const double *z1, const double *z2,
+                   long n_z, long z_stride, double *out, int nthreads)
+{
+    if (!(kind == K_DC || kind == K_DM || kind == K_DA || kind == K_T || kind == K_X)) return -1;
+    if (n_cosmo < 0 || n_z < 0 || !params || !z1 || !z2 || !out) return -1;
+    long total = n_cosmo * n_z;
+#ifdef _OPENMP
+    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
+#endif
+    for (long idx = 0; idx < total; ++idx) {
+        long ci = idx / n_z, i = idx % n_z;
+        out[idx] = between_one(kind, params + 4 * ci, z1[ci * z_stride + i], z2[ci * z_stride + i]);
     }
     (void)nthreads;
     return 0;

@@ -419,3 +419,113 @@ def test_roots_known_factorisation():
     # rounding the coefficients to FP64 moves a root pair d apart by ~ eps*rho/d
     assert np.max(np.abs(got - want)) < 100 * 2.2e-16 * rho / d
     assert abs(got[0] - want[0]) < 1e-14
+
+
+# --------------------------------------------------------------------------- between two redshifts
+Z1 = np.array([0.0, 1e-4, 0.1, 0.5, 1.0, 3.0, 50.0])
+Z2 = np.array([0.3, 2e-4, 0.1, 2.0, 0.2, 1000.0, 50.5])  # includes z1 == z2 and z1 > z2
+
+
+def _bt(kind, params, z1, z2):
+    return oracle.between(kind, np.array([params], dtype=float), np.asarray(z1, dtype=float),
+                          np.asarray(z2, dtype=float))[0]
+
+
+def _absdiff(a, b, scale):
+    return np.max(np.abs(np.asarray(a) - np.asarray(b)) / scale)
+
+
+def test_between_closed_forms():
+    """Limits (z1, z2) of eqs. 2.3-2.5 in universes with elementary integrals,
+    either order of the limits; F(z1, z2) = G(x2) - G(x1) with the antiderivative G."""
+    x1, x2 = 1.0 + Z1, 1.0 + Z2
+    h0 = 70.0
+    # Einstein-de Sitter: E = x^(3/2)
+    p = (h0, 1.0, 0.0, 0.0)
+    assert _absdiff(_bt("DC", p, Z1, Z2), 2 * DH(h0) * (x1 ** -0.5 - x2 ** -0.5), DH(h0)) < 1e-14
+    assert _absdiff(_bt("T", p, Z1, Z2), (2 / 3) * TH(h0) * (x1 ** -1.5 - x2 ** -1.5), TH(h0)) < 1e-14
+    assert _absdiff(_bt("X", p, Z1, Z2), (2 / 3) * DH(h0) * (x2 ** 1.5 - x1 ** 1.5),
+                    DH(h0) * x2 ** 1.5) < 1e-14
+    # radiation only: E = x^2
+    p = (h0, 0.0, 0.0, 1.0)
+    assert _absdiff(_bt("DC", p, Z1, Z2), DH(h0) * (1 / x1 - 1 / x2), DH(h0)) < 1e-14
+    assert _absdiff(_bt("T", p, Z1, Z2), TH(h0) * 0.5 * (x1 ** -2 - x2 ** -2), TH(h0)) < 1e-14
+    assert _absdiff(_bt("X", p, Z1, Z2), DH(h0) * (x2 - x1), DH(h0) * x2) < 1e-14
+    # de Sitter: E = 1
+    p = (h0, 0.0, 1.0, 0.0)
+    assert _absdiff(_bt("DC", p, Z1, Z2), DH(h0) * (Z2 - Z1), DH(h0) * x2) < 1e-14
+    assert _absdiff(_bt("T", p, Z1, Z2), TH(h0) * np.log(x2 / x1), TH(h0)) < 1e-14
+    # Milne (Ok0 = 1): E = x, D_M(z1, z2) = D_H sinh(ln(x2/x1)), D_A = D_M/x2
+    p = (h0, 0.0, 0.0, 0.0)
+    dm = DH(h0) * 0.5 * (x2 / x1 - x1 / x2)
+    assert _absdiff(_bt("DC", p, Z1, Z2), DH(h0) * np.log(x2 / x1), DH(h0)) < 1e-14
+    assert _absdiff(_bt("DM", p, Z1, Z2), dm, DH(h0) * x2) < 1e-14
+    assert _absdiff(_bt("DA", p, Z1, Z2), dm / x2, DH(h0)) < 1e-14
+    assert _absdiff(_bt("T", p, Z1, Z2), TH(h0) * (1 / x1 - 1 / x2), TH(h0)) < 1e-14
+
+
+def test_between_to_infinity_closed_forms():
+    """z2 = inf: chi(z, inf) and the age t(z, inf) (sec. 2.1) in the same universes;
+    the absorption distance diverges; D_A(z, inf) = 0."""
+    zz = np.array([0.0, 0.1, 1.0, 10.0, 1000.0])
+    x = 1.0 + zz
+    inf = np.full_like(zz, np.inf)
+    h0 = 67.0
+    p = (h0, 1.0, 0.0, 0.0)
+    assert rel(_bt("DC", p, zz, inf), 2 * DH(h0) * x ** -0.5) < 1e-14
+    assert rel(_bt("T", p, zz, inf), (2 / 3) * TH(h0) * x ** -1.5) < 1e-14
+    assert np.all(np.isinf(_bt("X", p, zz, inf)))
+    p = (h0, 0.0, 0.0, 1.0)
+    assert rel(_bt("DC", p, zz, inf), DH(h0) / x) < 1e-14
+    assert rel(_bt("T", p, zz, inf), TH(h0) * 0.5 / x ** 2) < 1e-14
+    p = (h0, 0.0, 0.0, 0.0)  # Milne: chi diverges logarithmically, t(z, inf) = t_H / x
+    assert rel(_bt("T", p, zz, inf), TH(h0) / x) < 1e-14
+    # open matter universe (Om0 = 0.3, Ok0 = 0.7): t(0, inf) in closed form
+    om = 0.3
+    ok = 1 - om
+    age = TH(h0) * (1 / ok - om / ok ** 1.5 * math.asinh(math.sqrt(ok / om)))
+    assert rel(_bt("T", (h0, om, 0.0, 0.0), [0.0], [np.inf]), [age]) < 1e-14
+    assert np.all(_bt("DA", (70.0, 0.3, 0.7, 9e-5), zz, inf) == 0.0)
+
+
+@pytest.mark.parametrize("p", COSMOS)
+def test_between_additivity_and_one_sided(p):
+    """chi(z1, z2) + chi(z2, z3) = chi(z1, z3) (and for t, d_abs); (0, z) is the
+    one-sided oracle; z2 = inf is the limit of large finite z2 (the tail of chi above
+    X = 1+Z is c/H0 [1/(sqrt(Or0) X) - Om0/(4 Or0^(3/2) X^2)] to second order, from
+    E = sqrt(Or0) x^2 (1 + Om0/(2 Or0 x) + ...))."""
+    za = np.array([0.0, 0.01, 0.4, 1.3, 7.0])
+    zb = np.array([0.02, 0.5, 0.4, 3.0, 20.0])
+    zc = np.array([1.0, 0.3, 2.5, 900.0, 21.0])
+    for kind, tol in (("DC", 3e-15), ("T", 3e-15), ("X", 3e-15)):
+        ab, bc, ac = (_bt(kind, p, u, v) for u, v in ((za, zb), (zb, zc), (za, zc)))
+        assert _absdiff(ab + bc, ac, np.abs(ab) + np.abs(bc) + np.abs(ac)) < tol, kind
+        assert rel(_bt(kind, p, np.zeros(4), zc[:4]), _ev(kind, p, zc[:4])) < 1e-14
+    if p[3] > 0:
+        zbig = 1e9
+        X = 1 + zbig
+        tail = DH(p[0]) * (1 / (math.sqrt(p[3]) * X) - p[1] / (4 * p[3] ** 1.5 * X ** 2))
+        inf_ = _bt("DC", p, za, np.full_like(za, np.inf))
+        fin = _bt("DC", p, za, np.full_like(za, zbig))
+        assert rel(inf_, fin + tail) < 1e-12
+
+
+def test_between_against_mpmath_quad():
+    """Generic cosmologies, finite and infinite upper limits, against mpmath's
+    tanh-sinh quadrature at 30 digits."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 30
+    for p in (COSMOS[0], COSMOS[3], COSMOS[6]):
+        h0, om, ol, orr = (mpmath.mpf(v) for v in p)
+        ok = 1 - om - ol - orr
+
+        def E(zz):
+            x = 1 + zz
+            return mpmath.sqrt(orr * x ** 4 + om * x ** 3 + ok * x ** 2 + ol)
+
+        for z1, z2 in ((0.2, 0.25), (1.0, 40.0), (3.0, mpmath.inf)):
+            dc = mpmath.quad(lambda t: 1 / E(t), [z1, z2]) * C / h0
+            tt = mpmath.quad(lambda t: 1 / ((1 + t) * E(t)), [z1, z2]) * mpmath.mpf(TH_FACTOR) / h0
+            zz2 = float(z2)
+            assert rel(_bt("DC", p, [z1], [zz2]), [float(dc)]) < 2e-14
+            assert rel(_bt("T", p, [z1], [zz2]), [float(tt)]) < 2e-14
