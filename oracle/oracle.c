@@ -101,6 +101,7 @@ struct panel { double a, b, r, e; };
 static double adapt(integrand_fn f, const void *ctx, double a, double b,
                     double epsabs, double epsrel, double *abserr)
 {
+    if (b < a) return -adapt(f, ctx, b, a, epsabs, epsrel, abserr); /* bisection needs a < b */
     struct panel *p = (struct panel *)malloc(sizeof(struct panel) * QUAD_LIMIT);
     int n = 1;
     p[0].a = a; p[0].b = b;
@@ -159,19 +160,22 @@ static double integrand_power(int which)
     return which == INT_CHI ? 0.0 : (which == INT_T ? -1.0 : 2.0);
 }
 
-struct ictx { const struct cosmo *c; int which; int dparam; };
+/* x = x0 e^u: x0 = 1 for integrals from z = 0 (u = ln(1+z)); x0 = 1 + z1 from a lower
+ * limit z1, which keeps the interval [0, ln((1+z2)/(1+z1))] exact for close limits. */
+struct ictx { const struct cosmo *c; int which; int dparam; double x0; };
 
 /* Integrand in u.  dparam == 0: (1+z)^p / E * dz/du.  dparam = a > 0: its partial
  * derivative with respect to parameter a, i.e. -(1/2) (1+z)^p (dE2/da) / E^3 * dz/du. */
 static double dist_integrand(double u, const void *vctx)
 {
     const struct ictx *k = (const struct ictx *)vctx;
-    double x = exp(u);
+    double x = k->x0 * exp(u);
     double e2 = E2_of_x(k->c, x);
     double e = sqrt(e2);
     double g = pow(x, integrand_power(k->which)) * x; /* (1+z)^p * dz/du */
     if (k->dparam == 0) return g / e;
-    return -0.5 * g * dE2_dparam(k->dparam, x, expm1(u)) / (e2 * e);
+    double xm1 = k->x0 == 1.0 ? expm1(u) : x - 1.0;
+    return -0.5 * g * dE2_dparam(k->dparam, x, xm1) / (e2 * e);
 }
 
 static const double EPSREL = 1e-14;
@@ -181,7 +185,7 @@ static const double EPSREL = 1e-14;
 static double dimless_integral(const struct cosmo *c, int which, int dparam, double z,
                                double *abserr)
 {
-    struct ictx k = {c, which, dparam};
+    struct ictx k = {c, which, dparam, 1.0};
     if (z == 0.0) { if (abserr) *abserr = 0.0; return 0.0; }
     return adapt(dist_integrand, &k, 0.0, log1p(z), 0.0, EPSREL, abserr);
 }
@@ -208,12 +212,24 @@ static double dimless_between(const struct cosmo *c, int which, double z1, doubl
     if (abserr) *abserr = 0.0;
     if (isinf(z2) && z2 > 0.0) {
         if (which == INT_ABS) return INFINITY;
-        struct ictx k = {c, which, 0};
-        return adapt(inf_integrand, &k, 0.0, 1.0 / sqrt(1.0 + z1), 0.0, EPSREL, abserr);
+        struct ictx k = {c, which, 0, 1.0};
+        /* panels [s1 10^-(j+1), s1 10^-j], j < 16, and [0, s1 1e-16]: the integrand has
+         * structure at the scale sqrt(Or/Om) (where radiation takes over from matter),
+         * which a single interval's first bisections would not sample */
+        double s1 = 1.0 / sqrt(1.0 + z1), hi = s1, sum = 0.0, e = 0.0, ej;
+        for (int j = 0; j < 16; ++j) {
+            double lo = hi * 0.1;
+            sum += adapt(inf_integrand, &k, lo, hi, 0.0, EPSREL, &ej);
+            e += ej;
+            hi = lo;
+        }
+        sum += adapt(inf_integrand, &k, 0.0, hi, 0.0, EPSREL, &ej);
+        if (abserr) *abserr = e + ej;
+        return sum;
     }
     if (z1 == z2) return 0.0;
-    struct ictx k = {c, which, 0};
-    return adapt(dist_integrand, &k, log1p(z1), log1p(z2), 0.0, EPSREL, abserr);
+    struct ictx k = {c, which, 0, 1.0 + z1};
+    return adapt(dist_integrand, &k, 0.0, log1p((z2 - z1) / (1.0 + z1)), 0.0, EPSREL, abserr);
 }
 
 /* ---------------------------------------------------------------------------

@@ -529,3 +529,20 @@ def test_between_against_mpmath_quad():
             zz2 = float(z2)
             assert rel(_bt("DC", p, [z1], [zz2]), [float(dc)]) < 2e-14
             assert rel(_bt("T", p, [z1], [zz2]), [float(tt)]) < 2e-14
+
+
+def test_between_reversed_and_tiny_radiation():
+    """chi(z2, z1) = -chi(z1, z2) over a long interval; and chi(z, inf) with a tiny
+    Or0 = eps next to Or0 = 0: the integrand in s = (1+z)^(-1/2) changes only near
+    s ~ sqrt(eps/Om0), by -2 sqrt(eps)/Om0 in total (to leading order), which a
+    quadrature that never samples that scale would miss."""
+    p = COSMOS[3]
+    for kind in ("DC", "T", "X"):
+        f = _bt(kind, p, [0.001, 7.6], [7.6, 0.001])
+        assert abs(f[0] + f[1]) <= 1e-15 * abs(f[0]), kind
+    eps = 1e-16
+    zz = np.array([0.0, 1.0, 30.0])
+    inf = np.full_like(zz, np.inf)
+    chi0 = _bt("DC", (70.0, 0.3, 0.7, 0.0), zz, inf)
+    chie = _bt("DC", (70.0, 0.3, 0.7 - eps, eps), zz, inf)
+    assert rel(chie, chi0 - DH(70.0) * 2 * math.sqrt(eps) / 0.3) < 1e-13
