@@ -111,6 +111,24 @@ int cosmo_distance(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_
                    const void *z, int64_t n_z, int64_t z_cosmo_stride, void *out,
                    int32_t *info, void *workspace, size_t workspace_bytes, void *stream);
 
+/* cosmo_distance_between -- observables between two redshifts, sec. 2.1 eqs.
+ * 2.3-2.4 with both limits free, evaluated as eqs. 3.7-3.8 (app. B.1-B.2 for
+ * Or0 == 0), whose Carlson arguments u_ij take both limits:
+ *   COSMO_DC  chi(z1, z2)               comoving distance from z1 to z2 [Mpc]
+ *   COSMO_DM  (c/H0) sinn(chi(z1, z2))  transverse comoving distance [Mpc]
+ *   COSMO_DA  D_M(z1, z2) / (1 + z2)    angular diameter distance of z2 seen
+ *                                       from z1 (lensing) [Mpc]
+ *   COSMO_T   t(z1, z2)                 time coordinate from z1 to z2 [Gyr]
+ * Other kinds return COSMO_E_KIND.  z1[c * z_cosmo_stride + i] and z2[...]: the
+ * limits of element (c, i), either order (the result changes sign, D_A aside),
+ * laid out like cosmo_distance's z; z2 = +inf gives the limits chi(z1, inf),
+ * D_M(z1, inf), D_A = 0 and the age t(z1, inf).  out: [n_cosmo][n_z] of dtype.
+ * info, workspace, workspace_bytes, stream: as cosmo_distance.  Forward only.     */
+int cosmo_distance_between(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo,
+                           const void *z1, const void *z2, int64_t n_z, int64_t z_cosmo_stride,
+                           void *out, int32_t *info, void *workspace, size_t workspace_bytes,
+                           void *stream);
+
 /* cosmo_distance_vjp -- adjoint of cosmo_distance for a cotangent `cot`
  * ([n_cosmo][n_z], dtype).  Gradients through the Carlson derivatives (eqs.
  * 2.10-2.12) and the differentiated root finding (app. A, eqs. A.1-A.4); the

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "cosmo.hip")
 LIB = os.path.join(HERE, "libcosmo.so")
-DEPS = [os.path.join(HERE, "csrc", f) for f in ("cmath.hpp", "carlson.hpp", "setup.hpp", "lane.hpp", "adjoint.hpp", "cosmo.hip")] + [
+DEPS = [os.path.join(HERE, "csrc", f) for f in ("cmath.hpp", "carlson.hpp", "setup.hpp", "lane.hpp", "adjoint.hpp", "between.hpp", "cosmo.hip")] + [
     os.path.join(ROOT, "include", "cosmo.h")]
 TOOL_SRC = os.path.join(HERE, "tools", "valu_ceiling.hip")
 TOOL = os.path.join(HERE, "tools", "valu_ceiling")

@@ -35,6 +35,7 @@ template <> struct Fp<float> {
     static __device__ __forceinline__ float sin(float x) { return sinf(x); }
     static __device__ __forceinline__ float cos(float x) { return cosf(x); }
     static __device__ __forceinline__ float nan() { return __builtin_nanf(""); }
+    static __device__ __forceinline__ float inf() { return __builtin_inff(); }
     // Duplication stopping thresholds: iterate while max|A0 - x_i| 4^-m > tau |A_m|.
     // 7th-order tails (R_F, R_C): remainder ~ tau^8 / 4; 5th-order (R_D, R_J): ~ tau^6.
     static constexpr float tau7 = 0.136f;
@@ -70,6 +71,7 @@ template <> struct Fp<double> {
     static __device__ __forceinline__ double sin(double x) { return ::sin(x); }
     static __device__ __forceinline__ double cos(double x) { return ::cos(x); }
     static __device__ __forceinline__ double nan() { return __builtin_nan(""); }
+    static __device__ __forceinline__ double inf() { return __builtin_inf(); }
     static constexpr double tau7 = 0.0121;
     static constexpr double tau5 = 0.0028;
     static constexpr double rc_series_max = 0.01;

@@ -16,6 +16,7 @@
 
 #include "../../include/cosmo.h"
 #include "adjoint.hpp"
+#include "between.hpp"
 
 namespace cosmo {
 
@@ -93,6 +94,30 @@ __global__ __launch_bounds__(kBlock) void k_forward(const CosmoRec *__restrict__
             unsigned long long m = __ballot(used_gl);
             if (m && (int)__lane_id() == __ffsll((long long)m) - 1) atomicOr(info + c, COSMO_INFO_X_QUADRATURE);
         }
+    }
+}
+
+// Observables between two redshifts (between.hpp): lane i of a cosmology evaluates the
+// pair (z1[i], z2[i]); grid and tiling as k_forward.
+template <typename T, int KIND>
+__global__ __launch_bounds__(kBlock) void k_between(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
+                                                     const T *__restrict__ z1, const T *__restrict__ z2,
+                                                     int64_t n_z, int64_t zstride, T *__restrict__ out,
+                                                     int ct, int64_t nzb) {
+    const int64_t b = blockIdx.x;
+    const int64_t tile = b / nzb, zb = b - tile * nzb;
+    const int64_t i = zb * kBlock + threadIdx.x;
+    if (i >= n_z) return;
+    const int64_t c0 = tile * ct;
+    const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
+    for (int64_t c = c0; c < c1; ++c) {
+        const CosmoRec &r = recs[c];
+        const T a = z1[c * zstride + i], bb = z2[c * zstride + i];
+        T v;
+        if (!r.valid) v = Fp<T>::nan();
+        else if (r.pair) v = eval_between<T, KIND, true>(r, a, bb);
+        else v = eval_between<T, KIND, false>(r, a, bb);
+        out[c * n_z + i] = v;
     }
 }
 
@@ -576,6 +601,22 @@ int launch_forward(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, 
 }
 
 template <typename T>
+int launch_between(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z1, const T *z2, int64_t n_z,
+                   int64_t zstride, T *out, hipStream_t s) {
+    Tiling t = tiling(n_cosmo, n_z);
+    dim3 grid((unsigned)t.nblocks), block(kBlock);
+#define COSMO_BTW(K) hipLaunchKernelGGL((k_between<T, K>), grid, block, 0, s, recs, n_cosmo, z1, z2, n_z, zstride, out, t.ct, t.nzb)
+    switch (kind) {
+    case COSMO_DC: COSMO_BTW(COSMO_DC); break;
+    case COSMO_DM: COSMO_BTW(COSMO_DM); break;
+    case COSMO_DA: COSMO_BTW(COSMO_DA); break;
+    case COSMO_T: COSMO_BTW(COSMO_T); break;
+    }
+#undef COSMO_BTW
+    return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
+}
+
+template <typename T>
 int launch_jac(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int64_t n_z, int64_t zstride, T *out,
                T *jac, int32_t *info, hipStream_t s) {
     Tiling t = tiling(n_cosmo, n_z);
@@ -737,6 +778,33 @@ int cosmo_distance(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_
     if (dt == COSMO_F32)
         return launch_forward<float>(kind, recs, n_cosmo, (const float *)z, n_z, z_cosmo_stride, (float *)out, info, s);
     return launch_forward<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, (double *)out, info, s);
+}
+
+int cosmo_distance_between(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo,
+                           const void *z1, const void *z2, int64_t n_z, int64_t z_cosmo_stride, void *out,
+                           int32_t *info, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!(kind == COSMO_DC || kind == COSMO_DM || kind == COSMO_DA || kind == COSMO_T)) return COSMO_E_KIND;
+    if (!valid_dtype(dt)) return COSMO_E_DTYPE;
+    if (n_cosmo < 0 || n_z < 0 || z_cosmo_stride < 0) return COSMO_E_ARG;
+    if (n_cosmo > 0 && !params) return COSMO_E_ARG;
+    if (n_cosmo > 0 && n_z > 0 && (!z1 || !z2 || !out)) return COSMO_E_ARG;
+    if (check_grid(n_cosmo, n_z) != COSMO_OK) return COSMO_E_ARG;
+    if (n_cosmo == 0) return COSMO_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_init();
+    if (rc != COSMO_OK) return rc;
+    WsLayout L = ws_layout(n_cosmo, 0);
+    Workspace ws;
+    rc = ws.acquire(workspace, workspace_bytes, L.pacc, s);
+    if (rc != COSMO_OK) return rc;
+    CosmoRec *recs = (CosmoRec *)ws.ptr;
+    rc = launch_setup(params, n_cosmo, recs, info, s);
+    if (rc != COSMO_OK || n_z == 0) return rc;
+    if (dt == COSMO_F32)
+        return launch_between<float>(kind, recs, n_cosmo, (const float *)z1, (const float *)z2, n_z, z_cosmo_stride,
+                                     (float *)out, s);
+    return launch_between<double>(kind, recs, n_cosmo, (const double *)z1, (const double *)z2, n_z, z_cosmo_stride,
+                                  (double *)out, s);
 }
 
 int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo, const void *z,

@@ -1,5 +1,5 @@
 // Host build of the per-lane forward formulas (D_C, T, X) for tests.
-#include "../../paper_2212_01937_amd/csrc/lane.hpp"
+#include "../../paper_2212_01937_amd/csrc/between.hpp"
 using namespace cosmo;
 namespace cosmo {
 double c_gl64_x[kGlN64], c_gl64_w[kGlN64];
@@ -43,5 +43,27 @@ extern "C" void host_rfd(int dt, int pair, double x, double a, double b, double 
         if (pair) rfd_s<double, true>(x, a, b, rf, rdx, rdy, rdz);
         else rfd_s<double, false>(x, a, b, rf, rdx, rdy, rdz);
         out[0] = rf; out[1] = rdx; out[2] = rdy.re; out[3] = rdy.im; out[4] = rdz;
+    }
+}
+
+// Observables between z1[i] and z2[i] (between.hpp) for one cosmology; kind:
+// COSMO_DC, COSMO_DM, COSMO_DA or COSMO_T; dt: 0 FP32, 1 FP64.
+template <typename T, bool PAIR> static double btw(const CosmoRec &r, int kind, T z1, T z2) {
+    switch (kind) {
+    case COSMO_DC: return eval_between<T, COSMO_DC, PAIR>(r, z1, z2);
+    case COSMO_DM: return eval_between<T, COSMO_DM, PAIR>(r, z1, z2);
+    case COSMO_DA: return eval_between<T, COSMO_DA, PAIR>(r, z1, z2);
+    default: return eval_between<T, COSMO_T, PAIR>(r, z1, z2);
+    }
+}
+extern "C" void host_between(const double *prm, int kind, int dt, const double *z1, const double *z2, long n,
+                             double *out) {
+    CosmoRec r;
+    setup_cosmo(prm, r);
+    for (long i = 0; i < n; ++i) {
+        if (!r.valid) { out[i] = __builtin_nan(""); continue; }
+        if (dt == 0) out[i] = r.pair ? btw<float, true>(r, kind, (float)z1[i], (float)z2[i])
+                                     : btw<float, false>(r, kind, (float)z1[i], (float)z2[i]);
+        else out[i] = r.pair ? btw<double, true>(r, kind, z1[i], z2[i]) : btw<double, false>(r, kind, z1[i], z2[i]);
     }
 }

@@ -126,3 +126,68 @@ def test_structured_rf_rd_match_oracle(libs, model):
             assert abs(s - ident) <= 10 * tol * (abs(out[1]) + abs(got_rdy) + abs(got_rdz)), (dt, pair, x, a, b)
             worst[dt] = max(worst[dt], max(errs))
     print("max relative error", worst)
+
+
+KIND_BTW = {"DC": 0, "DM": 1, "T": 4, "DA": 6}
+
+
+def host_between(lib, p, kind, dt, z1, z2):
+    z1 = np.ascontiguousarray(z1, dtype=np.float64)
+    z2 = np.ascontiguousarray(z2, dtype=np.float64)
+    out = np.zeros(z1.size)
+    lib.host_between(np.ascontiguousarray(p, dtype=np.float64).ctypes.data_as(ctypes.c_void_p), KIND_BTW[kind], dt,
+                     z1.ctypes.data_as(ctypes.c_void_p), z2.ctypes.data_as(ctypes.c_void_p), ctypes.c_long(z1.size),
+                     out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def between_pairs(rng, n):
+    """Seeded limit pairs: log-uniform z1 on [1e-4, 10], z2 = z1 + a log-uniform step on
+    [1e-6, 10] (close planes to long baselines), some reversed, some z2 = inf."""
+    z1 = 10.0 ** rng.uniform(-4, 1, n)
+    z2 = z1 + 10.0 ** rng.uniform(-6, 1, n)
+    flip = rng.random(n) < 0.2
+    z1[flip], z2[flip] = z2[flip], z1[flip].copy()
+    z2[rng.random(n) < 0.1] = np.inf
+    return z1, z2
+
+
+def _between_cases():
+    p4, _, _ = workloads.config4(n_per_family=4, n_z=8, seed=23)
+    p2, _ = workloads.config2(n_cosmo=16, n_z=8, seed=23)
+    return np.concatenate([p4, p2])
+
+
+@pytest.mark.parametrize("model", ["exact", "noisy"])
+@pytest.mark.parametrize("kind", ["DC", "DM", "DA", "T"])
+def test_between_formulas_match_oracle(libs, kind, model):
+    """between.hpp (eqs. 3.7-3.8 with both limits per lane; z2 = inf by the limit form)
+    against the oracle's quadrature from z1 to z2: FP64 <= 1e-12 relative, FP32 <= 1e-6
+    relative (D_M and D_A relative to the conditioning scale |D_M| + |C chi| D_H as in
+    the one-sided tests), at the FP32-rounded limits for FP32."""
+    rng = np.random.default_rng(5)
+    params = _between_cases()
+    for c in range(params.shape[0]):
+        z1, z2 = between_pairs(rng, 60)
+        if kind in ("DM", "DA"):
+            z2[np.isinf(z2)] = 1e4  # the transverse distances at infinity are covered by DC
+        for dt, tol in ((1, 1e-12), (0, 1e-6)):
+            if dt == 1 and model == "noisy":
+                continue
+            a = z1.astype(np.float32).astype(np.float64) if dt == 0 else z1
+            b = z2.astype(np.float32).astype(np.float64) if dt == 0 else z2
+            ref = oracle.between(kind, params[c:c + 1], a, b)[0]
+            got = host_between(libs[model], params[c], kind, dt, a, b)
+            fin = np.isfinite(ref)
+            if kind in ("DM", "DA"):
+                chi = oracle.between("DC", params[c:c + 1], a, b)[0]
+                ok = 1 - params[c, 1:].sum()
+                h = 299792.458 / params[c, 0]
+                sk = np.sqrt(abs(ok)) if ok != 0 else 0.0
+                cc = np.cosh(sk * chi / h) if ok > 0 else (np.cos(sk * chi / h) if ok < 0 else 1.0)
+                scale = np.abs(ref) + np.abs(cc * chi) / (1 + (b if kind == "DA" else 0))
+            else:
+                scale = np.abs(ref)
+            e = np.abs(got - ref)[fin] / np.maximum(scale[fin], 1e-300)
+            assert e.size and e.max() <= tol, (kind, model, dt, c, e.max(), a[fin][np.argmax(e)], b[fin][np.argmax(e)])
+            assert np.all(got[a == b] == 0.0)
