@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--paths", default="f32,f64")
     ap.add_argument("--skip-likelihood", action="store_true", help="skip the SN likelihood workload timing")
     ap.add_argument("--skip-workloads", action="store_true", help="skip the timing of the other workloads")
+    ap.add_argument("--skip-between", action="store_true",
+                    help="skip the timing of the observables between two redshifts")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run one 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -225,6 +227,30 @@ def main():
                           "loglike_c0": float(ll[0].item())}
         results["config3_loglike"] = {"workload": f"Gaussian log-likelihood of {zs.size} SN magnitudes for "
                                                   f"{th.shape[0]} parameter samples, value + gradient per step", **like}
+
+    # observables between two redshifts on the large batch's cosmologies: lens-source
+    # pairs (chi, D_M, D_A from z_l to z_s) and the age t(z, inf), 1e6 shared limit
+    # pairs per cosmology, forward per call
+    if not args.skip_between:
+        z1, z2 = workloads.lensing_pairs(n=n_z)
+        zage = workloads.age_redshifts(n=n_z)
+        btw = {"workload": f"{n_c} cosmologies x {n_z} shared limit pairs: lens-source (z1 ~ U(0.05, 1.5), "
+                           "z2 = z1 + U(0.01, 2)) and the age t(z, inf) (z ~ U(0, 20))", "evals": evals}
+        for path in args.paths.split(","):
+            dt = torch.float32 if path == "f32" else torch.float64
+            a, b = torch.tensor(z1, dtype=dt, device=dev), torch.tensor(z2, dtype=dt, device=dev)
+            za = torch.tensor(zage, dtype=dt, device=dev)
+            zinf = torch.full_like(za, float("inf"))
+            for label, kind, lo, hi in (("DC_lens", "DC", a, b), ("DA_lens", "DA", a, b), ("T_age", "T", za, zinf)):
+                def fb():
+                    return cosmo.cosmo_distance_between(kind, p, lo, hi, workspace=ws)
+                fb()
+                ev, _, _ = timed(fb, max(2, args.steps // 2), stream, torch)
+                btw[f"{path}_{label}_ms"] = float(np.median(ev))
+                btw[f"{path}_{label}_evals_per_s"] = evals / (np.median(ev) * 1e-3)
+            del a, b, za, zinf
+            torch.cuda.empty_cache()
+        results["between"] = btw
 
     # the other workloads, forward and value + gradient per call (gradient of the sum of
     # the output with a unit cotangent), each output kind the workload names

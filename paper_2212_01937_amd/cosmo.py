@@ -27,8 +27,8 @@ INFO = {"CUBIC": 0x1, "QUARTIC": 0x2, "THREE_REAL": 0x4, "YELLOW": 0x8, "RED": 0
 
 # every function declared in include/cosmo.h
 EXPORTS = ("cosmo_workspace_size", "cosmo_roots", "carlson_rf", "carlson_rd", "carlson_rj",
-           "carlson_rc", "cosmo_distance", "cosmo_distance_vjp", "cosmo_distance_jac", "cosmo_gaussian_loglike",
-           "cosmo_version")
+           "carlson_rc", "cosmo_distance", "cosmo_distance_between", "cosmo_distance_vjp", "cosmo_distance_jac",
+           "cosmo_gaussian_loglike", "cosmo_version")
 
 _lib = None
 
@@ -54,6 +54,8 @@ def load():
     lib.carlson_rc.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp]
     lib.cosmo_distance.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, i32p, vp,
                                    ctypes.c_size_t, vp]
+    lib.cosmo_distance_between.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, vp, i64, i64, vp, i32p, vp,
+                                           ctypes.c_size_t, vp]
     lib.cosmo_distance_vjp.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, vp, vp,
                                        i32p, vp, ctypes.c_size_t, vp]
     lib.cosmo_distance_jac.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, i32p, vp,
@@ -186,6 +188,33 @@ def cosmo_distance(kind, params, z, info=False, workspace=None):
         rc = lib.cosmo_distance(KINDS[kind], DTYPES[zc.dtype], _ptr(p), n_c, _ptr(zc), n_z, stride,
                                 _ptr(out), _ptr(inf), _ptr(ws), ws.numel(), _stream(p.device))
     _check(rc, "cosmo_distance")
+    return (out, inf) if info else out
+
+
+def cosmo_distance_between(kind, params, z1, z2, info=False, workspace=None):
+    """Observable `kind` ('DC', 'DM', 'DA', 'T') between redshifts z1 and z2 (either
+    order; z2 may be +inf: chi(z1, inf), D_M(z1, inf), D_A = 0, the age t(z1, inf)),
+    shape [n_cosmo, n_z] in the dtype of z1.  z1 and z2: same shape and dtype, [n_z]
+    shared by all cosmologies or [n_cosmo, n_z]."""
+    lib = load()
+    p = _params(params)
+    n_c = p.shape[0]
+    a, n_z, stride, _ = _z_layout(z1, n_c)
+    _need_gpu(z2, "z2")
+    if z2.shape != z1.shape or z2.dtype != z1.dtype:
+        raise CosmoError("z1 and z2 must have the same shape and dtype")
+    b = z2.contiguous()
+    a = a.contiguous()
+    stride = 0 if a.dim() == 1 else n_z
+    if a.device != p.device or b.device != p.device:
+        raise CosmoError("params, z1 and z2 must be on the same device")
+    out = torch.empty((n_c, n_z), dtype=a.dtype, device=p.device)
+    inf = torch.empty(n_c, dtype=torch.int32, device=p.device) if info else None
+    ws = workspace if workspace is not None else _workspace(n_c, n_z, p.device)
+    with torch.cuda.device(p.device):
+        rc = lib.cosmo_distance_between(KINDS[kind], DTYPES[a.dtype], _ptr(p), n_c, _ptr(a), _ptr(b), n_z, stride,
+                                        _ptr(out), _ptr(inf), _ptr(ws), ws.numel(), _stream(p.device))
+    _check(rc, "cosmo_distance_between")
     return (out, inf) if info else out
 
 

@@ -13,6 +13,9 @@ Workloads (sizes are n_cosmo x n_z):
   3  mock SN Ia likelihood, 64 parameter samples x 1e6 SNe with p(z) ~ z^2 on [0.01, 1.5]
   4  near-degenerate stress set, 1024 x 4096 shared log-uniform z in [1e-5, 1e3]
   5  large batch, 256 x 1e6 shared z ~ U(0.01, 2.3)
+Limit pairs for the observables between two redshifts (the cosmologies of 5):
+  lensing_pairs  lens z1 ~ U(0.05, 1.5), source z2 = z1 + U(0.01, 2), shared
+  age_redshifts  z ~ U(0, 20) for t(z, inf)
 """
 import numpy as np
 
@@ -175,6 +178,21 @@ def config5(n_cosmo=256, n_z=10 ** 6, seed=None):
             rows.append(row)
     z = np.sort(rng.uniform(0.01, 2.3, size=n_z))
     return np.array(rows), z
+
+
+def lensing_pairs(n=10 ** 6, seed=None):
+    """Lens and source redshifts (z1, z2), z1 ~ U(0.05, 1.5), z2 = z1 + U(0.01, 2),
+    float64, shared by all cosmologies (strong-lensing time-delay and D_A(z_l, z_s)
+    geometry)."""
+    rng = _rng(6, seed)
+    z1 = rng.uniform(0.05, 1.5, n)
+    z2 = z1 + rng.uniform(0.01, 2.0, n)
+    return z1, z2
+
+
+def age_redshifts(n=10 ** 6, seed=None):
+    """Redshifts z ~ U(0, 20) (float64) for the age t(z, inf)."""
+    return _rng(7, seed).uniform(0.0, 20.0, n)
 
 
 def cotangent_seed():

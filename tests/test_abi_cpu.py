@@ -80,3 +80,35 @@ def test_loglike_and_jacobian_argument_errors(lib):
     # missing Jacobian buffer
     assert lib.cosmo_distance_jac(0, 1, dummy, 1, dummy, 1, 0, null, null, null, null, 0, null) == E_ARG
     assert lib.cosmo_distance_jac(0, 1, dummy, -1, dummy, 1, 0, null, dummy, null, null, 0, null) == E_ARG
+
+
+def test_between_argument_errors(lib):
+    E_ARG, E_KIND, E_DTYPE = -1, -2, -3
+    dummy = ctypes.c_void_p(0x1000)
+    null = None
+    # kinds outside (DC, DM, DA, T): D_L, mu, X
+    for k in (2, 3, 5, 17):
+        assert lib.cosmo_distance_between(k, 1, dummy, 1, dummy, dummy, 1, 0, dummy, null, null, 0, null) == E_KIND
+    assert lib.cosmo_distance_between(0, 4, dummy, 1, dummy, dummy, 1, 0, dummy, null, null, 0, null) == E_DTYPE
+    # a missing limit or output, negative sizes
+    assert lib.cosmo_distance_between(0, 1, dummy, 1, null, dummy, 1, 0, dummy, null, null, 0, null) == E_ARG
+    assert lib.cosmo_distance_between(0, 1, dummy, 1, dummy, null, 1, 0, dummy, null, null, 0, null) == E_ARG
+    assert lib.cosmo_distance_between(4, 1, dummy, 1, dummy, dummy, 1, 0, null, null, null, 0, null) == E_ARG
+    assert lib.cosmo_distance_between(0, 1, dummy, 1, dummy, dummy, -3, 0, dummy, null, null, 0, null) == E_ARG
+    assert lib.cosmo_distance_between(0, 1, dummy, 1, dummy, dummy, 1, -1, dummy, null, null, 0, null) == E_ARG
+    assert lib.cosmo_distance_between(6, 1, null, 0, null, null, 0, 0, null, null, null, 0, null) == 0
+
+
+def test_binding_declares_every_argument(lib):
+    """Every entry point of the binding has ctypes argument types, one per parameter
+    of its declaration in include/cosmo.h (without them, 64-bit sizes and strides
+    passed on the stack would be truncated to 32 bits with undefined upper halves)."""
+    src = open(os.path.join(ROOT, "include", "cosmo.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    for m in re.finditer(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(([^)]*)\)\s*;", src, flags=re.M):
+        name, params = m.group(1), m.group(2).strip()
+        n_params = 0 if params in ("", "void") else params.count(",") + 1
+        fn = getattr(lib, name)
+        if n_params == 0:
+            continue
+        assert fn.argtypes is not None and len(fn.argtypes) == n_params, (name, n_params, fn.argtypes)
