@@ -108,7 +108,10 @@ def test_between_consistency(dt):
     z = np.sort(rng.uniform(0.001, 8.0, (3, 600)), axis=0)
     za, zb, zc = (torch.tensor(v, dtype=dt, device=DEV) for v in z)
     zero = torch.zeros_like(za)
-    tol = 1e-13 if dt == torch.float64 else 4e-7
+    # FP32: both entry points are within 1e-6 of the oracle; the one-sided one takes the
+    # lower limit's square roots from FP64 constants rounded once, this one forms them
+    # in FP32 at run time, so the two differ by up to twice that bound
+    tol = 1e-13 if dt == torch.float64 else 2e-6
     for kind in ("DC", "T"):
         one = cosmo.cosmo_distance(kind, p, zb)
         btw = cosmo.cosmo_distance_between(kind, p, zero, zb)
