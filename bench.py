@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--skip-workloads", action="store_true", help="skip the timing of the other workloads")
     ap.add_argument("--skip-between", action="store_true",
                     help="skip the timing of the observables between two redshifts")
+    ap.add_argument("--skip-snia", action="store_true",
+                    help="skip the timing of the supernova model's variational-inference step")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run one 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -251,6 +253,42 @@ def main():
             del a, b, za, zinf
             torch.cuda.empty_cache()
         results["between"] = btw
+
+    # the supernova model of sec. 4: one variational-inference step (4 reparametrised
+    # samples of the partial multivariate normal guide, ELBO, backward through the fused
+    # likelihood, Adam) on a mock catalogue of 1e6 supernovae
+    if not args.skip_snia:
+        from paper_2212_01937_amd import snia
+        n_sn, n_s = 10 ** 6, 4
+        zs, ez, em, th = workloads.snia_mock(n_sn)
+        zs_t = torch.tensor(zs, device=dev)
+        pth = torch.tensor([[snia.H0, th[0], th[1], 0.0]], device=dev)
+        mu_true = cosmo.cosmo_distance("MU", pth, zs_t)[0]
+        zhat = zs_t + (1 + zs_t) * snia.SIGMA_Z * torch.tensor(ez, device=dev)
+        muhat = mu_true + snia.SIGMA_MU * torch.tensor(em, device=dev)
+        sn = {"workload": f"supernova model (sec. 4), {n_sn} mock SNe, {n_s} ELBO samples per step, "
+                          "PMVN guide, Adam", "sn_evals_per_step": n_s * n_sn}
+        for path in args.paths.split(","):
+            dt = torch.float32 if path == "f32" else torch.float64
+            guide = snia.PMVNGuide(zhat, dtype=dt)
+            opt = torch.optim.Adam(guide.parameters(), lr=0.02)
+            gsn = torch.Generator(device=dev)
+            gsn.manual_seed(1)
+
+            def vi_step():
+                opt.zero_grad(set_to_none=True)
+                loss = -snia.elbo(guide, zhat, muhat, n_s, gsn)
+                loss.backward()
+                opt.step()
+                return loss
+            for _ in range(max(1, args.warmup)):
+                vi_step()
+            ev, wall, _ = timed(vi_step, max(2, args.steps // 2), stream, torch)
+            sn[f"{path}_ms_per_step"] = float(np.median(ev))
+            sn[f"{path}_sn_evals_per_s"] = n_s * n_sn / (np.median(ev) * 1e-3)
+            del guide, opt
+            torch.cuda.empty_cache()
+        results["snia_vi"] = sn
 
     # the other workloads, forward and value + gradient per call (gradient of the sum of
     # the output with a unit cotangent), each output kind the workload names

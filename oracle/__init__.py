@@ -115,6 +115,41 @@ def between(kind, params, z1, z2, nthreads=0):
     return out
 
 
+def snia_log_joint(theta, z, zhat, muhat, h0=70.0, sigma_mu=0.14, sigma_z=0.04, beta=3.0, shape=3.0,
+                   grad=False):
+    """Log joint density of the supernova model of sec. 4, per sample, up to the
+    constants of the two Gaussian likelihoods (written term by term):
+        sum_s  -1/2 ((muhat_s - mu(z_s; theta)) / sigma_mu)^2
+             + [-1/2 ((zhat_s - z_s) / ((1 + z_s) sigma_z))^2 - log((1 + z_s) sigma_z)]
+             + [(shape - 1) log z_s - beta z_s + shape log beta - lgamma(shape)]
+    with theta = (Om0, OL0), Or0 = 0, H0 fixed; mu from this oracle's quadrature.
+    theta (S, 2), z (S, N), zhat and muhat (N,).  Returns lp (S,) and, with grad,
+    (dlp/dtheta (S, 2), dlp/dz (S, N))."""
+    import math
+    th = np.asarray(theta, dtype=np.float64).reshape(-1, 2)
+    zz = np.asarray(z, dtype=np.float64).reshape(th.shape[0], -1)
+    zh = np.asarray(zhat, dtype=np.float64)
+    mh = np.asarray(muhat, dtype=np.float64)
+    S, N = zz.shape
+    params = np.column_stack([np.full(S, h0), th[:, 0], th[:, 1], np.zeros(S)])
+    if grad:
+        mu, g = distance("MU", params, zz, shared_z=False, grad=True)
+    else:
+        mu = distance("MU", params, zz, shared_z=False)
+    r = (mh - mu) / sigma_mu
+    sd = (1.0 + zz) * sigma_z
+    q = (zh - zz) / sd
+    lp = (-0.5 * r ** 2 - 0.5 * q ** 2 - np.log(sd) + (shape - 1.0) * np.log(zz) - beta * zz).sum(1)
+    lp += N * (shape * math.log(beta) - math.lgamma(shape))
+    if not grad:
+        return lp
+    w = r / sigma_mu  # d(-1/2 r^2)/dmu
+    dth = np.stack([(w * g[:, :, 1]).sum(1), (w * g[:, :, 2]).sum(1)], axis=1)
+    # d/dz of the photometric term: q^2 / (1 + z) + q / sd - 1 / (1 + z)
+    dz = w * g[:, :, 4] + q / sd + q ** 2 / (1.0 + zz) - 1.0 / (1.0 + zz) + (shape - 1.0) / zz - beta
+    return lp, dth, dz
+
+
 def E(params, z):
     """E(z) of eq. 2.2 for one cosmology (H0, Om0, OL0, Or0)."""
     lib = _load()

@@ -1,0 +1,120 @@
+"""Supernova Ia cosmology model of sec. 4 with variational inference, the distance
+path as its inner loop.
+
+Model (sec. 4, fig. 4b), for N supernovae with observed redshifts zhat_s and distance
+moduli muhat_s:
+    Om0, OL0               free (flat prior over the region where the method applies)
+    z_s                    ~ Gamma(shape 3, rate beta = 3)                (the redshift prior)
+    zhat_s | z_s           ~ N(z_s, (1 + z_s)^2 sigma_z^2),  sigma_z = 0.04 (photometric toy model)
+    muhat_s | z_s, theta   ~ N(mu(z_s; theta), sigma_mu^2),  sigma_mu = 0.14
+with radiationless LambdaCDM (Or0 = 0) and H0 fixed (it is degenerate with the
+absolute magnitude).  mu(z; theta) and its gradients with respect to theta and every
+z_s come from one fused pass of the HIP library (cosmo_gaussian_loglike).
+
+Guide: a partial multivariate normal (sec. 4) -- a bivariate normal for (Om0, OL0) and,
+per supernova, a normal for zeta_s = log z_s whose mean depends linearly on the
+global parameters (correlations between each latent redshift and the cosmology are
+kept, those between different supernovae are not):
+    theta ~ N(m, L L^T),   zeta_s | theta ~ N(a_s + b_s . (theta - m), s_s^2),   z_s = exp(zeta_s).
+The ELBO is estimated with S reparametrised samples per step and maximised with Adam.
+"""
+import math
+
+import torch
+
+from . import cosmo
+
+SIGMA_MU = 0.14
+SIGMA_Z = 0.04
+BETA = 3.0
+GAMMA_SHAPE = 3.0
+H0 = 70.0
+
+
+def params_of(theta):
+    """(S, 2) of (Om0, OL0) -> (S, 4) rows (H0, Om0, OL0, Or0 = 0), float64."""
+    s = theta.shape[0]
+    h = torch.full((s, 1), H0, dtype=torch.float64, device=theta.device)
+    zero = torch.zeros((s, 1), dtype=torch.float64, device=theta.device)
+    return torch.cat([h, theta.to(torch.float64), zero], dim=1)
+
+
+def log_joint(theta, z, zhat, muhat):
+    """log p(theta, z, zhat, muhat) per sample, up to a constant: theta (S, 2) float64,
+    z (S, N) latent redshifts in the compute dtype (float32 or float64), zhat and
+    muhat (N,).  Differentiable in theta and z.  Returns (S,) float64."""
+    S, N = z.shape
+    obs = muhat.to(z.dtype).expand(S, N).contiguous()
+    ll_mu = cosmo.gaussian_loglike("MU", params_of(theta), z, obs, SIGMA_MU)
+    zd = z.to(torch.float64)
+    zh = zhat.to(torch.float64)
+    sd = (1.0 + zd) * SIGMA_Z
+    ll_z = (-0.5 * ((zh - zd) / sd) ** 2 - torch.log(sd)).sum(1)
+    lp_z = ((GAMMA_SHAPE - 1.0) * torch.log(zd) - BETA * zd).sum(1) + N * (
+        GAMMA_SHAPE * math.log(BETA) - math.lgamma(GAMMA_SHAPE))
+    return ll_mu + ll_z + lp_z
+
+
+class PMVNGuide(torch.nn.Module):
+    """Partial multivariate normal proposal over (Om0, OL0, {log z_s})."""
+
+    def __init__(self, zhat, theta0=(0.3, 0.7), dtype=torch.float32):
+        super().__init__()
+        dev = zhat.device
+        n = zhat.shape[0]
+        self.dtype = dtype
+        self.m = torch.nn.Parameter(torch.tensor(theta0, dtype=torch.float64, device=dev))
+        self.l_raw = torch.nn.Parameter(torch.tensor([math.log(0.05), 0.0, math.log(0.05)], dtype=torch.float64,
+                                                     device=dev))  # log diag 0, off-diag, log diag 1
+        zc = zhat.to(torch.float64).clamp_min(0.02)
+        self.a = torch.nn.Parameter(torch.log(zc))
+        self.b = torch.nn.Parameter(torch.zeros((n, 2), dtype=torch.float64, device=dev))
+        self.log_s = torch.nn.Parameter(torch.log((1.0 + zc) * SIGMA_Z / zc))
+
+    def chol(self):
+        l00, l10, l11 = torch.exp(self.l_raw[0]), self.l_raw[1], torch.exp(self.l_raw[2])
+        zero = torch.zeros((), dtype=torch.float64, device=l00.device)
+        return torch.stack([torch.stack([l00, zero]), torch.stack([l10, l11])])
+
+    def sample(self, n_samples, gen):
+        """Reparametrised draws: theta (S, 2), zeta (S, N) and log q(theta, zeta) (S,)."""
+        dev = self.m.device
+        n = self.a.shape[0]
+        L = self.chol()
+        eg = torch.randn((n_samples, 2), dtype=torch.float64, device=dev, generator=gen)
+        el = torch.randn((n_samples, n), dtype=torch.float64, device=dev, generator=gen)
+        dtheta = eg @ L.T
+        theta = self.m + dtheta
+        s = torch.exp(self.log_s)
+        # the per-supernova regression on the globals as two broadcast multiply-adds (a
+        # (N, 2) x (2, S) product would go to a GEMM shaped badly for N ~ 1e6)
+        zeta = self.a + dtheta[:, 0:1] * self.b[:, 0] + dtheta[:, 1:2] * self.b[:, 1] + s * el
+        logq = (-0.5 * (eg ** 2).sum(1) - torch.log(torch.diagonal(L)).sum()
+                - 0.5 * (el ** 2).sum(1) - self.log_s.sum()
+                - 0.5 * (n + 2) * math.log(2 * math.pi))
+        return theta, zeta, logq
+
+
+def elbo(guide, zhat, muhat, n_samples, gen):
+    """Monte-Carlo ELBO estimate (mean over n_samples draws): E_q[log p(theta, z(zeta))
+    + sum zeta (the Jacobian of z = exp(zeta)) - log q(theta, zeta)] + const."""
+    theta, zeta, logq = guide.sample(n_samples, gen)
+    z = torch.exp(zeta).to(guide.dtype)
+    lp = log_joint(theta, z, zhat, muhat)
+    return (lp + zeta.sum(1) - 0.5 * zhat.shape[0] * math.log(2 * math.pi) - logq).mean()
+
+
+def fit(zhat, muhat, steps=2000, n_samples=4, lr=0.02, dtype=torch.float32, seed=0, theta0=(0.3, 0.7)):
+    """Maximise the ELBO with Adam; returns the guide and the ELBO trace."""
+    guide = PMVNGuide(zhat, theta0=theta0, dtype=dtype)
+    opt = torch.optim.Adam(guide.parameters(), lr=lr)
+    gen = torch.Generator(device=zhat.device)
+    gen.manual_seed(seed)
+    trace = []
+    for _ in range(steps):
+        opt.zero_grad(set_to_none=True)
+        loss = -elbo(guide, zhat, muhat, n_samples, gen)
+        loss.backward()
+        opt.step()
+        trace.append(-float(loss.detach()))
+    return guide, trace

@@ -16,6 +16,8 @@ Workloads (sizes are n_cosmo x n_z):
 Limit pairs for the observables between two redshifts (the cosmologies of 5):
   lensing_pairs  lens z1 ~ U(0.05, 1.5), source z2 = z1 + U(0.01, 2), shared
   age_redshifts  z ~ U(0, 20) for t(z, inf)
+Supernova model of sec. 4 (mock catalogue):
+  snia_mock      true z ~ Gamma(3, rate 3), standard-normal noise draws for zhat, muhat
 """
 import numpy as np
 
@@ -193,6 +195,17 @@ def lensing_pairs(n=10 ** 6, seed=None):
 def age_redshifts(n=10 ** 6, seed=None):
     """Redshifts z ~ U(0, 20) (float64) for the age t(z, inf)."""
     return _rng(7, seed).uniform(0.0, 20.0, n)
+
+
+def snia_mock(n=1000, seed=None):
+    """Mock supernova catalogue draws for the model of sec. 4: true redshifts
+    z ~ Gamma(shape 3, rate 3) and two standard-normal noise vectors; the caller forms
+    zhat = z + (1 + z) sigma_z eps_z and muhat = mu(z; theta_true) + sigma_mu eps_mu.
+    True cosmology (Om0, OL0) = (0.3, 0.7), Or0 = 0, H0 = 70.
+    Returns z (n,), eps_z (n,), eps_mu (n,), theta_true (2,)."""
+    rng = _rng(8, seed)
+    z = rng.gamma(3.0, 1.0 / 3.0, n)
+    return z, rng.standard_normal(n), rng.standard_normal(n), np.array([0.3, 0.7])
 
 
 def cotangent_seed():

@@ -546,3 +546,55 @@ def test_between_reversed_and_tiny_radiation():
     chi0 = _bt("DC", (70.0, 0.3, 0.7, 0.0), zz, inf)
     chie = _bt("DC", (70.0, 0.3, 0.7 - eps, eps), zz, inf)
     assert rel(chie, chi0 - DH(70.0) * 2 * math.sqrt(eps) / 0.3) < 1e-13
+
+
+# --------------------------------------------------------------------------- supernova model (sec. 4)
+def _mu_eds(h0, z):
+    x = 1.0 + np.asarray(z, dtype=float)
+    dl = x * 2 * DH(h0) * (1 - 1 / np.sqrt(x))
+    return 5 * np.log10(dl) + 25
+
+
+def test_snia_log_joint_value():
+    """Einstein-de Sitter (Om0 = 1, OL0 = 0): mu in closed form; the photometric
+    likelihood and the Gamma(3, rate 3) prior against scipy.stats."""
+    from scipy import stats
+    theta = np.array([[1.0, 0.0]])
+    z = np.array([[0.35, 1.2, 2.5]])
+    zhat = np.array([0.31, 1.3, 2.45])
+    z_mu = np.array([0.4, 1.2, 2.0])  # muhat = mu_EdS at these redshifts
+    muhat = _mu_eds(70.0, z_mu)
+    lp = oracle.snia_log_joint(theta, z, zhat, muhat)
+    ref = (-0.5 * ((muhat - _mu_eds(70.0, z[0])) / 0.14) ** 2
+           + stats.norm.logpdf(zhat, z[0], (1 + z[0]) * 0.04) + 0.5 * math.log(2 * math.pi)
+           + stats.gamma.logpdf(z[0], a=3.0, scale=1 / 3.0)).sum()
+    assert abs(lp[0] - ref) <= 1e-12 * abs(ref)
+
+
+def test_snia_log_joint_gradient_fd():
+    """Gradients with respect to (Om0, OL0) and every z_s against central differences
+    of the value (Richardson-extrapolated)."""
+    rng = np.random.default_rng(2)
+    theta = np.array([[0.31, 0.68], [0.25, 0.8]])
+    z = rng.gamma(3.0, 1 / 3.0, (2, 5)) + 0.05
+    zhat = z[0] + 0.04 * (1 + z[0]) * rng.standard_normal(5)
+    muhat = oracle.distance("MU", [[70.0, 0.3, 0.7, 0.0]], z[0])[0] + 0.14 * rng.standard_normal(5)
+    lp, dth, dz = oracle.snia_log_joint(theta, z, zhat, muhat, grad=True)
+
+    def fd(f, h):
+        d1 = (f(h) - f(-h)) / (2 * h)
+        d2 = (f(h / 2) - f(-h / 2)) / h
+        return (4 * d2 - d1) / 3
+
+    for a in range(2):
+        def f(h, a=a):
+            t = theta.copy()
+            t[:, a] += h
+            return oracle.snia_log_joint(t, z, zhat, muhat)
+        assert rel(dth[:, a], fd(f, 1e-4)) < 1e-7, a
+    for j in range(5):
+        def g(h, j=j):
+            zz = z.copy()
+            zz[:, j] += h
+            return oracle.snia_log_joint(theta, zz, zhat, muhat)
+        assert rel(dz[:, j], fd(g, 1e-4)) < 1e-7, j
