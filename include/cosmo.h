@@ -53,10 +53,11 @@ typedef enum { COSMO_F32 = 0, COSMO_F64 = 1 } cosmo_dtype;
  *  MU: distance modulus 5 log10(D_L / 10 pc) (fn. 22), mag
  *  T : time coordinate / lookback time t(0, z) (eq. 2.4), Gyr
  *  X : absorption distance d_abs (eq. 2.5), Mpc
- *  DA: angular-diameter distance D_M / (1+z), Mpc                                */
+ *  DA: angular-diameter distance D_M / (1+z), Mpc
+ *  VC: all-sky comoving volume 4 pi int_0^z D_M^2 dD_C (sec. 2.1), Mpc^3          */
 typedef enum {
     COSMO_DC = 0, COSMO_DM = 1, COSMO_DL = 2, COSMO_MU = 3,
-    COSMO_T = 4, COSMO_X = 5, COSMO_DA = 6
+    COSMO_T = 4, COSMO_X = 5, COSMO_DA = 6, COSMO_VC = 7
 } cosmo_kind;
 
 /* Bits of the per-cosmology `info` word (int32).                                */

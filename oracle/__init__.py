@@ -17,7 +17,7 @@ import numpy as np
 
 from . import build as _build
 
-KINDS = {"DC": 0, "DM": 1, "DL": 2, "MU": 3, "T": 4, "X": 5, "DA": 6}
+KINDS = {"DC": 0, "DM": 1, "DL": 2, "MU": 3, "T": 4, "X": 5, "DA": 6, "VC": 7}
 CARLSON = {"RF": 0, "RD": 1, "RJ": 2, "RC": 3}
 
 _lib = None

@@ -49,6 +49,7 @@
 #define C_KMS 299792.458
 #define MPC_KM 3.0856775814913673e19
 #define GYR_S 3.15576e16
+#define FOUR_PI 12.566370614359172953850573533118
 
 /* ---------------------------------------------------------------------------
  * 7/15-point Gauss-Kronrod rule on [-1, 1] (nodes/weights of QUADPACK qk15).
@@ -235,7 +236,7 @@ static double dimless_between(const struct cosmo *c, int which, double z1, doubl
 /* ---------------------------------------------------------------------------
  * Output kinds (numbering matches the public ABI's enumeration of observables).
  * ------------------------------------------------------------------------- */
-enum { K_DC = 0, K_DM = 1, K_DL = 2, K_MU = 3, K_T = 4, K_X = 5, K_DA = 6 };
+enum { K_DC = 0, K_DM = 1, K_DL = 2, K_MU = 3, K_T = 4, K_X = 5, K_DA = 6, K_VC = 7 };
 
 /* Curvature transform S_k(chi) = sinh(sqrt(Ok) chi)/sqrt(Ok) (Ok > 0), chi (Ok = 0),
  * sin(sqrt(-Ok) chi)/sqrt(-Ok) (Ok < 0), with chi = D_C/D_H dimensionless.
@@ -272,10 +273,13 @@ static void curvature_transform(double ok, double chi, double *S, double *dS_dch
     }
 }
 
+static double volume_one(const double *prm, double z, double *grad, double *errest);
+
 /* One evaluation: value of `kind` at (cosmology, z) and, if grad != NULL, its
  * gradient with respect to (H0, Om, OL, Or, z) in grad[0..4]. */
 static double eval_one(int kind, const double *prm, double z, double *grad, double *errest)
 {
+    if (kind == K_VC) return volume_one(prm, z, grad, errest);
     struct cosmo c;
     c.H0 = prm[0]; c.Om = prm[1]; c.OL = prm[2]; c.Or = prm[3];
     c.Ok = 1.0 - c.Om - c.OL - c.Or;
@@ -355,13 +359,58 @@ static double eval_one(int kind, const double *prm, double z, double *grad, doub
     return val;
 }
 
+/* All-sky comoving volume V_C(z) = 4 pi int_0^z D_M(z')^2 dD_C(z')  (sec. 2.1; dD_C =
+ * (c/H0) dz'/E), by quadrature in u = ln(1+z') over this file's own D_M(z') (itself a
+ * quadrature).  The parameter gradient is the same integral of the derivatives of the
+ * integrand (Leibniz rule), with D_M's gradient from eval_one; d/dz by the fundamental
+ * theorem of calculus. */
+struct vctx { const double *prm; int a; }; /* a < 0: value; 0..3: d/d(H0, Om, OL, Or) */
+
+static double vol_integrand(double u, const void *vctx)
+{
+    const struct vctx *k = (const struct vctx *)vctx;
+    const double *prm = k->prm;
+    struct cosmo c = {prm[0], prm[1], prm[2], prm[3], 1.0 - prm[1] - prm[2] - prm[3]};
+    double x = exp(u), z = expm1(u);
+    double g[5];
+    double dm = eval_one(K_DM, prm, z, k->a >= 0 ? g : NULL, NULL);
+    double e2 = E2_of_x(&c, x);
+    double f = (C_KMS / c.H0) * x / sqrt(e2); /* dD_C/du */
+    if (k->a < 0) return FOUR_PI * dm * dm * f;
+    double df = k->a == 0 ? -f / c.H0 : -0.5 * f * dE2_dparam(k->a, x, z) / e2;
+    return FOUR_PI * (2.0 * dm * g[k->a] * f + dm * dm * df);
+}
+
+static double volume_one(const double *prm, double z, double *grad, double *errest)
+{
+    double err = 0.0;
+    if (z == 0.0) {
+        if (grad) memset(grad, 0, 5 * sizeof(double));
+        if (errest) *errest = 0.0;
+        return 0.0;
+    }
+    struct vctx k = {prm, -1};
+    double val = adapt(vol_integrand, &k, 0.0, log1p(z), 0.0, EPSREL, &err);
+    if (errest) *errest = err;
+    if (grad) {
+        for (int a = 0; a < 4; ++a) {
+            struct vctx ka = {prm, a};
+            grad[a] = adapt(vol_integrand, &ka, 0.0, log1p(z), 0.0, EPSREL, NULL);
+        }
+        struct cosmo c = {prm[0], prm[1], prm[2], prm[3], 1.0 - prm[1] - prm[2] - prm[3]};
+        double dm = eval_one(K_DM, prm, z, NULL, NULL);
+        grad[4] = FOUR_PI * dm * dm * (C_KMS / c.H0) / sqrt(E2_of_x(&c, 1.0 + z));
+    }
+    return val;
+}
+
 /* Batched driver.  params: [n_cosmo][4] = (H0, Om, OL, Or); z[c*z_stride + i];
  * out[c*n_z + i]; grad (nullable): [n_cosmo][n_z][5]; errest (nullable): like out.
  * Returns 0, or -1 on bad arguments.  nthreads <= 0 means "all OpenMP threads". */
 int oracle_eval(int kind, const double *params, long n_cosmo, const double *z, long n_z,
                 long z_stride, double *out, double *grad, double *errest, int nthreads)
 {
-    if (kind < 0 || kind > 6 || n_cosmo < 0 || n_z < 0 || !params || !z || !out) return -1;
+    if (kind < 0 || kind > 7 || n_cosmo < 0 || n_z < 0 || !params || !z || !out) return -1;
     long total = n_cosmo * n_z;
 #ifdef _OPENMP
     int nt = nthreads > 0 ? nthreads : omp_get_max_threads();

@@ -18,7 +18,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcosmo.so")
 
-KINDS = {"DC": 0, "DM": 1, "DL": 2, "MU": 3, "T": 4, "X": 5, "DA": 6}
+KINDS = {"DC": 0, "DM": 1, "DL": 2, "MU": 3, "T": 4, "X": 5, "DA": 6, "VC": 7}
 DTYPES = {torch.float32: 0, torch.float64: 1}
 STATUS = {0: "COSMO_OK", -1: "COSMO_E_ARG", -2: "COSMO_E_KIND", -3: "COSMO_E_DTYPE",
           -4: "COSMO_E_HIP", -5: "COSMO_E_WORKSPACE"}

@@ -557,7 +557,7 @@ int ensure_init() {
     return COSMO_OK;
 }
 
-bool valid_kind(int k) { return k >= COSMO_DC && k <= COSMO_DA; }
+bool valid_kind(int k) { return k >= COSMO_DC && k <= COSMO_VC; }
 bool valid_dtype(int d) { return d == COSMO_F32 || d == COSMO_F64; }
 
 // Scoped workspace: the caller's, or stream-ordered pool memory.
@@ -595,6 +595,7 @@ int launch_forward(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, 
     case COSMO_T: COSMO_FWD(COSMO_T); break;
     case COSMO_X: COSMO_FWD(COSMO_X); break;
     case COSMO_DA: COSMO_FWD(COSMO_DA); break;
+    case COSMO_VC: COSMO_FWD(COSMO_VC); break;
     }
 #undef COSMO_FWD
     return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
@@ -631,6 +632,7 @@ int launch_jac(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int6
     case COSMO_T: COSMO_JAC(COSMO_T); break;
     case COSMO_X: COSMO_JAC(COSMO_X); break;
     case COSMO_DA: COSMO_JAC(COSMO_DA); break;
+    case COSMO_VC: COSMO_JAC(COSMO_VC); break;
     }
 #undef COSMO_JAC
     return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
@@ -668,6 +670,7 @@ int launch_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int6
     case COSMO_T: COSMO_VJP(COSMO_T); break;
     case COSMO_X: COSMO_VJP(COSMO_X); break;
     case COSMO_DA: COSMO_VJP(COSMO_DA); break;
+    case COSMO_VC: COSMO_VJP(COSMO_VC); break;
     }
 #undef COSMO_VJP
 #undef COSMO_VJP_Z

@@ -17,7 +17,7 @@ from paper_2212_01937_amd import cosmo, workloads
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["DC", "DM", "DL", "MU", "T", "X", "DA"]
+KINDS = ["DC", "DM", "DL", "MU", "T", "X", "DA", "VC"]
 TOL = {torch.float64: 1e-10, torch.float32: 1e-4}
 
 
@@ -267,6 +267,19 @@ def jac_check(kind, dt, params, z, shared, label, dev):
         zfull = np.ascontiguousarray(np.broadcast_to(zr, out.shape)) if shared else zr
         _, _, _, agz = ref_vjp(kind, params, zfull, w, False)
         scale[..., 4] = np.maximum(scale[..., 4], agz)
+    if kind == "VC":
+        # V_C = 4 pi D_H^3 G(chi, Ok): d/dtheta = 4 pi D_H^3 (S^2 dchi/dtheta - dG/dOk), two
+        # terms that cancel partly; scale by their sizes (dG/dOk ~ chi^5 / 15 (1 + |Ok chi^2|))
+        zfull = np.ascontiguousarray(np.broadcast_to(zr, out.shape)) if shared else zr
+        dc, gdc = oracle.distance("DC", params, zfull, shared_z=False, grad=True)
+        dm = oracle.distance("DM", params, zfull, shared_z=False)
+        dh = 299792.458 / params[:, :1]
+        ok = (1 - params[:, 1] - params[:, 2] - params[:, 3])[:, None]
+        chi = dc / dh
+        v4 = 4 * np.pi * dh ** 3
+        curv = (np.abs(v4 * (dm / dh) ** 2)[..., None] * np.abs(gdc[..., 1:4]) / dh[..., None]
+                + (v4 * chi ** 5 / 15 * (1 + np.abs(ok * chi ** 2)))[..., None])
+        scale[..., 1:4] = np.maximum(scale[..., 1:4], np.where(undef[..., None], 0.0, curv))
     e = np.where(undef[..., None], 0.0, np.abs(jac - g) / np.maximum(scale, 1e-300))
     tol = np.array([TOL[dt]] * 3 + [5 * TOL[dt] if dt == torch.float32 else TOL[dt], TOL[dt]])
     worst = e.reshape(-1, 5).max(0)

@@ -13,7 +13,7 @@ from paper_2212_01937_amd import cosmo, workloads
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["DC", "DM", "DL", "MU", "T", "X", "DA"]
+KINDS = ["DC", "DM", "DL", "MU", "T", "X", "DA", "VC"]
 TOL = {torch.float64: 1e-12, torch.float32: 1e-6}
 MU_TOL = {torch.float64: 1e-11, torch.float32: 1e-4}
 
@@ -22,7 +22,8 @@ def cond_scale(kind, params, z, ref):
     """Error scale of an observable that applies the curvature transform sinn to
     chi = D_C/D_H: a relative error eps in chi moves it by eps |d out/d chi| chi, which
     beyond the antipode of a closed universe (sin near zero) exceeds eps |out|.
-    Returns |out| + |d out/d chi| chi (mu: 1 + |C chi / S| in units of 5/ln 10)."""
+    Returns |out| + |d out/d chi| chi (mu: 1 + |C chi / S| in units of 5/ln 10; the
+    comoving volume: max(|V|, chi dV/dchi))."""
     params = np.asarray(params, dtype=np.float64).reshape(-1, 4)
     n = params.shape[0]
     ref2 = np.asarray(ref, dtype=np.float64).reshape(n, -1)
@@ -38,6 +39,10 @@ def cond_scale(kind, params, z, ref):
     s = np.where(ok == 0, chi, np.where(ok < 0, np.sin(x), np.sinh(x)) / sk)
     if kind == "MU":
         out = 1.0 + np.abs(c * chi / s)
+    elif kind == "VC":
+        # V_C = 4 pi D_H^3 G(chi): a relative error eps in chi moves it by eps chi dV/dchi
+        # = eps 4 pi D_H^3 chi S^2 (about 3 |V| for small curvature)
+        out = np.maximum(np.abs(ref2), 4 * np.pi * dh ** 3 * chi * s ** 2)
     else:
         factor = {"DM": 1.0, "DL": 1 + zz, "DA": 1 / (1 + zz)}[kind]
         out = np.abs(ref2) + np.abs(dh * c * chi * factor)
@@ -56,7 +61,7 @@ def check(kind, dt, got, ref, label="", params=None, z=None):
     got = np.asarray(got)
     ref = np.asarray(ref)
     scale = None
-    if params is not None and kind in ("DM", "DL", "DA", "MU"):
+    if params is not None and kind in ("DM", "DL", "DA", "MU", "VC"):
         scale = cond_scale(kind, params, z, ref).ravel()
     got = got.ravel()
     ref = ref.ravel()

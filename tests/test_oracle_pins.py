@@ -245,7 +245,7 @@ def _richardson(f, x0, h):
     return (4 * d2 - d1) / 3
 
 
-@pytest.mark.parametrize("kind", ["DC", "DM", "DL", "MU", "T", "X", "DA"])
+@pytest.mark.parametrize("kind", ["DC", "DM", "DL", "MU", "T", "X", "DA", "VC"])
 def test_gradient_vs_richardson_differences(kind):
     """Leibniz-rule gradients vs central differences of the oracle's own values,
     for open and closed curvature."""
@@ -598,3 +598,26 @@ def test_snia_log_joint_gradient_fd():
             zz[:, j] += h
             return oracle.snia_log_joint(theta, zz, zhat, muhat)
         assert rel(dz[:, j], fd(g, 1e-4)) < 1e-7, j
+
+
+
+# --------------------------------------------------------------------------- comoving volume
+def test_comoving_volume_closed_forms():
+    """V_C = 4 pi int D_M^2 dD_C: flat (EdS) 4 pi D_M^3 / 3; Milne (Ok0 = 1, chi = ln(1+z))
+    4 pi D_H^3 (sinh(2 chi)/2 - chi)/2; a closed matter universe (Om0 = 3, Ok0 = -2)
+    4 pi D_H^3 (chi - sin(2 a chi)/(2a)) / (2|Ok0|), a = sqrt(2), chi from Mattig's
+    closed form of D_M."""
+    h0 = 70.0
+    z = np.array([0.05, 0.5, 1.0, 3.0, 10.0])
+    x = 1 + z
+    dm = 2 * DH(h0) * (1 - 1 / np.sqrt(x))
+    assert rel(_ev("VC", (h0, 1.0, 0.0, 0.0), z), 4 * np.pi / 3 * dm ** 3) < 1e-13
+    chi = np.log(x)
+    assert rel(_ev("VC", (h0, 0.0, 0.0, 0.0), z), 4 * np.pi * DH(h0) ** 3 * (np.sinh(2 * chi) / 2 - chi) / 2) < 1e-13
+    om, ok = 3.0, -2.0
+    a = math.sqrt(-ok)
+    # Mattig: D_M = 2 D_H (om z + (om - 2)(sqrt(1 + om z) - 1)) / (om^2 (1 + z))
+    dmm = 2 * DH(h0) * (om * z + (om - 2) * (np.sqrt(1 + om * z) - 1)) / (om ** 2 * x)
+    chi = np.arcsin(a * dmm / DH(h0)) / a  # below the antipode for these z
+    g = (chi - np.sin(2 * a * chi) / (2 * a)) / (2 * abs(ok))
+    assert rel(_ev("VC", (h0, om, 0.0, 0.0), z[:3]), 4 * np.pi * DH(h0) ** 3 * g[:3]) < 1e-12
