@@ -43,7 +43,7 @@ def _load():
         lib.oracle_gk15_panel.restype = ctypes.c_double
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_between.argtypes = [ctypes.c_int, dp, ctypes.c_long, dp, dp, ctypes.c_long, ctypes.c_long,
-                                       dp, ctypes.c_int]
+                                       dp, dp, ctypes.c_int]
         lib.oracle_between.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -87,14 +87,15 @@ def distance(kind, params, z, shared_z=None, grad=False, errest=False, nthreads=
     return res[0] if len(res) == 1 else tuple(res)
 
 
-def between(kind, params, z1, z2, nthreads=0):
+def between(kind, params, z1, z2, grad=False, nthreads=0):
     """Observable `kind` ('DC', 'DM', 'DA', 'T', 'X') between redshifts z1 and z2:
     the integrals of eqs. 2.3-2.5 from z1 to z2 (either order; z2 = inf allowed for
     'DC', 'DM', 'DA' and 'T', the latter being the age t(z1, inf)).  D_M(z1, z2) is
     the curvature transform of chi(z1, z2) and D_A(z1, z2) = D_M(z1, z2)/(1 + z2).
 
     params: (n_cosmo, 4); z1, z2: broadcastable to (n_z,) (shared by all cosmologies)
-    or (n_cosmo, n_z).  Returns (n_cosmo, n_z)."""
+    or (n_cosmo, n_z).  Returns out (n_cosmo, n_z) and, with grad, the derivatives
+    (n_cosmo, n_z, 6) with respect to (H0, Om0, OL0, Or0, z1, z2)."""
     lib = _load()
     p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1, 4))
     n_c = p.shape[0]
@@ -109,10 +110,12 @@ def between(kind, params, z1, z2, nthreads=0):
     a = np.ascontiguousarray(a)
     b = np.ascontiguousarray(b)
     out = np.empty((n_c, n_z))
-    rc = lib.oracle_between(KINDS[kind], _ptr(p), n_c, _ptr(a), _ptr(b), n_z, stride, _ptr(out), int(nthreads))
+    g = np.empty((n_c, n_z, 6)) if grad else None
+    rc = lib.oracle_between(KINDS[kind], _ptr(p), n_c, _ptr(a), _ptr(b), n_z, stride, _ptr(out), _ptr(g),
+                            int(nthreads))
     if rc != 0:
         raise ValueError("oracle_between rejected its arguments")
-    return out
+    return (out, g) if grad else out
 
 
 def snia_log_joint(theta, z, zhat, muhat, h0=70.0, sigma_mu=0.14, sigma_z=0.04, beta=3.0, shape=3.0,

@@ -203,17 +203,21 @@ static double inf_integrand(double s, const void *vctx)
     double a = s * s;
     double P = c->Or + c->Om * a + c->Ok * a * a + c->OL * a * a * a * a;
     double num = k->which == INT_CHI ? 2.0 * s : 2.0 * s * s * s;
-    return num / sqrt(P);
+    if (k->dparam == 0) return num / sqrt(P);
+    /* Leibniz: -1/2 num (dP/dtheta) / P^(3/2), Ok eliminated: dP/dOm = a - a^2,
+     * dP/dOL = a^4 - a^2, dP/dOr = 1 - a^2 */
+    double dP = k->dparam == 1 ? a - a * a : (k->dparam == 2 ? a * a * a * a - a * a : 1.0 - a * a);
+    return -0.5 * num * dP / (P * sqrt(P));
 }
 
 /* Dimensionless integral from z1 to z2 (either order; z2 = +inf for the comoving
  * distance and the time coordinate; the absorption distance diverges there). */
-static double dimless_between(const struct cosmo *c, int which, double z1, double z2, double *abserr)
+static double dimless_between(const struct cosmo *c, int which, int dparam, double z1, double z2, double *abserr)
 {
     if (abserr) *abserr = 0.0;
     if (isinf(z2) && z2 > 0.0) {
         if (which == INT_ABS) return INFINITY;
-        struct ictx k = {c, which, 0, 1.0};
+        struct ictx k = {c, which, dparam, 1.0};
         /* panels [s1 10^-(j+1), s1 10^-j], j < 16, and [0, s1 1e-16]: the integrand has
          * structure at the scale sqrt(Or/Om) (where radiation takes over from matter),
          * which a single interval's first bisections would not sample */
@@ -229,7 +233,7 @@ static double dimless_between(const struct cosmo *c, int which, double z1, doubl
         return sum;
     }
     if (z1 == z2) return 0.0;
-    struct ictx k = {c, which, 0, 1.0 + z1};
+    struct ictx k = {c, which, dparam, 1.0 + z1};
     return adapt(dist_integrand, &k, 0.0, log1p((z2 - z1) / (1.0 + z1)), 0.0, EPSREL, abserr);
 }
 
@@ -428,28 +432,74 @@ int oracle_eval(int kind, const double *params, long n_cosmo, const double *z, l
 }
 
 /* Between two redshifts: kind K_DC, K_DM, K_DA, K_T or K_X at (z1, z2) of one
- * cosmology.  D_M(z1, z2) = (c/H0) sinn(chi(z1, z2)), D_A(z1, z2) = D_M(z1, z2)/(1+z2). */
-static double between_one(int kind, const double *prm, double z1, double z2)
+ * cosmology.  D_M(z1, z2) = (c/H0) sinn(chi(z1, z2)), D_A(z1, z2) = D_M(z1, z2)/(1+z2).
+ * grad (nullable): d/d(H0, Om, OL, Or, z1, z2) in grad[0..5] (Leibniz rule for the
+ * parameters, the fundamental theorem for the limits; d/dz2 = 0 at z2 = inf). */
+static double between_one(int kind, const double *prm, double z1, double z2, double *grad)
 {
     struct cosmo c;
     c.H0 = prm[0]; c.Om = prm[1]; c.OL = prm[2]; c.Or = prm[3];
     c.Ok = 1.0 - c.Om - c.OL - c.Or;
     double DH = C_KMS / c.H0;
     double tH = MPC_KM / (c.H0 * GYR_S);
-    if (kind == K_T) return tH * dimless_between(&c, INT_T, z1, z2, NULL);
-    if (kind == K_X) return DH * dimless_between(&c, INT_ABS, z1, z2, NULL);
-    double chi = dimless_between(&c, INT_CHI, z1, z2, NULL);
-    if (kind == K_DC) return DH * chi;
+    int zinf = isinf(z2) && z2 > 0.0;
+    double x1 = 1.0 + z1, x2 = 1.0 + z2;
+    double iE1 = 1.0 / sqrt(E2_of_x(&c, x1)), iE2 = zinf ? 0.0 : 1.0 / sqrt(E2_of_x(&c, x2));
+    if (kind == K_T || kind == K_X) {
+        int which = kind == K_T ? INT_T : INT_ABS;
+        double scale = kind == K_T ? tH : DH;
+        double val = scale * dimless_between(&c, which, 0, z1, z2, NULL);
+        if (grad) {
+            grad[0] = -val / c.H0;
+            for (int a = 1; a <= 3; ++a) grad[a] = scale * dimless_between(&c, which, a, z1, z2, NULL);
+            double p = integrand_power(which);
+            grad[4] = -scale * pow(x1, p) * iE1;
+            grad[5] = zinf ? 0.0 : scale * pow(x2, p) * iE2;
+        }
+        return val;
+    }
+    double chi = dimless_between(&c, INT_CHI, 0, z1, z2, NULL);
+    double dchi[6] = {0, 0, 0, 0, -iE1, iE2};
+    if (grad)
+        for (int a = 1; a <= 3; ++a) dchi[a] = dimless_between(&c, INT_CHI, a, z1, z2, NULL);
+    if (kind == K_DC) {
+        double val = DH * chi;
+        if (grad) {
+            grad[0] = -val / c.H0;
+            for (int a = 1; a <= 5; ++a) grad[a] = DH * dchi[a];
+        }
+        return val;
+    }
     double S, dS_dchi, dS_dok;
     curvature_transform(c.Ok, chi, &S, &dS_dchi, &dS_dok);
-    if (kind == K_DM) return DH * S;
-    return isinf(z2) ? 0.0 : DH * S / (1.0 + z2); /* K_DA */
+    double DM = DH * S;
+    double g[6];
+    g[0] = -DM / c.H0;
+    for (int a = 1; a <= 3; ++a) g[a] = DH * (dS_dchi * dchi[a] - dS_dok); /* dOk/da = -1 */
+    g[4] = DH * dS_dchi * dchi[4];
+    g[5] = DH * dS_dchi * dchi[5];
+    if (kind == K_DM) {
+        if (grad) memcpy(grad, g, sizeof g);
+        return DM;
+    }
+    /* K_DA */
+    if (zinf) {
+        if (grad) memset(grad, 0, 6 * sizeof(double));
+        return 0.0;
+    }
+    double DA = DM / x2;
+    if (grad) {
+        for (int a = 0; a < 5; ++a) grad[a] = g[a] / x2;
+        grad[5] = g[5] / x2 - DA / x2;
+    }
+    return DA;
 }
 
-/* Batched: out[c*n_z + i] for the pair (z1[c*z_stride + i], z2[c*z_stride + i]).
- * kind: K_DC, K_DM, K_DA, K_T or K_X.  Returns 0, or -1 on bad arguments. */
+/* Batched: out[c*n_z + i] for the pair (z1[c*z_stride + i], z2[c*z_stride + i]);
+ * grad (nullable): [n_cosmo][n_z][6].  kind: K_DC, K_DM, K_DA, K_T or K_X.  Returns 0,
+ * or -1 on bad arguments. */
 int oracle_between(int kind, const double *params, long n_cosmo, const double *z1, const double *z2,
-                   long n_z, long z_stride, double *out, int nthreads)
+                   long n_z, long z_stride, double *out, double *grad, int nthreads)
 {
     if (!(kind == K_DC || kind == K_DM || kind == K_DA || kind == K_T || kind == K_X)) return -1;
     if (n_cosmo < 0 || n_z < 0 || !params || !z1 || !z2 || !out) return -1;
@@ -460,7 +510,8 @@ int oracle_between(int kind, const double *params, long n_cosmo, const double *z
 #endif
     for (long idx = 0; idx < total; ++idx) {
         long ci = idx / n_z, i = idx % n_z;
-        out[idx] = between_one(kind, params + 4 * ci, z1[ci * z_stride + i], z2[ci * z_stride + i]);
+        out[idx] = between_one(kind, params + 4 * ci, z1[ci * z_stride + i], z2[ci * z_stride + i],
+                               grad ? grad + 6 * idx : NULL);
     }
     (void)nthreads;
     return 0;

@@ -621,3 +621,34 @@ def test_comoving_volume_closed_forms():
     chi = np.arcsin(a * dmm / DH(h0)) / a  # below the antipode for these z
     g = (chi - np.sin(2 * a * chi) / (2 * a)) / (2 * abs(ok))
     assert rel(_ev("VC", (h0, om, 0.0, 0.0), z[:3]), 4 * np.pi * DH(h0) ** 3 * g[:3]) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["DC", "DM", "DA", "T"])
+def test_between_gradient_vs_richardson(kind):
+    """Leibniz-rule gradients between two redshifts (and to infinity) against central
+    differences of the oracle's own values, open and closed curvature."""
+    for p in [(70.0, 0.3, 0.6, 1e-4), (66.0, 0.45, 0.85, 3e-5), (72.0, 0.2, 0.3, 0.0)]:
+        for z1, z2 in ((0.4, 1.9), (2.5, 0.7), (1.1, np.inf)):
+            if kind == "DA" and np.isinf(z2):
+                continue
+            _, g = oracle.between(kind, np.array([p]), np.array([z1]), np.array([z2]), grad=True)
+            g = g[0, 0]
+            base = list(p) + [z1, z2]
+            for a, h in zip(range(6), (1e-2, 1e-4, 1e-4, 1e-6, 1e-4, 1e-4)):
+                if a == 5 and np.isinf(z2):
+                    assert g[5] == 0.0
+                    continue
+                if a == 3 and np.isinf(z2) and p[3] == 0.0:
+                    # d chi(z, inf)/d Or0 at Or0 = 0 is -inf (chi_eps = chi_0 - 2 sqrt(eps)/Om0 ...)
+                    assert g[3] == -np.inf or (kind == "T" and np.isfinite(g[3]))
+                    continue
+
+                def f(v, a=a):
+                    q = list(base)
+                    q[a] = v
+                    return oracle.between(kind, np.array([q[:4]]), np.array([q[4]]), np.array([q[5]]))[0, 0]
+                fd = _richardson(f, base[a], h)
+                v0 = f(base[a])
+                scale = max(abs(fd), 1e-6 * abs(v0) / max(abs(base[a]), 1e-4), 1e-12)
+                tol = 1e-5 if a == 3 else 1e-7
+                assert abs(g[a] - fd) <= tol * scale + 1e-6 * abs(g[a]) * (a == 3), (kind, p, z1, z2, a, g[a], fd)
