@@ -124,11 +124,31 @@ int cosmo_distance(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_
  * limits of element (c, i), either order (the result changes sign, D_A aside),
  * laid out like cosmo_distance's z; z2 = +inf gives the limits chi(z1, inf),
  * D_M(z1, inf), D_A = 0 and the age t(z1, inf).  out: [n_cosmo][n_z] of dtype.
- * info, workspace, workspace_bytes, stream: as cosmo_distance.  Forward only.     */
+ * info, workspace, workspace_bytes, stream: as cosmo_distance.  Adjoint:
+ * cosmo_distance_between_vjp (distance kinds).                                      */
 int cosmo_distance_between(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo,
                            const void *z1, const void *z2, int64_t n_z, int64_t z_cosmo_stride,
                            void *out, int32_t *info, void *workspace, size_t workspace_bytes,
                            void *stream);
+
+/* cosmo_distance_between_vjp -- adjoint of cosmo_distance_between for the distance
+ * kinds COSMO_DC, COSMO_DM and COSMO_DA (other kinds: COSMO_E_KIND), through the
+ * Carlson derivatives of eq. 3.7 (eq. 2.10) with both limits' square roots per
+ * element and the root Jacobian (app. A); limits by the fundamental theorem of
+ * calculus.  cot: [n_cosmo][n_z] of dtype.
+ * out        : nullable; the observable from the same pass.
+ * grad_params: [n_cosmo][4] FP64, sum over elements of cot * d out/d(H0, Om0, OL0,
+ *              Or0); nullable.  NaN for a cosmology with an infinite upper limit and
+ *              Or0 = 0 (d chi(z, inf)/d Or0 is -inf there), and for near-multiple-root
+ *              cosmologies (whose gradient is the Leibniz quadrature) with z2 = inf.
+ * grad_z1, grad_z2: dtype, nullable; [n_z] summed over cosmologies when
+ *              z_cosmo_stride == 0, else [n_cosmo][n_z]; d/dz2 is 0 where z2 = inf.
+ * workspace  : cosmo_workspace_size(n_cosmo, n_z) bytes (NULL allowed).            */
+int cosmo_distance_between_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params,
+                               int64_t n_cosmo, const void *z1, const void *z2, int64_t n_z,
+                               int64_t z_cosmo_stride, const void *cot, void *out,
+                               double *grad_params, void *grad_z1, void *grad_z2, int32_t *info,
+                               void *workspace, size_t workspace_bytes, void *stream);
 
 /* cosmo_distance_vjp -- adjoint of cosmo_distance for a cotangent `cot`
  * ([n_cosmo][n_z], dtype).  Gradients through the Carlson derivatives (eqs.

@@ -27,7 +27,8 @@ INFO = {"CUBIC": 0x1, "QUARTIC": 0x2, "THREE_REAL": 0x4, "YELLOW": 0x8, "RED": 0
 
 # every function declared in include/cosmo.h
 EXPORTS = ("cosmo_workspace_size", "cosmo_roots", "carlson_rf", "carlson_rd", "carlson_rj",
-           "carlson_rc", "cosmo_distance", "cosmo_distance_between", "cosmo_distance_vjp", "cosmo_distance_jac",
+           "carlson_rc", "cosmo_distance", "cosmo_distance_between", "cosmo_distance_between_vjp",
+           "cosmo_distance_vjp", "cosmo_distance_jac",
            "cosmo_gaussian_loglike", "cosmo_version")
 
 _lib = None
@@ -56,6 +57,8 @@ def load():
                                    ctypes.c_size_t, vp]
     lib.cosmo_distance_between.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, vp, i64, i64, vp, i32p, vp,
                                            ctypes.c_size_t, vp]
+    lib.cosmo_distance_between_vjp.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, vp, i64, i64, vp, vp, vp,
+                                               vp, vp, i32p, vp, ctypes.c_size_t, vp]
     lib.cosmo_distance_vjp.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, vp, vp,
                                        i32p, vp, ctypes.c_size_t, vp]
     lib.cosmo_distance_jac.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, i32p, vp,
@@ -218,6 +221,40 @@ def cosmo_distance_between(kind, params, z1, z2, info=False, workspace=None):
     return (out, inf) if info else out
 
 
+def cosmo_distance_between_vjp(kind, params, z1, z2, cot, want_params=True, want_z=True, info=False,
+                               workspace=None, want_value=False):
+    """Adjoint of cosmo_distance_between for 'DC', 'DM', 'DA': (grad_params [n_cosmo, 4]
+    float64 or None, grad_z1, grad_z2 like the limits (summed over cosmologies when
+    shared) or None); with want_value=True the observable first."""
+    lib = load()
+    p = _params(params)
+    n_c = p.shape[0]
+    a, n_z, _, shared = _z_layout(z1, n_c)
+    _need_gpu(z2, "z2")
+    if z2.shape != z1.shape or z2.dtype != z1.dtype:
+        raise CosmoError("z1 and z2 must have the same shape and dtype")
+    a = a.contiguous()
+    b = z2.contiguous()
+    stride = 0 if shared else n_z
+    _need_gpu(cot, "cot")
+    c = cot.to(a.dtype).reshape(n_c, n_z).contiguous()
+    gp = torch.empty((n_c, 4), dtype=torch.float64, device=p.device) if want_params else None
+    g1 = g2 = None
+    if want_z:
+        g1 = torch.empty(n_z if shared else (n_c, n_z), dtype=a.dtype, device=p.device)
+        g2 = torch.empty_like(g1)
+    val = torch.empty((n_c, n_z), dtype=a.dtype, device=p.device) if want_value else None
+    inf = torch.empty(n_c, dtype=torch.int32, device=p.device) if info else None
+    ws = workspace if workspace is not None else _workspace(n_c, n_z, p.device)
+    with torch.cuda.device(p.device):
+        rc = lib.cosmo_distance_between_vjp(KINDS[kind], DTYPES[a.dtype], _ptr(p), n_c, _ptr(a), _ptr(b), n_z,
+                                            stride, _ptr(c), _ptr(val), _ptr(gp), _ptr(g1), _ptr(g2), _ptr(inf),
+                                            _ptr(ws), ws.numel(), _stream(p.device))
+    _check(rc, "cosmo_distance_between_vjp")
+    res = ((val,) if want_value else ()) + (gp, g1, g2)
+    return res + (inf,) if info else res
+
+
 def cosmo_distance_vjp(kind, params, z, cot, want_params=True, want_z=True, info=False, workspace=None,
                        want_value=False):
     """Adjoint: (grad_params [n_cosmo, 4] float64 or None, grad_z like z or None).
@@ -356,6 +393,30 @@ class _Distance(torch.autograd.Function):
 def distance(kind, params, z):
     """Differentiable observable: autograd through cosmo_distance / cosmo_distance_vjp."""
     return _Distance.apply(kind, params, z)
+
+
+class _Between(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, kind, params, z1, z2):
+        ctx.kind = kind
+        ctx.save_for_backward(params, z1, z2)
+        return cosmo_distance_between(kind, params.detach(), z1.detach(), z2.detach())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        params, z1, z2 = ctx.saved_tensors
+        want_z = ctx.needs_input_grad[2] or ctx.needs_input_grad[3]
+        gp, g1, g2 = cosmo_distance_between_vjp(ctx.kind, params.detach(), z1.detach(), z2.detach(), grad_out,
+                                                want_params=ctx.needs_input_grad[1], want_z=want_z)
+        g1 = g1.reshape(z1.shape) if (g1 is not None and ctx.needs_input_grad[2]) else None
+        g2 = g2.reshape(z2.shape) if (g2 is not None and ctx.needs_input_grad[3]) else None
+        return None, gp.reshape(params.shape) if gp is not None else None, g1, g2
+
+
+def distance_between(kind, params, z1, z2):
+    """Differentiable observable between two redshifts ('DC', 'DM', 'DA'): autograd
+    through cosmo_distance_between / cosmo_distance_between_vjp."""
+    return _Between.apply(kind, params, z1, z2)
 
 
 def version():

@@ -13,7 +13,7 @@
 // R_J (-3/2) and R_C (-1/2) the prefactors 2 dz, dz^2 then become 2 and 1.
 #pragma once
 
-#include "lane.hpp"
+#include "adjoint.hpp"
 
 namespace cosmo {
 
@@ -160,6 +160,188 @@ __device__ __forceinline__ T eval_between(const CosmoRec &r, T z1, T z2) {
     sinn(chi, k.ok, k.sk, S, C, dS);
     if (KIND == COSMO_DM) return k.dh * S;
     return z2 == Fp<T>::inf() ? T(0) : k.dh * S * Fp<T>::rcp(T(1) + z2); // COSMO_DA
+}
+
+// ---------------------------------------------------------------- adjoint (D_C family)
+// One limit with the reciprocals the chain needs (square roots as v rsqrt(v), as in
+// build_u's INV form): it2 = 1/t^2, i0 = 1/n0^2, i1 = 1/n1^2 (PAIR: the complex
+// 1/(x - rho_1)), i2 = 1/n2^2, and ie = 1/(t n0 |n1|^2) (PAIR) or 1/(t n0 n1 n2), so that
+// 1/E = beta^(-1/2) ie at that limit.  At infinity the scaled side does not depend on
+// the roots: its reciprocal squares are zero, and with x = 1 the sigma term of the
+// chain (d t^2/d sigma = -x) holds for t^2 = -sigma.
+template <typename T, bool PAIR> struct SideG {
+    Side<T, PAIR> s;
+    T it2, i0, i1re, i1im, i2, ie;
+};
+
+template <typename T, bool PAIR> __device__ __forceinline__ void side_at_g(const LaneConst<T> &k, T z, SideG<T, PAIR> &o) {
+    Side<T, PAIR> &s = o.s;
+    s.x = T(1) + z;
+    s.t2 = k.yt2 - k.sigma * z;
+    const T v0 = z + k.w0;
+    const T rt = Fp<T>::rsqrt(s.t2), r0 = Fp<T>::rsqrt(v0);
+    s.t = s.t2 * rt; o.it2 = rt * rt;
+    s.n0 = v0 * r0; o.i0 = r0 * r0;
+    if (PAIR) {
+        T ab, iab;
+        const cx<T> w = mkc(z + k.w1re, k.w1im);
+        const cx<T> n1 = csqrt_inv(w, ab, iab);
+        s.n1re = n1.re; s.n1im = n1.im; s.n1abs = ab;
+        const T i2v = iab * iab;
+        o.i1re = w.re * i2v; o.i1im = -w.im * i2v;
+        s.n2 = T(0); o.i2 = T(0);
+        o.ie = rt * r0 * iab;
+    } else {
+        const T v1 = z + k.w1re, v2 = z + k.w2;
+        const T r1 = Fp<T>::rsqrt(v1), r2 = Fp<T>::rsqrt(v2);
+        s.n1re = v1 * r1; s.n1im = T(0); s.n1abs = T(0);
+        s.n2 = v2 * r2;
+        o.i1re = r1 * r1; o.i1im = T(0); o.i2 = r2 * r2;
+        o.ie = rt * r0 * r1 * r2;
+    }
+}
+
+template <typename T, bool PAIR> __device__ __forceinline__ void side_inf_g(const LaneConst<T> &k, SideG<T, PAIR> &o) {
+    side_inf<T, PAIR>(k, o.s);
+    o.it2 = Fp<T>::rcp(o.s.t2); // 1/(-sigma): infinite without radiation (see chi_grad_between)
+    o.i0 = T(0); o.i1re = T(0); o.i1im = T(0); o.i2 = T(0);
+    o.ie = T(0);
+}
+
+// chi(z1, z2)/D_H and its partials in the root parameters (sigma, rho_0, rho_1 [re, im]
+// or rho_1, rho_2) at fixed beta, through dR_F/d(U_m^2) = -R_D(., ., U_m^2)/6 (eq. 2.10)
+// and the square roots of both limits (each U_m = T1_m + T2_m, T1 led by the upper
+// limit's sqrt(1 - sigma x), T2 by the lower's):
+//   d/dsigma  = -1/2 [x2 A / t2^2 + x1 B / t1^2],
+//   d/drho_n  = -1/2 [(a_n + B - b_n) / (x2 - rho_n) + (b_n + A - a_n) / (x1 - rho_n)],
+// a_m = G_m T1_m, b_m = G_m T2_m, G_m = dR_F/dU_m, A = sum a, B = sum b (the one-sided
+// chi_grad with the lower limit per lane).  Also 1/E at both limits (0 at infinity).
+// Without radiation the sigma partial diverges at an infinite upper limit (d chi/d Or0
+// is -inf at Or0 = 0 there): it is returned as NaN.
+template <typename T, bool PAIR> struct ChiGrad2 {
+    T chi, dsig, dr0, dr1re, dr1im, dr2, iE1, iE2;
+};
+
+template <typename T, bool PAIR>
+__device__ __forceinline__ void chi_grad_between(const LaneConst<T> &k, T z1, T z2, ChiGrad2<T, PAIR> &o) {
+    SideG<T, PAIR> a, b;
+    side_at_g<T, PAIR>(k, z1, b);
+    const bool zinf = z2 == Fp<T>::inf();
+    T dz;
+    if (zinf) {
+        side_inf_g<T, PAIR>(k, a);
+        dz = T(1);
+    } else {
+        side_at_g<T, PAIR>(k, z2, a);
+        dz = z2 - z1;
+    }
+    const Side<T, PAIR> &A_ = a.s, &B_ = b.s;
+    T U0, va, vb, T1_0, T2_0;
+    cx<T> U1, T1_1, T2_1;
+    T U2 = T(0), T1_2 = T(0), T2_2 = T(0), T1_1r = T(0), T2_1r = T(0);
+    if (PAIR) {
+        T1_0 = A_.t * A_.n0 * B_.n1abs;
+        T2_0 = B_.t * B_.n0 * A_.n1abs;
+        const cx<T> w = mkc(A_.n1re, A_.n1im) * mkc(B_.n1re, -B_.n1im);
+        T1_1 = w * (A_.t * B_.n0);
+        T2_1 = conj(w) * (B_.t * A_.n0);
+        U1 = T1_1 + T2_1;
+        va = U1.re * U1.re - U1.im * U1.im;
+        vb = T(2) * U1.re * U1.im;
+    } else {
+        T1_0 = A_.t * A_.n0 * B_.n1re * B_.n2;
+        T2_0 = B_.t * B_.n0 * A_.n1re * A_.n2;
+        T1_1r = A_.t * A_.n1re * B_.n0 * B_.n2;
+        T2_1r = B_.t * B_.n1re * A_.n0 * A_.n2;
+        T1_2 = A_.t * A_.n2 * B_.n0 * B_.n1re;
+        T2_2 = B_.t * B_.n2 * A_.n0 * A_.n1re;
+        U1 = mkc(T1_1r + T2_1r, T(0));
+        U2 = T1_2 + T2_2;
+        va = U1.re * U1.re;
+        vb = U2 * U2;
+    }
+    U0 = T1_0 + T2_0;
+    T rf, rdx, rdz;
+    cx<T> rdy;
+    rfd_s<T, PAIR>(U0 * U0, va, vb, rf, rdx, rdy, rdz);
+    const T scale = k.pre * T(2) * dz;
+    o.chi = scale * rf;
+    o.iE1 = k.pre * b.ie;
+    o.iE2 = k.pre * a.ie;
+    const T h = scale * T(-0.5);
+    const T G0 = -U0 * rdx * T(1.0 / 3.0);
+    const T a0 = G0 * T1_0, b0 = G0 * T2_0;
+    if (PAIR) {
+        const cx<T> G1 = U1 * rdy * T(-1.0 / 3.0);
+        const cx<T> a1 = G1 * T1_1, b1 = G1 * T2_1;
+        const T Asum = a0 + T(2) * a1.re, Bsum = b0 + T(2) * b1.re;
+        o.dsig = h * (A_.x * Asum * a.it2 + B_.x * Bsum * b.it2);
+        o.dr0 = h * ((a0 + Bsum - b0) * a.i0 + (b0 + Asum - a0) * b.i0);
+        const cx<T> d1 = (a1 + Bsum - b1) * mkc(a.i1re, a.i1im) + (b1 + Asum - a1) * mkc(b.i1re, b.i1im);
+        o.dr1re = h * d1.re;
+        o.dr1im = h * d1.im;
+        o.dr2 = T(0);
+    } else {
+        const T G1 = -U1.re * rdy.re * T(1.0 / 3.0), G2 = -U2 * rdz * T(1.0 / 3.0);
+        const T a1 = G1 * T1_1r, b1 = G1 * T2_1r, a2 = G2 * T1_2, b2 = G2 * T2_2;
+        const T Asum = a0 + a1 + a2, Bsum = b0 + b1 + b2;
+        o.dsig = h * (A_.x * Asum * a.it2 + B_.x * Bsum * b.it2);
+        o.dr0 = h * ((a0 + Bsum - b0) * a.i0 + (b0 + Asum - a0) * b.i0);
+        o.dr1re = h * ((a1 + Bsum - b1) * a.i1re + (b1 + Asum - a1) * b.i1re);
+        o.dr2 = h * ((a2 + Bsum - b2) * a.i2 + (b2 + Asum - a2) * b.i2);
+        o.dr1im = T(0);
+    }
+    if (zinf && k.sigma == T(0)) o.dsig = Fp<T>::nan();
+}
+
+// Derivatives of one lane between z1 and z2 for KIND = COSMO_DC, COSMO_DM or COSMO_DA,
+// in the layout of LaneGrad (root mode: p[0..4]; near-multiple roots: the Leibniz
+// quadrature partials from 0 to each limit, differenced, in q[0..2]); dz1 and dz2 by the
+// fundamental theorem of calculus.
+template <typename T> struct LaneGrad2 {
+    LaneGrad<T> g;
+    T dz1;
+};
+
+template <typename T, int KIND, bool PAIR>
+__device__ __forceinline__ void lane_grad_between(const CosmoRec &r, T z1, T z2, LaneGrad2<T> &o) {
+    const LaneConst<T> &k = lane_of<T>(r);
+    const bool fp32 = sizeof(T) == 4;
+    const bool zinf = z2 == Fp<T>::inf();
+    ChiGrad2<T, PAIR> cg;
+    chi_grad_between<T, PAIR>(k, z1, z2, cg);
+    LaneGrad<T> &g = o.g;
+    g.quad = direct_mode(KIND, r, fp32);
+    g.p[0] = cg.chi; g.p[1] = cg.dsig; g.p[2] = cg.dr0; g.p[3] = cg.dr1re; g.p[4] = PAIR ? cg.dr1im : cg.dr2;
+    if (g.quad) {
+        // near-multiple roots: the root chain is ill conditioned; Leibniz quadrature from
+        // 0 to each limit (not defined to an infinite limit)
+        if (zinf) {
+            g.q[0] = g.q[1] = g.q[2] = Fp<double>::nan();
+        } else if (fp32) {
+            T v, g1[3], g2[3];
+            gl_integral<T, PAIR>(k, z2, 0, true, v, g2);
+            gl_integral<T, PAIR>(k, z1, 0, true, v, g1);
+            for (int i = 0; i < 3; ++i) g.q[i] = (double)g2[i] - (double)g1[i];
+        } else {
+            const GlChi c2 = gl_chi_grad<PAIR>(r, (double)z2), c1 = gl_chi_grad<PAIR>(r, (double)z1);
+            g.q[0] = c2.g0 - c1.g0; g.q[1] = c2.g1 - c1.g1; g.q[2] = c2.g2 - c1.g2;
+        }
+    }
+    const T H0inv = k.hinv;
+    const T chi = cg.chi;
+    if (KIND == COSMO_DC) {
+        g.val = k.dh * chi; g.s = k.dh; g.dok = T(0);
+    } else {
+        T S, C, dS;
+        sinn(chi, k.ok, k.sk, S, C, dS);
+        const T f = KIND == COSMO_DA ? (zinf ? T(0) : Fp<T>::rcp(T(1) + z2)) : T(1);
+        g.val = k.dh * S * f; g.s = k.dh * C * f; g.dok = k.dh * dS * f;
+    }
+    g.dh = -g.val * H0inv;
+    o.dz1 = -g.s * cg.iE1;
+    g.dz = g.s * cg.iE2;
+    if (KIND == COSMO_DA && !zinf) g.dz -= g.val * Fp<T>::rcp(T(1) + z2);
 }
 
 } // namespace cosmo

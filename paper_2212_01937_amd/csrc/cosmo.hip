@@ -314,6 +314,123 @@ __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_vjp(
     }
 }
 
+// Adjoint of the observables between two redshifts (D_C family): the structure of k_vjp
+// (ZPT pairs per lane, per-wave partial sums of the same accumulator slots, finalised by
+// k_finalize_params) with two redshift gradients; for limits shared by all cosmologies
+// the z1- and z2-gradients are summed over the tile in thread-private LDS slots.
+template <typename T, int KIND, bool PAIR, int ZPT>
+__device__ __forceinline__ void between_vjp_cosmo(const CosmoRec &r, int64_t c, const T *__restrict__ z1,
+                                                  const T *__restrict__ z2, int64_t n_z, int64_t zstride,
+                                                  const T *__restrict__ cot, int64_t base, T acc[kAcc], T *gl1,
+                                                  T *gl2, T *__restrict__ g1_out, T *__restrict__ g2_out,
+                                                  T *__restrict__ out) {
+#pragma unroll 1
+    for (int k = 0; k < ZPT; ++k) {
+        const int64_t i = base + (int64_t)k * kBlock;
+        if (i >= n_z) break;
+        const T a = z1[c * zstride + i], b = z2[c * zstride + i];
+        const T w = cot[c * n_z + i];
+        LaneGrad2<T> o;
+        lane_grad_between<T, KIND, PAIR>(r, a, b, o);
+        const LaneGrad<T> &g = o.g;
+        T d[5], e[3];
+        if (g.quad) {
+            const double ws = (double)w * (double)g.s;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) d[q] = T(0);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) e[q] = T(ws * g.q[q]);
+        } else {
+            const T ws = w * g.s;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) d[q] = ws * g.p[q];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) e[q] = T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[q] += d[q];
+        acc[5] += w * g.dok;
+        acc[6] += w * g.dh;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[7 + q] += e[q];
+        if (out) out[c * n_z + i] = g.val;
+        const T gz1 = w * o.dz1, gz2 = w * g.dz;
+        if (zstride != 0) {
+            if (g1_out) g1_out[c * n_z + i] = gz1;
+            if (g2_out) g2_out[c * n_z + i] = gz2;
+        } else {
+            gl1[k * kBlock + threadIdx.x] += gz1;
+            gl2[k * kBlock + threadIdx.x] += gz2;
+        }
+    }
+}
+
+template <typename T, int KIND, int ZPT>
+__global__ __launch_bounds__(kBlock) void k_between_vjp(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
+                                                        const T *__restrict__ z1, const T *__restrict__ z2,
+                                                        int64_t n_z, int64_t zstride, const T *__restrict__ cot,
+                                                        double *__restrict__ pacc, T *__restrict__ g1_out,
+                                                        T *__restrict__ g2_out, double *__restrict__ g1_part,
+                                                        double *__restrict__ g2_part, T *__restrict__ out, int ct,
+                                                        int64_t nzb) {
+    __shared__ T gl1[ZPT * kBlock], gl2[ZPT * kBlock];
+    const int64_t b = blockIdx.x;
+    const int64_t tile = b / nzb, zb = b - tile * nzb;
+    const int64_t base = zb * (int64_t)(kBlock * ZPT) + threadIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t nwz = nzb * (kBlock / 64);
+    const int64_t gw = zb * (kBlock / 64) + wave;
+    const int64_t c0 = tile * ct;
+    const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
+    for (int k = 0; k < ZPT; ++k) gl1[k * kBlock + threadIdx.x] = gl2[k * kBlock + threadIdx.x] = T(0);
+    for (int64_t c = c0; c < c1; ++c) {
+        const CosmoRec &r = recs[c];
+        T acc[kAcc];
+#pragma unroll
+        for (int s = 0; s < kAcc; ++s) acc[s] = T(0);
+        if (r.valid) {
+            if (r.pair) between_vjp_cosmo<T, KIND, true, ZPT>(r, c, z1, z2, n_z, zstride, cot, base, acc, gl1, gl2, g1_out, g2_out, out);
+            else between_vjp_cosmo<T, KIND, false, ZPT>(r, c, z1, z2, n_z, zstride, cot, base, acc, gl1, gl2, g1_out, g2_out, out);
+        } else {
+            for (int k = 0; k < ZPT; ++k) {
+                const int64_t i = base + (int64_t)k * kBlock;
+                if (i >= n_z) break;
+                if (out) out[c * n_z + i] = Fp<T>::nan();
+                if (zstride != 0) {
+                    if (g1_out) g1_out[c * n_z + i] = Fp<T>::nan();
+                    if (g2_out) g2_out[c * n_z + i] = Fp<T>::nan();
+                } else {
+                    gl1[k * kBlock + threadIdx.x] = Fp<T>::nan();
+                    gl2[k * kBlock + threadIdx.x] = Fp<T>::nan();
+                }
+            }
+        }
+        if (pacc) {
+#pragma unroll
+            for (int s = 0; s < kAcc; ++s) {
+                T v = T(0);
+                if (__ballot(acc[s] != T(0))) v = wave_sum(acc[s]);
+                if (lane == 0) pacc[(c * nwz + gw) * kAcc + s] = (double)v;
+            }
+        }
+    }
+    if (zstride == 0) {
+        for (int k = 0; k < ZPT; ++k) {
+            const int64_t i = base + (int64_t)k * kBlock;
+            if (i >= n_z) break;
+            const T v1 = gl1[k * kBlock + threadIdx.x], v2 = gl2[k * kBlock + threadIdx.x];
+            if (g1_out) {
+                if (g1_part) g1_part[tile * n_z + i] = (double)v1;
+                else g1_out[i] = v1;
+            }
+            if (g2_out) {
+                if (g2_part) g2_part[tile * n_z + i] = (double)v2;
+                else g2_out[i] = v2;
+            }
+        }
+    }
+}
+
 // Materialised Jacobian: per lane the observable and d out / d(H0, Om0, OL0, Or0, z),
 // written as five planes jac[q][c][i]; the root-space partials are contracted with the
 // root Jacobian per lane, in FP64.  Grid as k_forward.
@@ -499,7 +616,7 @@ WsLayout ws_layout(int64_t n_cosmo, int64_t n_z) {
     w.recs = 0;
     w.pacc = align256(sizeof(CosmoRec) * (size_t)n_cosmo);
     w.gzp = w.pacc + align256(sizeof(double) * kAcc * (size_t)n_cosmo * (size_t)t.nzb * (kBlock / 64));
-    w.total = w.gzp + align256(sizeof(double) * (size_t)t.ntile * (size_t)n_z);
+    w.total = w.gzp + align256(sizeof(double) * 2 * (size_t)t.ntile * (size_t)n_z); // z1 and z2 planes (between adjoint)
     return w;
 }
 
@@ -649,7 +766,7 @@ int launch_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int6
     Tiling t = tiling(n_cosmo, n_z, zpt);
     const bool like = ivar != nullptr;
     double *pacc = (grad_params || loglike) ? (double *)(ws + L.pacc) : nullptr;
-    double *gzp = (grad_z && zstride == 0 && t.ntile > 1) ? (double *)(ws + L.gzp) : nullptr;
+    double *gzp = (grad_z && zstride == 0 && t.ntile > 1 && n_z > 0) ? (double *)(ws + L.gzp) : nullptr;
     dim3 grid((unsigned)t.nblocks), block(kBlock);
 #define COSMO_VJP_Z(K, Z, LK)                                                                                   \
     hipLaunchKernelGGL((k_vjp<T, K, Z, LK>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, cot, ivar, wc,  \
@@ -683,6 +800,48 @@ int launch_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int6
     if (gzp) {
         hipLaunchKernelGGL((k_reduce_gz<T>), dim3((unsigned)((n_z + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, gzp,
                            t.ntile, n_z, grad_z);
+        if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
+    }
+    return COSMO_OK;
+}
+
+template <typename T>
+int launch_between_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z1, const T *z2, int64_t n_z,
+                       int64_t zstride, const T *cot, T *out, double *grad_params, T *g1, T *g2,
+                       const WsLayout &L, char *ws, hipStream_t s) {
+    const int zpt = vjp_zpt(n_z);
+    Tiling t = tiling(n_cosmo, n_z, zpt);
+    double *pacc = grad_params ? (double *)(ws + L.pacc) : nullptr;
+    const bool part = zstride == 0 && t.ntile > 1 && n_z > 0;
+    double *p1 = (part && g1) ? (double *)(ws + L.gzp) : nullptr;
+    double *p2 = (part && g2) ? (double *)(ws + L.gzp) + (size_t)t.ntile * (size_t)n_z : nullptr;
+    dim3 grid((unsigned)t.nblocks), block(kBlock);
+#define COSMO_BVJP_Z(K, Z)                                                                                      \
+    hipLaunchKernelGGL((k_between_vjp<T, K, Z>), grid, block, 0, s, recs, n_cosmo, z1, z2, n_z, zstride, cot,   \
+                       pacc, g1, g2, p1, p2, out, t.ct, t.nzb)
+#define COSMO_BVJP(K)                                                                                           \
+    if (zpt == 8) COSMO_BVJP_Z(K, 8);                                                                           \
+    else COSMO_BVJP_Z(K, 1)
+    switch (kind) {
+    case COSMO_DC: COSMO_BVJP(COSMO_DC); break;
+    case COSMO_DM: COSMO_BVJP(COSMO_DM); break;
+    case COSMO_DA: COSMO_BVJP(COSMO_DA); break;
+    }
+#undef COSMO_BVJP
+#undef COSMO_BVJP_Z
+    if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
+    if (pacc) {
+        hipLaunchKernelGGL(k_finalize_params, dim3((unsigned)n_cosmo), dim3(kBlock), 0, s, recs, n_cosmo, pacc,
+                           t.nzb * (kBlock / 64), kind, (int)(sizeof(T) == 4), grad_params, (double *)nullptr);
+        if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
+    }
+    const dim3 rg((unsigned)((n_z + kBlock - 1) / kBlock));
+    if (p1) {
+        hipLaunchKernelGGL((k_reduce_gz<T>), rg, dim3(kBlock), 0, s, p1, t.ntile, n_z, g1);
+        if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
+    }
+    if (p2) {
+        hipLaunchKernelGGL((k_reduce_gz<T>), rg, dim3(kBlock), 0, s, p2, t.ntile, n_z, g2);
         if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
     }
     return COSMO_OK;
@@ -808,6 +967,48 @@ int cosmo_distance_between(cosmo_kind kind, cosmo_dtype dt, const double *params
                                      (float *)out, s);
     return launch_between<double>(kind, recs, n_cosmo, (const double *)z1, (const double *)z2, n_z, z_cosmo_stride,
                                   (double *)out, s);
+}
+
+int cosmo_distance_between_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo,
+                               const void *z1, const void *z2, int64_t n_z, int64_t z_cosmo_stride, const void *cot,
+                               void *out, double *grad_params, void *grad_z1, void *grad_z2, int32_t *info,
+                               void *workspace, size_t workspace_bytes, void *stream) {
+    if (!(kind == COSMO_DC || kind == COSMO_DM || kind == COSMO_DA)) return COSMO_E_KIND;
+    if (!valid_dtype(dt)) return COSMO_E_DTYPE;
+    if (n_cosmo < 0 || n_z < 0 || z_cosmo_stride < 0) return COSMO_E_ARG;
+    if (n_cosmo > 0 && !params) return COSMO_E_ARG;
+    if (n_cosmo > 0 && n_z > 0 && (!z1 || !z2 || !cot)) return COSMO_E_ARG;
+    if (check_grid(n_cosmo, n_z) != COSMO_OK) return COSMO_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_cosmo == 0) {
+        // empty sums over cosmologies: shared-limit gradients are zero (fill kernels, no
+        // memset)
+        if (n_z > 0 && z_cosmo_stride == 0) {
+            unsigned nb = (unsigned)((n_z + kBlock - 1) / kBlock);
+            for (void *g : {grad_z1, grad_z2}) {
+                if (!g) continue;
+                if (dt == COSMO_F32) hipLaunchKernelGGL(k_fill_zero<float>, dim3(nb), dim3(kBlock), 0, s, (float *)g, n_z);
+                else hipLaunchKernelGGL(k_fill_zero<double>, dim3(nb), dim3(kBlock), 0, s, (double *)g, n_z);
+            }
+        }
+        return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
+    }
+    int rc = ensure_init();
+    if (rc != COSMO_OK) return rc;
+    WsLayout L = ws_layout(n_cosmo, n_z);
+    Workspace ws;
+    rc = ws.acquire(workspace, workspace_bytes, L.total, s);
+    if (rc != COSMO_OK) return rc;
+    CosmoRec *recs = (CosmoRec *)ws.ptr;
+    rc = launch_setup(params, n_cosmo, recs, info, s);
+    if (rc != COSMO_OK) return rc;
+    if (dt == COSMO_F32)
+        return launch_between_vjp<float>(kind, recs, n_cosmo, (const float *)z1, (const float *)z2, n_z,
+                                         z_cosmo_stride, (const float *)cot, (float *)out, grad_params,
+                                         (float *)grad_z1, (float *)grad_z2, L, (char *)ws.ptr, s);
+    return launch_between_vjp<double>(kind, recs, n_cosmo, (const double *)z1, (const double *)z2, n_z,
+                                      z_cosmo_stride, (const double *)cot, (double *)out, grad_params,
+                                      (double *)grad_z1, (double *)grad_z2, L, (char *)ws.ptr, s);
 }
 
 int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo, const void *z,

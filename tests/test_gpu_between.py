@@ -173,3 +173,123 @@ def test_between_full_size_sampled(dt):
             scale = np.abs(ref)
         e = np.abs(got - ref) / scale
         assert e.max() <= TOL[dt], (kind, dt, float(e.max()))
+
+
+# --------------------------------------------------------------------------- adjoint
+GTOL = {torch.float64: 1e-10, torch.float32: 1e-4}
+
+
+def ref_between_vjp(kind, params, z1, z2, w):
+    """Oracle vector-Jacobian products: grad_params [c, 4], grad_z1, grad_z2 per element,
+    with the natural scales sum |w d out/d theta| and |w d out/dz|."""
+    out, g = oracle.between(kind, params, z1, z2, grad=True)
+    gp = np.einsum("cz,czk->ck", w, g[..., :4])
+    sp = np.einsum("cz,czk->ck", np.abs(w), np.abs(g[..., :4]))
+    s1, s2 = np.abs(w * g[..., 4]), np.abs(w * g[..., 5])
+    if kind in ("DM", "DA"):
+        # the curvature transform: d/dtheta = (dS/dchi) dchi/dtheta - dS/dOk, two terms
+        # that can cancel; scale by the size of the chi-path term as well.  d/dz = C dchi/dz
+        # crosses zero with C (closed universes), where a relative error e of chi moves it
+        # by |S| x e dchi/dz: scale by that term too.
+        chi, gc = oracle.between("DC", params, z1, z2, grad=True)
+        h = 299792.458 / params[:, :1]
+        ok = (1 - params[:, 1] - params[:, 2] - params[:, 3])[:, None]
+        x = np.sqrt(np.abs(ok)) * chi / h
+        c = np.where(ok < 0, np.cos(x), np.where(ok > 0, np.cosh(x), 1.0))
+        sn = np.where(ok < 0, np.sin(x), np.where(ok > 0, np.sinh(x), 0.0))
+        f = 1.0 / (1.0 + np.broadcast_to(z2, out.shape)) if kind == "DA" else 1.0
+        with np.errstate(invalid="ignore"):
+            sp = sp + np.einsum("cz,czk->ck", np.abs(w), np.abs((c * f)[..., None] * gc[..., :4]))
+            cz = np.abs(w * sn * x * f)
+        s1 = s1 + cz * np.abs(gc[..., 4])
+        s2 = s2 + cz * np.abs(gc[..., 5])
+    return gp, sp, w * g[..., 4], w * g[..., 5], s1, s2
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", ["DC", "DM", "DA"])
+def test_between_vjp_workloads(kind, dt):
+    """grad_params, grad_z1 and grad_z2 of cosmo_distance_between_vjp against the oracle's
+    Leibniz-rule and fundamental-theorem derivatives, per-cosmology limits on the flat,
+    non-flat and near-degenerate subsets (close, long and reversed limits; z2 = inf for
+    D_C and D_M on cosmologies with radiation)."""
+    rng = np.random.default_rng(29)
+    p1, _ = workloads.config1()
+    p2, _ = workloads.config2(n_cosmo=16, n_z=8)
+    p4, _, _ = workloads.config4(n_per_family=4, n_z=8)
+    for label, params in (("flat", p1), ("non-flat", p2), ("near-degenerate", p4)):
+        n_c = params.shape[0]
+        z1 = np.empty((n_c, 400))
+        z2 = np.empty((n_c, 400))
+        for c in range(n_c):
+            z1[c], z2[c] = pairs(rng, 400, inf_share=0.0)
+        # an infinite upper limit where the gradient is defined (radiation present, roots
+        # well separated) and the observable is not D_A (zero there)
+        ok_inf = (params[:, 3] > 0) & (kind != "DA")
+        z2[ok_inf, :40] = np.inf
+        w = rng.standard_normal((n_c, 400))
+        p = torch.tensor(params, device=DEV)
+        a = torch.tensor(z1, dtype=dt, device=DEV)
+        b = torch.tensor(z2, dtype=dt, device=DEV)
+        wt = torch.tensor(w, dtype=dt, device=DEV)
+        val, gp, g1, g2 = cosmo.cosmo_distance_between_vjp(kind, p, a, b, wt, want_value=True)
+        ar, br, wr = (t.double().cpu().numpy() for t in (a, b, wt))
+        rgp, sp, r1, r2, s1, s2 = ref_between_vjp(kind, params, ar, br, wr)
+        gp = gp.cpu().numpy()
+        direct = np.isnan(gp).any(1)
+        # NaN only where documented: near-multiple roots with an infinite limit
+        assert not (direct & ~np.isinf(br).any(1)).any(), (label, kind)
+        ep = np.abs(gp - rgp)[~direct] / np.maximum(sp[~direct], 1e-300)
+        tol = GTOL[dt]
+        ptol = np.array([tol, tol, tol, 5 * tol if dt == torch.float32 else tol])
+        assert np.all(ep.max(0) <= ptol), (label, kind, dt, ep.max(0))
+        for got, ref, sc in ((g1, r1, s1), (g2, r2, s2)):
+            e = np.abs(got.double().cpu().numpy() - ref) / np.maximum(sc, 1e-300 + 1e-12 * sc.max())
+            assert e.max() <= tol, (label, kind, dt, float(e.max()))
+        check(kind, dt, params, ar, br, val, label + " value from the adjoint")
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_between_vjp_shared_limits_and_autograd(dt):
+    """Limits shared by all cosmologies (gradients summed over the tile and across tiles)
+    and the autograd wrapper against the explicit adjoint and the oracle."""
+    params, _ = workloads.config5(n_cosmo=12, n_z=8)
+    z1, z2 = workloads.lensing_pairs(n=1000)
+    p = torch.tensor(params, device=DEV, requires_grad=True)
+    a = torch.tensor(z1, dtype=dt, device=DEV, requires_grad=True)
+    b = torch.tensor(z2, dtype=dt, device=DEV, requires_grad=True)
+    rng = np.random.default_rng(8)
+    w = torch.tensor(rng.standard_normal((12, 1000)), dtype=dt, device=DEV)
+    out = cosmo.distance_between("DA", p, a, b)
+    (out * w).sum().backward()
+    gp, g1, g2 = cosmo.cosmo_distance_between_vjp("DA", p.detach(), a.detach(), b.detach(), w)
+    assert torch.equal(p.grad, gp) and torch.equal(a.grad, g1) and torch.equal(b.grad, g2)
+    ar, br, wr = a.detach().double().cpu().numpy(), b.detach().double().cpu().numpy(), w.double().cpu().numpy()
+    rgp, sp, r1, r2, s1, s2 = ref_between_vjp("DA", params, ar, br, wr)
+    tol = GTOL[dt]
+    assert np.max(np.abs(gp.cpu().numpy() - rgp) / sp) <= 5 * tol
+    for got, ref, sc in ((g1, r1.sum(0), s1.sum(0)), (g2, r2.sum(0), s2.sum(0))):
+        assert np.max(np.abs(got.double().cpu().numpy() - ref) / sc) <= tol
+
+
+def test_between_vjp_edge_cases():
+    """Empty inputs; invalid cosmologies give NaN rows; T and the other kinds are
+    rejected by the adjoint."""
+    good = [70.0, 0.3, 0.7 - 9e-5, 9e-5]
+    bad = [70.0, 0.05, 1.3, 0.0]
+    p = torch.tensor([good, bad], dtype=torch.float64, device=DEV)
+    z1 = torch.linspace(0.1, 1.0, 300, dtype=torch.float64, device=DEV)
+    z2 = z1 + 0.5
+    w = torch.ones((2, 300), dtype=torch.float64, device=DEV)
+    gp, g1, g2 = cosmo.cosmo_distance_between_vjp("DC", p, z1, z2, w)
+    assert torch.isnan(gp[1]).all() and torch.isfinite(gp[0]).all()
+    assert torch.isnan(g1).all() and torch.isnan(g2).all()  # shared limits sum the NaN row
+    e = torch.empty(0, dtype=torch.float64, device=DEV)
+    gp, g1, g2 = cosmo.cosmo_distance_between_vjp("DM", p, e, e, torch.empty((2, 0), dtype=torch.float64, device=DEV))
+    assert torch.equal(gp[0], torch.zeros_like(gp[0])) and torch.isnan(gp[1]).all() and g1.numel() == 0
+    gp, g1, g2 = cosmo.cosmo_distance_between_vjp("DC", p[:0], z1, z2, torch.empty((0, 300), dtype=torch.float64,
+                                                                                      device=DEV))
+    assert gp.shape == (0, 4) and torch.equal(g1, torch.zeros_like(g1)) and torch.equal(g2, torch.zeros_like(g2))
+    for k in ("T", "X", "MU"):
+        with pytest.raises(cosmo.CosmoError):
+            cosmo.cosmo_distance_between_vjp(k, p, z1, z2, w)
