@@ -250,7 +250,17 @@ def main():
                 ev, _, _ = timed(fb, max(2, args.steps // 2), stream, torch)
                 btw[f"{path}_{label}_ms"] = float(np.median(ev))
                 btw[f"{path}_{label}_evals_per_s"] = evals / (np.median(ev) * 1e-3)
-            del a, b, za, zinf
+            # D_A from lens to source with its gradients in the cosmology and both limits
+            # (value + adjoint in one pass, limits shared by every cosmology)
+            wb = torch.randn((n_c, n_z), dtype=torch.float64, device=dev, generator=gen).to(dt)
+
+            def fbv():
+                return cosmo.cosmo_distance_between_vjp("DA", p, a, b, wb, want_value=True, workspace=ws)
+            fbv()
+            ev, _, _ = timed(fbv, max(2, args.steps // 2), stream, torch)
+            btw[f"{path}_DA_lens_value_and_grad_ms"] = float(np.median(ev))
+            btw[f"{path}_DA_lens_value_and_grad_evals_per_s"] = evals / (np.median(ev) * 1e-3)
+            del a, b, za, zinf, wb
             torch.cuda.empty_cache()
         results["between"] = btw
 

@@ -293,3 +293,90 @@ def test_between_vjp_edge_cases():
     for k in ("T", "X", "MU"):
         with pytest.raises(cosmo.CosmoError):
             cosmo.cosmo_distance_between_vjp(k, p, z1, z2, w)
+
+
+_ORACLE_CACHE = {}
+
+
+def _mid_case(kind, shared):
+    """Limits exactly representable in FP32 (one oracle evaluation serves both paths):
+    2 non-flat cosmologies x 8300 pairs -- past the row length at which the adjoint
+    takes 8 limit pairs per lane, with a ragged tail."""
+    key = (kind, shared)
+    if key not in _ORACLE_CACHE:
+        rng = np.random.default_rng(41)
+        params, _ = workloads.config2(n_cosmo=2, n_z=8)
+        n = 8300
+        shape = (n,) if shared else (2, n)
+        z1 = np.empty(shape)
+        z2 = np.empty(shape)
+        for row in ([z1, z2],) if shared else ([z1[0], z2[0]], [z1[1], z2[1]]):
+            row[0][:], row[1][:] = pairs(rng, n, inf_share=0.0)
+        z1 = z1.astype(np.float32).astype(np.float64)
+        z2 = z2.astype(np.float32).astype(np.float64)
+        w = rng.standard_normal((2, n)).astype(np.float32).astype(np.float64)
+        _ORACLE_CACHE[key] = (params, z1, z2, w, ref_between_vjp(kind, params, z1, z2, w))
+    return _ORACLE_CACHE[key]
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind,shared", [("DC", True), ("DM", False)])
+def test_between_vjp_eight_pairs_per_lane(kind, shared, dt):
+    """Rows of 8300 limit pairs (8 per lane in the adjoint, several blocks and a ragged
+    tail) against the oracle, shared and per-cosmology limits."""
+    params, z1, z2, w, (rgp, sp, r1, r2, s1, s2) = _mid_case(kind, shared)
+    p = torch.tensor(params, device=DEV)
+    a = torch.tensor(z1, dtype=dt, device=DEV)
+    b = torch.tensor(z2, dtype=dt, device=DEV)
+    wt = torch.tensor(w, dtype=dt, device=DEV)
+    val, gp, g1, g2 = cosmo.cosmo_distance_between_vjp(kind, p, a, b, wt, want_value=True)
+    tol = GTOL[dt]
+    ep = np.abs(gp.cpu().numpy() - rgp) / sp
+    assert ep.max() <= (5 * tol if dt == torch.float32 else tol), (kind, dt, ep.max(0))
+    if shared:
+        r1, r2, s1, s2 = r1.sum(0), r2.sum(0), s1.sum(0), s2.sum(0)
+    for got, ref, sc in ((g1, r1, s1), (g2, r2, s2)):
+        e = np.abs(got.double().cpu().numpy() - ref) / np.maximum(sc, 1e-12 * sc.max())
+        assert e.max() <= tol, (kind, dt, float(e.max()))
+    check(kind, dt, params, z1, z2, val, "value from the adjoint, 8 pairs per lane")
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_between_vjp_full_size_sampled(dt):
+    """The benchmark's launch: D_A from lens to source, the 256 cosmologies of the large
+    batch x 1e6 shared pairs, value and gradients in one pass.  The limit gradients
+    (sums over all cosmologies) at 32 seeded sampled pairs against the oracle; the
+    parameter gradients (sums over all 1e6 pairs) against the sum of four launches over
+    quarters of the pairs, to the tolerance relative to a sampled estimate of the sum of
+    |w dD_A/dtheta|."""
+    params, _ = workloads.config5()
+    z1, z2 = workloads.lensing_pairs()
+    n_c, n_z = params.shape[0], z1.size
+    p = torch.tensor(params, device=DEV)
+    a = torch.tensor(z1, dtype=dt, device=DEV)
+    b = torch.tensor(z2, dtype=dt, device=DEV)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(workloads.cotangent_seed())
+    w = torch.randn((n_c, n_z), dtype=torch.float64, device=DEV, generator=gen).to(dt)
+    val, gp, g1, g2 = cosmo.cosmo_distance_between_vjp("DA", p, a, b, w, want_value=True)
+    _, zi = workloads.subsample(1, n_z, 32, seed=78)
+    zi = np.unique(zi)
+    ar = a.double().cpu().numpy()[zi]
+    br = b.double().cpu().numpy()[zi]
+    ws = w[:, torch.tensor(zi, device=DEV)].double().cpu().numpy()
+    rgp, sp, r1, r2, s1, s2 = ref_between_vjp("DA", params, ar, br, ws)
+    tol = GTOL[dt]
+    for got, ref, sc in ((g1, r1.sum(0), s1.sum(0)), (g2, r2.sum(0), s2.sum(0))):
+        got = got[torch.tensor(zi, device=DEV)].double().cpu().numpy()
+        e = np.abs(got - ref) / sc
+        assert e.max() <= tol, (dt, float(e.max()))
+    check("DA", dt, params, ar, br, val[:, torch.tensor(zi, device=DEV)], "full-size value from the adjoint")
+    del val, g1, g2
+    q = n_z // 4
+    parts = [cosmo.cosmo_distance_between_vjp("DA", p, a[k * q:(k + 1) * q], b[k * q:(k + 1) * q],
+                                              w[:, k * q:(k + 1) * q].contiguous(), want_z=False)[0]
+             for k in range(4)]
+    gsum = sum(parts).cpu().numpy()
+    scale = sp * (n_z / zi.size)  # sampled estimate of sum_z |w dD_A/dtheta| per cosmology
+    e = np.abs(gp.cpu().numpy() - gsum) / scale
+    assert e.max() <= tol, (dt, e.max(0))
