@@ -104,6 +104,46 @@ def cpu_baseline(params, z_by_path, mu_at, budget_s=12.0):
             "error_samples": {head: n, **{p: 200 for p in mu_at if p != head}}}
 
 
+def cpu_oracle_rate(label, call, n_total_c, n_total_z, budget_s=4.0, seed=4343):
+    """The CPU oracle on a bounded sample of a widened row's workload: call(ci, zi)
+    evaluates the sampled (cosmology, input) pairs; the sample grows until it takes
+    about a quarter of budget_s.  Returns the oracle's evals/s and the sample."""
+    from paper_2212_01937_amd import workloads
+    import oracle
+    n = 16
+    while True:
+        ci, zi = workloads.subsample(n_total_c, n_total_z, n, seed=seed + n)
+        t0 = time.perf_counter()
+        call(ci, zi)
+        dt = time.perf_counter() - t0
+        if dt > budget_s / 4 or n >= 2 ** 18:
+            break
+        n = int(min(n * max(2.0, (budget_s / 2) / max(dt, 1e-3)), 2 ** 18))
+    return {"value": n / dt, "unit": "evals/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{n} random pairs of the {label} workload"}
+
+
+def cpu_baseline_widened(params, z1, z2, zv):
+    """The oracle timed beside the widened rows: D_A from lens to source with its
+    gradients in the cosmology and both limits, and the comoving volume with its
+    gradients, on bounded samples of the workloads bench.py times."""
+    import oracle
+
+    def da(ci, zi):
+        for c in np.unique(ci):
+            m = ci == c
+            oracle.between("DA", params[c:c + 1], z1[zi[m]], z2[zi[m]], grad=True)
+
+    def vc(ci, zi):
+        for c in np.unique(ci):
+            m = ci == c
+            oracle.distance("VC", params[c:c + 1], zv[zi[m]], grad=True)
+    return {"DA_lens_value_and_grad": cpu_oracle_rate("lens-source D_A (value + gradients)", da, params.shape[0],
+                                                      z1.size),
+            "VC_value_and_grad": cpu_oracle_rate("comoving volume (value + gradients)", vc, params.shape[0],
+                                                 zv.size)}
+
+
 def timed(fn, steps, stream, torch):
     """Event-timed repetitions of fn on `stream`; returns (per-call ms list, wall ms per call)."""
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
@@ -264,6 +304,29 @@ def main():
             torch.cuda.empty_cache()
         results["between"] = btw
 
+    # the comoving volume V_C(z) on the large batch (the same cosmologies and shared
+    # redshifts as the headline step): forward, and value + gradient in one pass
+    if not args.skip_between:
+        vol = {"workload": f"comoving volume V_C(z), {n_c} cosmologies x {n_z} shared redshifts", "evals": evals}
+        for path in args.paths.split(","):
+            dt = torch.float32 if path == "f32" else torch.float64
+            zt = torch.tensor(z, dtype=dt, device=dev)
+            wv = torch.randn((n_c, n_z), dtype=torch.float64, device=dev, generator=gen).to(dt)
+
+            def vf():
+                return cosmo.cosmo_distance("VC", p, zt, workspace=ws)
+
+            def vg():
+                return cosmo.cosmo_distance_vjp("VC", p, zt, wv, want_value=True, workspace=ws)
+            for label, fn in (("fwd", vf), ("value_and_grad", vg)):
+                fn()
+                ev, _, _ = timed(fn, max(2, args.steps // 2), stream, torch)
+                vol[f"{path}_{label}_ms"] = float(np.median(ev))
+                vol[f"{path}_{label}_evals_per_s"] = evals / (np.median(ev) * 1e-3)
+            del zt, wv
+            torch.cuda.empty_cache()
+        results["volume"] = vol
+
     # the supernova model of sec. 4: one variational-inference step (4 reparametrised
     # samples of the partial multivariate normal guide, ELBO, backward through the fused
     # likelihood, Adam) on a mock catalogue of 1e6 supernovae
@@ -378,6 +441,11 @@ def main():
         zp = {p: (z.astype(np.float32).astype(np.float64) if p == "f32" else z) for p in mus}
         order = sorted(mus, key=lambda p: p != head)
         line["cpu_baseline"] = cpu_baseline(params, zp, {p: at(p) for p in order})
+        if not args.skip_between:
+            bz1, bz2 = workloads.lensing_pairs(n=n_z)
+            wide = cpu_baseline_widened(params, bz1, bz2, z)
+            results["between"]["cpu_oracle_DA_lens_value_and_grad"] = wide["DA_lens_value_and_grad"]
+            results["volume"]["cpu_oracle_value_and_grad"] = wide["VC_value_and_grad"]
     print(json.dumps(line), flush=True)
 
 
