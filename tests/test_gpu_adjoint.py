@@ -397,3 +397,53 @@ def test_gaussian_loglike_edge_cases(dev):
     assert torch.isfinite(ll[0]) and torch.isnan(ll[1]) and torch.isnan(gp[1]).all() and torch.isfinite(gp[0]).all()
     ll, gp, gz = cosmo.cosmo_gaussian_loglike("MU", p[:1], torch.empty(0, **f64), torch.empty(0, **f64), sigma=0.1)
     assert torch.all(ll == 0) and torch.all(gp == 0) and gz.shape == (0,)
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_volume_config5_full_size_sampled(dev, dt):
+    """The comoving volume in the launch the benchmark times (256 cosmologies x 1e6
+    shared redshifts): the forward on 40 sampled pairs against the oracle (relative to
+    max(|V|, chi dV/dchi), the size a relative error of chi moves it by), and the
+    adjoint with a cotangent supported on those pairs, per cosmology and per redshift."""
+    params, z = workloads.config5()
+    n_c, n_z = params.shape[0], z.shape[0]
+    ci, zi = workloads.subsample(n_c, n_z, 40, seed=779)
+    key = ci * n_z + zi
+    _, first = np.unique(key, return_index=True)
+    ci, zi = ci[first], zi[first]
+    p = torch.tensor(params, device=dev)
+    zt = torch.tensor(z, dtype=dt, device=dev)
+    cit, zit = torch.tensor(ci, device=dev), torch.tensor(zi, device=dev)
+    v = cosmo.cosmo_distance("VC", p, zt)[cit, zit].double().cpu().numpy()
+    zr = zt.double().cpu().numpy()
+    wv = np.random.default_rng(6).normal(size=ci.shape[0])
+    w = torch.zeros((n_c, n_z), dtype=dt, device=dev)
+    w[cit, zit] = torch.tensor(wv, dtype=dt, device=dev)
+    gp, gz = cosmo.cosmo_distance_vjp("VC", p, zt, w)
+    gp = gp.cpu().numpy()
+    gz = gz.double().cpu().numpy()
+    wr = w[cit, zit].double().cpu().numpy()
+    rgp = np.zeros((n_c, 4))
+    sp = np.zeros((n_c, 4))
+    rgz, sgz = {}, {}
+    for k, (c, i, ww) in enumerate(zip(ci, zi, wr)):
+        ref, g = oracle.distance("VC", params[c:c + 1], np.array([zr[i]]), grad=True)
+        dc = oracle.distance("DC", params[c:c + 1], np.array([zr[i]]))[0, 0]
+        dh = 299792.458 / params[c, 0]
+        ok = 1 - params[c, 1:].sum()
+        chi = dc / dh
+        s = np.sin(np.sqrt(-ok) * chi) / np.sqrt(-ok) if ok < 0 else (
+            np.sinh(np.sqrt(ok) * chi) / np.sqrt(ok) if ok > 0 else chi)
+        scale = max(abs(ref[0, 0]), 4 * np.pi * dh ** 3 * chi * s ** 2)
+        assert abs(v[k] - ref[0, 0]) <= {torch.float64: 1e-12, torch.float32: 1e-6}[dt] * scale, (c, i, v[k], ref)
+        rgp[c] += ww * g[0, 0, :4]
+        sp[c] += np.abs(ww * g[0, 0, :4])
+        rgz[i] = rgz.get(i, 0.0) + ww * g[0, 0, 4]
+        sgz[i] = sgz.get(i, 0.0) + abs(ww * g[0, 0, 4])
+    touched = np.unique(ci)
+    ep = np.abs(gp[touched] - rgp[touched]) / sp[touched]
+    tol = TOL[dt]
+    assert np.all(ep.max(0) <= np.array([tol, tol, tol, 5 * tol if dt == torch.float32 else tol])), ep.max(0)
+    assert np.all(gp[np.setdiff1d(np.arange(n_c), touched)] == 0.0)
+    for i, r in rgz.items():
+        assert abs(gz[i] - r) <= tol * sgz[i], (i, gz[i], r)
