@@ -30,9 +30,9 @@ __global__ void k_setup(const double *__restrict__ params, int64_t n, CosmoRec *
                         int32_t *__restrict__ info) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
-    CosmoRec r;
+    // built in place: a private record would live in scratch memory (~0.5 KB per lane)
+    CosmoRec &r = recs[c];
     setup_cosmo(params + 4 * c, r);
-    recs[c] = r;
     if (info) info[c] = r.info;
 }
 
@@ -216,7 +216,9 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 // registers, then over the wave, and each wave writes its own partial (no block
 // barrier).  The shared-z gradient is summed over the tile's cosmologies in
 // thread-private LDS slots (gzl[k][t]), which keeps the rolled k-loop free of
-// dynamically indexed register arrays.
+// dynamically indexed register arrays.  Both partials are stored in the lane
+// precision (they are sums in that precision already) and summed in FP64 by
+// k_finalize_params and k_reduce_gz.
 template <typename T, int KIND, bool PAIR, int ZPT, bool LIKE>
 __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T *__restrict__ z, int64_t n_z,
                                           int64_t zstride, const T *__restrict__ cot, const T *__restrict__ ivar,
@@ -257,8 +259,8 @@ template <typename T, int KIND, int ZPT, bool LIKE>
 __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_vjp(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
                                                  const T *__restrict__ z, int64_t n_z, int64_t zstride,
                                                  const T *__restrict__ cot, const T *__restrict__ ivar,
-                                                 const double *__restrict__ wcs, double *__restrict__ pacc,
-                                                 T *__restrict__ gz_out, double *__restrict__ gz_part,
+                                                 const double *__restrict__ wcs, T *__restrict__ pacc,
+                                                 T *__restrict__ gz_out, T *__restrict__ gz_part,
                                                  T *__restrict__ out, int32_t *__restrict__ info,
                                                  int ct, int64_t nzb) {
     __shared__ T gzl[ZPT * kBlock];
@@ -299,7 +301,7 @@ __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_vjp(
                 // the quadrature slots away from small z) skip the reduction
                 T v = T(0);
                 if (__ballot(acc[s] != T(0))) v = wave_sum(acc[s]);
-                if (lane == 0) pacc[(c * nwz + gw) * kAcc + s] = (double)v;
+                if (lane == 0) pacc[(c * nwz + gw) * kAcc + s] = v;
             }
         }
     }
@@ -308,7 +310,7 @@ __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_vjp(
             const int64_t i = base + (int64_t)k * kBlock;
             if (i >= n_z) break;
             const T v = gzl[k * kBlock + threadIdx.x];
-            if (gz_part) gz_part[tile * n_z + i] = (double)v;
+            if (gz_part) gz_part[tile * n_z + i] = v;
             else gz_out[i] = v;
         }
     }
@@ -369,9 +371,9 @@ template <typename T, int KIND, int ZPT>
 __global__ __launch_bounds__(kBlock) void k_between_vjp(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
                                                         const T *__restrict__ z1, const T *__restrict__ z2,
                                                         int64_t n_z, int64_t zstride, const T *__restrict__ cot,
-                                                        double *__restrict__ pacc, T *__restrict__ g1_out,
-                                                        T *__restrict__ g2_out, double *__restrict__ g1_part,
-                                                        double *__restrict__ g2_part, T *__restrict__ out, int ct,
+                                                        T *__restrict__ pacc, T *__restrict__ g1_out,
+                                                        T *__restrict__ g2_out, T *__restrict__ g1_part,
+                                                        T *__restrict__ g2_part, T *__restrict__ out, int ct,
                                                         int64_t nzb) {
     __shared__ T gl1[ZPT * kBlock], gl2[ZPT * kBlock];
     const int64_t b = blockIdx.x;
@@ -410,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_between_vjp(const CosmoRec *__restri
             for (int s = 0; s < kAcc; ++s) {
                 T v = T(0);
                 if (__ballot(acc[s] != T(0))) v = wave_sum(acc[s]);
-                if (lane == 0) pacc[(c * nwz + gw) * kAcc + s] = (double)v;
+                if (lane == 0) pacc[(c * nwz + gw) * kAcc + s] = v;
             }
         }
     }
@@ -420,11 +422,11 @@ __global__ __launch_bounds__(kBlock) void k_between_vjp(const CosmoRec *__restri
             if (i >= n_z) break;
             const T v1 = gl1[k * kBlock + threadIdx.x], v2 = gl2[k * kBlock + threadIdx.x];
             if (g1_out) {
-                if (g1_part) g1_part[tile * n_z + i] = (double)v1;
+                if (g1_part) g1_part[tile * n_z + i] = v1;
                 else g1_out[i] = v1;
             }
             if (g2_out) {
-                if (g2_part) g2_part[tile * n_z + i] = (double)v2;
+                if (g2_part) g2_part[tile * n_z + i] = v2;
                 else g2_out[i] = v2;
             }
         }
@@ -501,8 +503,9 @@ __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_jac(
     }
 }
 
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_finalize_params(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
-                                                            const double *__restrict__ pacc, int64_t nwz,
+                                                            const T *__restrict__ pacc, int64_t nwz,
                                                             int kind, int fp32, double *__restrict__ grad,
                                                             double *__restrict__ loglike) {
     __shared__ double red[kBlock / 64][kAcc];
@@ -513,7 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_params(const CosmoRec *__re
     for (int s = 0; s < kAcc; ++s) acc[s] = 0.0;
     for (int64_t q = threadIdx.x; q < nwz; q += kBlock)
 #pragma unroll
-        for (int s = 0; s < kAcc; ++s) acc[s] += pacc[(c * nwz + q) * kAcc + s];
+        for (int s = 0; s < kAcc; ++s) acc[s] += (double)pacc[(c * nwz + q) * kAcc + s];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
     for (int s = 0; s < kAcc; ++s) {
@@ -551,11 +554,11 @@ template <typename T> __global__ void k_fill_zero(T *__restrict__ p, int64_t n) 
 }
 
 template <typename T>
-__global__ void k_reduce_gz(const double *__restrict__ part, int64_t ntile, int64_t n_z, T *__restrict__ out) {
+__global__ void k_reduce_gz(const T *__restrict__ part, int64_t ntile, int64_t n_z, T *__restrict__ out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_z) return;
     double s = 0.0;
-    for (int64_t t = 0; t < ntile; ++t) s += part[t * n_z + i];
+    for (int64_t t = 0; t < ntile; ++t) s += (double)part[t * n_z + i];
     out[i] = (T)s;
 }
 
@@ -765,8 +768,8 @@ int launch_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int6
     const int zpt = vjp_zpt(n_z);
     Tiling t = tiling(n_cosmo, n_z, zpt);
     const bool like = ivar != nullptr;
-    double *pacc = (grad_params || loglike) ? (double *)(ws + L.pacc) : nullptr;
-    double *gzp = (grad_z && zstride == 0 && t.ntile > 1 && n_z > 0) ? (double *)(ws + L.gzp) : nullptr;
+    T *pacc = (grad_params || loglike) ? (T *)(ws + L.pacc) : nullptr;
+    T *gzp = (grad_z && zstride == 0 && t.ntile > 1 && n_z > 0) ? (T *)(ws + L.gzp) : nullptr;
     dim3 grid((unsigned)t.nblocks), block(kBlock);
 #define COSMO_VJP_Z(K, Z, LK)                                                                                   \
     hipLaunchKernelGGL((k_vjp<T, K, Z, LK>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, cot, ivar, wc,  \
@@ -793,7 +796,7 @@ int launch_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int6
 #undef COSMO_VJP_Z
     if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
     if (pacc) {
-        hipLaunchKernelGGL(k_finalize_params, dim3((unsigned)n_cosmo), dim3(kBlock), 0, s, recs, n_cosmo, pacc,
+        hipLaunchKernelGGL(k_finalize_params<T>, dim3((unsigned)n_cosmo), dim3(kBlock), 0, s, recs, n_cosmo, pacc,
                            t.nzb * (kBlock / 64), kind, (int)(sizeof(T) == 4), grad_params, loglike);
         if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
     }
@@ -811,10 +814,10 @@ int launch_between_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T 
                        const WsLayout &L, char *ws, hipStream_t s) {
     const int zpt = vjp_zpt(n_z);
     Tiling t = tiling(n_cosmo, n_z, zpt);
-    double *pacc = grad_params ? (double *)(ws + L.pacc) : nullptr;
+    T *pacc = grad_params ? (T *)(ws + L.pacc) : nullptr;
     const bool part = zstride == 0 && t.ntile > 1 && n_z > 0;
-    double *p1 = (part && g1) ? (double *)(ws + L.gzp) : nullptr;
-    double *p2 = (part && g2) ? (double *)(ws + L.gzp) + (size_t)t.ntile * (size_t)n_z : nullptr;
+    T *p1 = (part && g1) ? (T *)(ws + L.gzp) : nullptr;
+    T *p2 = (part && g2) ? (T *)(ws + L.gzp) + (size_t)t.ntile * (size_t)n_z : nullptr;
     dim3 grid((unsigned)t.nblocks), block(kBlock);
 #define COSMO_BVJP_Z(K, Z)                                                                                      \
     hipLaunchKernelGGL((k_between_vjp<T, K, Z>), grid, block, 0, s, recs, n_cosmo, z1, z2, n_z, zstride, cot,   \
@@ -831,7 +834,7 @@ int launch_between_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T 
 #undef COSMO_BVJP_Z
     if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
     if (pacc) {
-        hipLaunchKernelGGL(k_finalize_params, dim3((unsigned)n_cosmo), dim3(kBlock), 0, s, recs, n_cosmo, pacc,
+        hipLaunchKernelGGL(k_finalize_params<T>, dim3((unsigned)n_cosmo), dim3(kBlock), 0, s, recs, n_cosmo, pacc,
                            t.nzb * (kBlock / 64), kind, (int)(sizeof(T) == 4), grad_params, (double *)nullptr);
         if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
     }
