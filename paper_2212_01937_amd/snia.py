@@ -76,8 +76,9 @@ class PMVNGuide(torch.nn.Module):
         zero = torch.zeros((), dtype=torch.float64, device=l00.device)
         return torch.stack([torch.stack([l00, zero]), torch.stack([l10, l11])])
 
-    def sample(self, n_samples, gen):
-        """Reparametrised draws: theta (S, 2), zeta (S, N) and log q(theta, zeta) (S,)."""
+    def draw(self, n_samples, gen):
+        """Reparametrised draws: theta (S, 2), zeta (S, N) and the standard normals
+        behind them, eg (S, 2) and el (S, N)."""
         dev = self.m.device
         n = self.a.shape[0]
         L = self.chol()
@@ -89,7 +90,13 @@ class PMVNGuide(torch.nn.Module):
         # the per-supernova regression on the globals as two broadcast multiply-adds (a
         # (N, 2) x (2, S) product would go to a GEMM shaped badly for N ~ 1e6)
         zeta = self.a + dtheta[:, 0:1] * self.b[:, 0] + dtheta[:, 1:2] * self.b[:, 1] + s * el
-        logq = (-0.5 * (eg ** 2).sum(1) - torch.log(torch.diagonal(L)).sum()
+        return theta, zeta, eg, el
+
+    def sample(self, n_samples, gen):
+        """Reparametrised draws: theta (S, 2), zeta (S, N) and log q(theta, zeta) (S,)."""
+        theta, zeta, eg, el = self.draw(n_samples, gen)
+        n = self.a.shape[0]
+        logq = (-0.5 * (eg ** 2).sum(1) - torch.log(torch.diagonal(self.chol())).sum()
                 - 0.5 * (el ** 2).sum(1) - self.log_s.sum()
                 - 0.5 * (n + 2) * math.log(2 * math.pi))
         return theta, zeta, logq
@@ -97,11 +104,26 @@ class PMVNGuide(torch.nn.Module):
 
 def elbo(guide, zhat, muhat, n_samples, gen):
     """Monte-Carlo ELBO estimate (mean over n_samples draws): E_q[log p(theta, z(zeta))
-    + sum zeta (the Jacobian of z = exp(zeta)) - log q(theta, zeta)] + const."""
-    theta, zeta, logq = guide.sample(n_samples, gen)
+    + sum zeta (the Jacobian of z = exp(zeta)) - log q(theta, zeta)] + const.
+
+    Only the mean over draws is needed, so every per-supernova term (the photometric
+    likelihood, the redshift prior, the Jacobian and the guide's own density) enters
+    one elementwise expression over all (draw, supernova) pairs and one full sum: row
+    sums over a few long rows are slow on the GPU, a full sum is not.  Equal to the
+    mean over draws of log_joint + sum zeta - sample()'s log q - N log(2 pi)/2."""
+    theta, zeta, eg, el = guide.draw(n_samples, gen)
+    S, N = zeta.shape
     z = torch.exp(zeta).to(guide.dtype)
-    lp = log_joint(theta, z, zhat, muhat)
-    return (lp + zeta.sum(1) - 0.5 * zhat.shape[0] * math.log(2 * math.pi) - logq).mean()
+    obs = muhat.to(z.dtype).expand(S, N).contiguous()
+    ll_mu = cosmo.gaussian_loglike("MU", params_of(theta), z, obs, SIGMA_MU).sum()
+    zd = z.to(torch.float64)
+    sd = (1.0 + zd) * SIGMA_Z
+    per_sn = (-0.5 * ((zhat.to(torch.float64) - zd) / sd) ** 2 - torch.log(sd)
+              + (GAMMA_SHAPE - 1.0) * torch.log(zd) - BETA * zd + zeta + 0.5 * el ** 2)
+    const = S * N * (GAMMA_SHAPE * math.log(BETA) - math.lgamma(GAMMA_SHAPE)) - 0.5 * S * N * math.log(2 * math.pi)
+    logq_rest = (-0.5 * (eg ** 2).sum() - S * torch.log(torch.diagonal(guide.chol())).sum()
+                 - S * guide.log_s.sum() - 0.5 * S * (N + 2) * math.log(2 * math.pi))
+    return (ll_mu + per_sn.sum() + const - logq_rest) / S
 
 
 def fit(zhat, muhat, steps=2000, n_samples=4, lr=0.02, dtype=torch.float32, seed=0, theta0=(0.3, 0.7)):

@@ -55,3 +55,28 @@ def test_vi_fit_recovers_the_cosmology():
     assert np.all(np.isfinite(trace))
     assert np.mean(trace[-100:]) > np.mean(trace[:100])
     assert np.all(np.abs(m - th) <= 3 * sd + 0.02), (m, sd)
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_elbo_equals_per_draw_form(dt):
+    """The ELBO as one sum over all (draw, supernova) terms equals the mean over draws
+    of log p(theta, z) + sum zeta - log q(theta, zeta) - N log(2 pi)/2 built from the
+    per-draw log joint (checked against the oracle above) and the guide's log density,
+    on the same draws; and so do its gradients in the guide's parameters."""
+    _, zhat, muhat, _ = mock(3000, seed=31)
+    zh, mh = torch.tensor(zhat, device=DEV), torch.tensor(muhat, device=DEV)
+    guide = snia.PMVNGuide(zh, dtype=dt)
+    g1 = torch.Generator(device=DEV)
+    g1.manual_seed(9)
+    e1 = snia.elbo(guide, zh, mh, 4, g1)
+    grads1 = torch.autograd.grad(e1, list(guide.parameters()))
+    g2 = torch.Generator(device=DEV)
+    g2.manual_seed(9)
+    theta, zeta, logq = guide.sample(4, g2)
+    z = torch.exp(zeta).to(dt)
+    lp = snia.log_joint(theta, z, zh, mh)
+    e2 = (lp + zeta.sum(1) - 0.5 * zh.shape[0] * np.log(2 * np.pi) - logq).mean()
+    grads2 = torch.autograd.grad(e2, list(guide.parameters()))
+    assert abs(e1.item() - e2.item()) <= 1e-10 * abs(e2.item()), (e1.item(), e2.item())
+    for a, b in zip(grads1, grads2):
+        assert torch.allclose(a, b, rtol=1e-9, atol=1e-9 * b.abs().max().item()), (a, b)
