@@ -197,6 +197,44 @@ int cosmo_gaussian_loglike(cosmo_kind kind, cosmo_dtype dt, const double *params
                            void *grad_z, int32_t *info, void *workspace, size_t workspace_bytes,
                            void *stream);
 
+/* ---- the supernova model of sec. 4 (fig. 4b), the distance path as its inner loop ----
+ * Latent redshifts of n_sn supernovae under n_draws reparametrised draws of the partial
+ * multivariate normal guide (sec. 4): for draw s and supernova n
+ *   zeta[s][n] = a[n] + dtheta[s][0] b[n][0] + dtheta[s][1] b[n][1] + exp(log_s[n]) eps[s][n],
+ *   z[s][n]    = exp(zeta[s][n]), rounded once to dt.
+ * a, log_s, zhat: [n_sn] FP64; b: [n_sn][2] FP64; dtheta: [n_draws][2] FP64 (the draw's
+ * offset of (Om0, OL0) from the guide's mean); eps: [n_draws][n_sn] FP64 standard normals
+ * drawn by the caller.  All device pointers, caller-owned; asynchronous on `stream`.
+ * Errors: COSMO_E_DTYPE; COSMO_E_ARG for negative sizes, n_draws * n_sn beyond
+ * 2^32 - 1 blocks of 256, or a NULL array that the sizes require.                    */
+int snia_draw(cosmo_dtype dt, int64_t n_draws, int64_t n_sn, const double *a, const double *b,
+              const double *log_s, const double *dtheta, const double *eps, void *z, void *stream);
+
+/* snia_latent_vjp -- the per-supernova terms of the model's log joint density (sec. 4)
+ * and their adjoint, summed over draws and supernovae:
+ *   F = sum_{s,n} [ -1/2 ((zhat - z)/((1 + z) sigma_z))^2 - log((1 + z) sigma_z)
+ *                   + (gamma_shape - 1) log z - gamma_rate z + zeta + eps^2 / 2 ]
+ * (photometric redshift likelihood, Gamma redshift prior up to its constant, the
+ * Jacobian of z = exp(zeta) and the eps^2/2 of the guide density), with z recomputed
+ * as snia_draw does.  grad_z ([n_draws][n_sn] of dt, nullable) is an extra derivative
+ * d G/dz of terms computed elsewhere (the distance likelihood of cosmo_gaussian_loglike);
+ * the adjoint is that of F + G:
+ *   value_dtheta[0]          = F (FP64),
+ *   value_dtheta[1 + 2s + j] = d(F + G)/d dtheta[s][j],
+ *   grad_a[n], grad_b[n][j], grad_log_s[n] = d(F + G)/d a[n], b[n][j], log_s[n]   (FP64).
+ * value_dtheta: [1 + 2 n_draws]; overwritten (zeros for empty sizes).
+ * workspace: snia_workspace_size(n_draws, n_sn) bytes, or NULL (allocated on stream).
+ * Errors: as snia_draw; COSMO_E_ARG also unless sigma_z, gamma_shape and gamma_rate
+ * are finite and positive; COSMO_E_WORKSPACE for a workspace below the size.          */
+int snia_latent_vjp(cosmo_dtype dt, int64_t n_draws, int64_t n_sn, const double *a, const double *b,
+                    const double *log_s, const double *dtheta, const double *eps, const double *zhat,
+                    const void *grad_z, double sigma_z, double gamma_shape, double gamma_rate,
+                    double *value_dtheta, double *grad_a, double *grad_b, double *grad_log_s,
+                    void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes of snia_latent_vjp.  COSMO_E_ARG for invalid sizes or NULL bytes. */
+int snia_workspace_size(int64_t n_draws, int64_t n_sn, size_t *bytes);
+
 /* Library version string (static storage). */
 const char *cosmo_version(void);
 

@@ -29,7 +29,7 @@ INFO = {"CUBIC": 0x1, "QUARTIC": 0x2, "THREE_REAL": 0x4, "YELLOW": 0x8, "RED": 0
 EXPORTS = ("cosmo_workspace_size", "cosmo_roots", "carlson_rf", "carlson_rd", "carlson_rj",
            "carlson_rc", "cosmo_distance", "cosmo_distance_between", "cosmo_distance_between_vjp",
            "cosmo_distance_vjp", "cosmo_distance_jac",
-           "cosmo_gaussian_loglike", "cosmo_version")
+           "cosmo_gaussian_loglike", "snia_draw", "snia_latent_vjp", "snia_workspace_size", "cosmo_version")
 
 _lib = None
 
@@ -65,6 +65,11 @@ def load():
                                        ctypes.c_size_t, vp]
     lib.cosmo_gaussian_loglike.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, vp, vp, vp,
                                            vp, i32p, vp, ctypes.c_size_t, vp]
+    f64 = ctypes.c_double
+    lib.snia_draw.argtypes = [ctypes.c_int, i64, i64, vp, vp, vp, vp, vp, vp, vp]
+    lib.snia_latent_vjp.argtypes = [ctypes.c_int, i64, i64, vp, vp, vp, vp, vp, vp, vp, f64, f64, f64, vp, vp, vp,
+                                    vp, vp, ctypes.c_size_t, vp]
+    lib.snia_workspace_size.argtypes = [i64, i64, ctypes.POINTER(ctypes.c_size_t)]
     for n in EXPORTS[:-1]:
         getattr(lib, n).restype = ctypes.c_int
     lib.cosmo_version.restype = ctypes.c_char_p
@@ -371,6 +376,62 @@ def gaussian_loglike(kind, params, z, obs, sigma):
     iv = (1.0 / torch.as_tensor(sigma, device=zc.device, dtype=torch.float64) ** 2).to(zc.dtype)
     return _GaussianLogLike.apply(kind, params, z, torch.as_tensor(obs, device=zc.device).to(zc.dtype),
                                   iv.expand(zc.shape[-1:] if zc.dim() == 1 else zc.shape).contiguous())
+
+
+def _f64(t, shape, name):
+    _need_gpu(t, name)
+    if t.dtype != torch.float64 or tuple(t.shape) != tuple(shape):
+        raise CosmoError(f"{name} must be float64 of shape {tuple(shape)}")
+    return t.contiguous()
+
+
+def snia_draw(a, b, log_s, dtheta, eps, dtype=torch.float32):
+    """Latent redshifts of the supernova model's guide (see include/cosmo.h: snia_draw):
+    z[s][n] = exp(a[n] + dtheta[s] . b[n] + exp(log_s[n]) eps[s][n]) in `dtype`."""
+    lib = load()
+    n_sn = a.shape[0]
+    S = dtheta.shape[0]
+    args = [_f64(a, (n_sn,), "a"), _f64(b, (n_sn, 2), "b"), _f64(log_s, (n_sn,), "log_s"),
+            _f64(dtheta, (S, 2), "dtheta"), _f64(eps, (S, n_sn), "eps")]
+    z = torch.empty((S, n_sn), dtype=dtype, device=a.device)
+    with torch.cuda.device(a.device):
+        rc = lib.snia_draw(DTYPES[dtype], S, n_sn, *(_ptr(t) for t in args), _ptr(z), _stream(a.device))
+    _check(rc, "snia_draw")
+    return z
+
+
+def snia_latent_vjp(a, b, log_s, dtheta, eps, zhat, grad_z, sigma_z, gamma_shape, gamma_rate, dtype=torch.float32,
+                    workspace=None):
+    """Per-supernova terms of the model's log joint summed over draws and supernovae,
+    and the adjoint of those terms plus an outside term whose z-gradient is grad_z (see
+    include/cosmo.h: snia_latent_vjp).  Returns (F, grad_dtheta [S, 2], grad_a,
+    grad_b [N, 2], grad_log_s), all float64."""
+    lib = load()
+    n_sn = a.shape[0]
+    S = dtheta.shape[0]
+    args = [_f64(a, (n_sn,), "a"), _f64(b, (n_sn, 2), "b"), _f64(log_s, (n_sn,), "log_s"),
+            _f64(dtheta, (S, 2), "dtheta"), _f64(eps, (S, n_sn), "eps"), _f64(zhat, (n_sn,), "zhat")]
+    gz = None
+    if grad_z is not None:
+        _need_gpu(grad_z, "grad_z")
+        if grad_z.dtype != dtype or tuple(grad_z.shape) != (S, n_sn):
+            raise CosmoError(f"grad_z must be {dtype} of shape {(S, n_sn)}")
+        gz = grad_z.contiguous()
+    dev = a.device
+    vd = torch.empty(1 + 2 * S, dtype=torch.float64, device=dev)
+    ga = torch.empty(n_sn, dtype=torch.float64, device=dev)
+    gb = torch.empty((n_sn, 2), dtype=torch.float64, device=dev)
+    gl = torch.empty(n_sn, dtype=torch.float64, device=dev)
+    if workspace is None:
+        nb = ctypes.c_size_t()
+        _check(lib.snia_workspace_size(S, n_sn, ctypes.byref(nb)), "snia_workspace_size")
+        workspace = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=dev)
+    with torch.cuda.device(dev):
+        rc = lib.snia_latent_vjp(DTYPES[dtype], S, n_sn, *(_ptr(t) for t in args), _ptr(gz), float(sigma_z),
+                                 float(gamma_shape), float(gamma_rate), _ptr(vd), _ptr(ga), _ptr(gb), _ptr(gl),
+                                 _ptr(workspace), workspace.numel(), _stream(dev))
+    _check(rc, "snia_latent_vjp")
+    return vd[0], vd[1:].reshape(S, 2), ga, gb, gl
 
 
 class _Distance(torch.autograd.Function):

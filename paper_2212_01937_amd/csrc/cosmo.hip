@@ -562,6 +562,107 @@ __global__ void k_reduce_gz(const T *__restrict__ part, int64_t ntile, int64_t n
     out[i] = (T)s;
 }
 
+// ---------------------------------------------------------------- supernova model (sec. 4)
+// The per-supernova part of the variational objective of the SN Ia model (fig. 4b):
+// latent redshifts z = exp(zeta) drawn from the partial multivariate normal guide,
+//   zeta[s][n] = a[n] + dtheta[s] . b[n] + exp(log_s[n]) eps[s][n],
+// and, per draw s and supernova n, the photometric likelihood N(zhat | z, (1+z)^2 sz^2),
+// the Gamma(shape, rate) redshift prior (up to its constant), the Jacobian zeta of
+// z = exp(zeta) and the eps^2/2 of the guide's density.  All arithmetic in FP64; z is
+// rounded once to the distance path's precision T, and the terms use that rounded z
+// (the z the distance likelihood sees).
+struct SniaConst {
+    double sigma_z, shape, rate;
+};
+
+template <typename T>
+__global__ void k_snia_draw(int64_t S, int64_t N, const double *__restrict__ a, const double *__restrict__ b,
+                            const double *__restrict__ log_s, const double *__restrict__ dth,
+                            const double *__restrict__ eps, T *__restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S * N) return;
+    const int64_t s = i / N, n = i - s * N;
+    const double zeta = a[n] + dth[2 * s] * b[2 * n] + dth[2 * s + 1] * b[2 * n + 1] + exp(log_s[n]) * eps[i];
+    z[i] = (T)exp(zeta);
+}
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads(); // the previous use of red is complete
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+    return t;
+}
+
+// One lane per supernova, the draws in a loop.  With G[s][n] the derivative of
+//   F = sum_{s,n} term[s][n] + sum_s loglike_s(z[s])
+// with respect to zeta[s][n] (grad_z[s][n] = d loglike_s / dz[s][n], from the fused
+// distance likelihood, enters through dz/dzeta = z):
+//   grad_a[n] = sum_s G,  grad_b[n] = sum_s G dtheta[s],  grad_log_s[n] = sum_s G s_n eps,
+// and per block the partial sums of F's terms and of sum_n G b[n] (the dtheta[s]
+// gradient), part[blk][1 + 2S].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_snia_latent(int64_t S, int64_t N, const double *__restrict__ a,
+                                                        const double *__restrict__ b,
+                                                        const double *__restrict__ log_s,
+                                                        const double *__restrict__ dth,
+                                                        const double *__restrict__ eps,
+                                                        const double *__restrict__ zhat,
+                                                        const T *__restrict__ gz, SniaConst k,
+                                                        double *__restrict__ ga, double *__restrict__ gb,
+                                                        double *__restrict__ gls, double *__restrict__ part) {
+    __shared__ double red[kBlock / 64];
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool act = n < N;
+    double an = 0.0, b0 = 0.0, b1 = 0.0, sn = 0.0, zh = 0.0;
+    if (act) {
+        an = a[n]; b0 = b[2 * n]; b1 = b[2 * n + 1]; sn = exp(log_s[n]); zh = zhat[n];
+    }
+    const double isz = 1.0 / k.sigma_z;
+    double vsum = 0.0, sa = 0.0, sb0 = 0.0, sb1 = 0.0, sls = 0.0;
+    double *out = part + (int64_t)blockIdx.x * (1 + 2 * S);
+    for (int64_t s = 0; s < S; ++s) {
+        const double d0 = dth[2 * s], d1 = dth[2 * s + 1];
+        double g = 0.0;
+        if (act) {
+            const double e = eps[s * N + n];
+            const double zeta = an + d0 * b0 + d1 * b1 + sn * e;
+            const double ez = exp(zeta);
+            const double zd = (double)(T)ez;
+            const double x = 1.0 + zd, ix = 1.0 / x;
+            const double r = (zh - zd) * ix * isz; // (zhat - z) / ((1 + z) sigma_z)
+            vsum += -0.5 * r * r - log(x * k.sigma_z) + (k.shape - 1.0) * log(zd) - k.rate * zd + zeta + 0.5 * e * e;
+            // d/dz of the photometric, normalisation and prior terms
+            const double dv = r * (1.0 + zh) * ix * ix * isz - ix + (k.shape - 1.0) / zd - k.rate;
+            const double dl = gz ? (double)gz[s * N + n] : 0.0;
+            g = (dv + dl) * ez + 1.0;
+            sa += g; sb0 += g * d0; sb1 += g * d1; sls += g * sn * e;
+        }
+        const double p0 = block_sum(g * b0, red), p1 = block_sum(g * b1, red);
+        if (threadIdx.x == 0) { out[1 + 2 * s] = p0; out[2 + 2 * s] = p1; }
+    }
+    const double v = block_sum(vsum, red);
+    if (threadIdx.x == 0) out[0] = v;
+    if (act) {
+        ga[n] = sa; gb[2 * n] = sb0; gb[2 * n + 1] = sb1; gls[n] = sls;
+    }
+}
+
+// out[q] = sum over blocks of part[blk][q], q < nq (one block per quantity).
+__global__ __launch_bounds__(kBlock) void k_sum_parts(const double *__restrict__ part, int64_t nblk, int64_t nq,
+                                                      double *__restrict__ out) {
+    __shared__ double red[kBlock / 64];
+    const int64_t q = blockIdx.x;
+    double v = 0.0;
+    for (int64_t t = threadIdx.x; t < nblk; t += kBlock) v += part[t * nq + q];
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) out[q] = v;
+}
+
 // ---------------------------------------------------------------- Carlson entry kernels
 template <typename T, int WHICH>
 __global__ void k_carlson(int64_t n, const T *__restrict__ x, const T *__restrict__ y, const T *__restrict__ z,
@@ -885,6 +986,18 @@ int check_grid(int64_t n_cosmo, int64_t n_z) {
     return COSMO_OK;
 }
 
+size_t snia_ws_bytes(int64_t n_draws, int64_t n_sn) {
+    const int64_t nblk = (n_sn + kBlock - 1) / kBlock;
+    return align256(sizeof(double) * (size_t)nblk * (size_t)(1 + 2 * n_draws));
+}
+
+bool snia_sizes_ok(int64_t n_draws, int64_t n_sn) {
+    if (n_draws < 0 || n_sn < 0) return false;
+    if (n_draws > 0 && n_sn > ((int64_t)0xFFFFFFFFll * kBlock) / n_draws) return false; // one lane per (draw, SN)
+    if (2 * n_draws + 1 > 0x7FFFFFFFll) return false;
+    return true;
+}
+
 } // namespace
 
 extern "C" {
@@ -1121,6 +1234,72 @@ int cosmo_gaussian_loglike(cosmo_kind kind, cosmo_dtype dt, const double *params
     return launch_vjp<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, (const double *)obs,
                               (const double *)ivar, wc, loglike, nullptr, grad_params, (double *)grad_z, info, L,
                               (char *)ws.ptr, s);
+}
+
+
+int snia_workspace_size(int64_t n_draws, int64_t n_sn, size_t *bytes) {
+    if (!bytes || !snia_sizes_ok(n_draws, n_sn)) return COSMO_E_ARG;
+    *bytes = snia_ws_bytes(n_draws, n_sn);
+    return COSMO_OK;
+}
+
+int snia_draw(cosmo_dtype dt, int64_t n_draws, int64_t n_sn, const double *a, const double *b, const double *log_s,
+              const double *dtheta, const double *eps, void *z, void *stream) {
+    if (!valid_dtype(dt)) return COSMO_E_DTYPE;
+    if (!snia_sizes_ok(n_draws, n_sn)) return COSMO_E_ARG;
+    if (n_draws == 0 || n_sn == 0) return COSMO_OK;
+    if (!a || !b || !log_s || !dtheta || !eps || !z) return COSMO_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t tot = n_draws * n_sn;
+    const dim3 grid((unsigned)((tot + kBlock - 1) / kBlock));
+    if (dt == COSMO_F32) hipLaunchKernelGGL(k_snia_draw<float>, grid, dim3(kBlock), 0, s, n_draws, n_sn, a, b, log_s, dtheta, eps, (float *)z);
+    else hipLaunchKernelGGL(k_snia_draw<double>, grid, dim3(kBlock), 0, s, n_draws, n_sn, a, b, log_s, dtheta, eps, (double *)z);
+    return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
+}
+
+int snia_latent_vjp(cosmo_dtype dt, int64_t n_draws, int64_t n_sn, const double *a, const double *b,
+                    const double *log_s, const double *dtheta, const double *eps, const double *zhat,
+                    const void *grad_z, double sigma_z, double gamma_shape, double gamma_rate,
+                    double *value_dtheta, double *grad_a, double *grad_b, double *grad_log_s, void *workspace,
+                    size_t workspace_bytes, void *stream) {
+    if (!valid_dtype(dt)) return COSMO_E_DTYPE;
+    if (!snia_sizes_ok(n_draws, n_sn)) return COSMO_E_ARG;
+    if (!(sigma_z > 0.0) || !(gamma_shape > 0.0) || !(gamma_rate > 0.0) || !__builtin_isfinite(sigma_z) ||
+        !__builtin_isfinite(gamma_shape) || !__builtin_isfinite(gamma_rate))
+        return COSMO_E_ARG;
+    if (!value_dtheta) return COSMO_E_ARG;
+    if (n_sn > 0 && (!grad_a || !grad_b || !grad_log_s)) return COSMO_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_draws == 0 || n_sn == 0) {
+        // empty sums (fill kernels, no memset)
+        const int64_t nq = 1 + 2 * n_draws;
+        hipLaunchKernelGGL(k_fill_zero<double>, dim3((unsigned)((nq + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           value_dtheta, nq);
+        if (n_sn > 0) {
+            const dim3 g1((unsigned)((n_sn + kBlock - 1) / kBlock)), g2((unsigned)((2 * n_sn + kBlock - 1) / kBlock));
+            hipLaunchKernelGGL(k_fill_zero<double>, g1, dim3(kBlock), 0, s, grad_a, n_sn);
+            hipLaunchKernelGGL(k_fill_zero<double>, g2, dim3(kBlock), 0, s, grad_b, 2 * n_sn);
+            hipLaunchKernelGGL(k_fill_zero<double>, g1, dim3(kBlock), 0, s, grad_log_s, n_sn);
+        }
+        return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
+    }
+    if (!a || !b || !log_s || !dtheta || !eps || !zhat) return COSMO_E_ARG;
+    Workspace ws;
+    int rc = ws.acquire(workspace, workspace_bytes, snia_ws_bytes(n_draws, n_sn), s);
+    if (rc != COSMO_OK) return rc;
+    double *part = (double *)ws.ptr;
+    const int64_t nblk = (n_sn + kBlock - 1) / kBlock;
+    const SniaConst k{sigma_z, gamma_shape, gamma_rate};
+    if (dt == COSMO_F32)
+        hipLaunchKernelGGL(k_snia_latent<float>, dim3((unsigned)nblk), dim3(kBlock), 0, s, n_draws, n_sn, a, b, log_s,
+                           dtheta, eps, zhat, (const float *)grad_z, k, grad_a, grad_b, grad_log_s, part);
+    else
+        hipLaunchKernelGGL(k_snia_latent<double>, dim3((unsigned)nblk), dim3(kBlock), 0, s, n_draws, n_sn, a, b,
+                           log_s, dtheta, eps, zhat, (const double *)grad_z, k, grad_a, grad_b, grad_log_s, part);
+    if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)(1 + 2 * n_draws)), dim3(kBlock), 0, s, part, nblk,
+                       1 + 2 * n_draws, value_dtheta);
+    return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
 }
 
 } // extern "C"

@@ -76,15 +76,19 @@ class PMVNGuide(torch.nn.Module):
         zero = torch.zeros((), dtype=torch.float64, device=l00.device)
         return torch.stack([torch.stack([l00, zero]), torch.stack([l10, l11])])
 
+    def normals(self, n_samples, gen):
+        """The standard normals behind one set of draws: eg (S, 2) for the globals and
+        el (S, N) for the latent redshifts (drawn in that order)."""
+        dev = self.m.device
+        eg = torch.randn((n_samples, 2), dtype=torch.float64, device=dev, generator=gen)
+        el = torch.randn((n_samples, self.a.shape[0]), dtype=torch.float64, device=dev, generator=gen)
+        return eg, el
+
     def draw(self, n_samples, gen):
         """Reparametrised draws: theta (S, 2), zeta (S, N) and the standard normals
         behind them, eg (S, 2) and el (S, N)."""
-        dev = self.m.device
-        n = self.a.shape[0]
-        L = self.chol()
-        eg = torch.randn((n_samples, 2), dtype=torch.float64, device=dev, generator=gen)
-        el = torch.randn((n_samples, n), dtype=torch.float64, device=dev, generator=gen)
-        dtheta = eg @ L.T
+        eg, el = self.normals(n_samples, gen)
+        dtheta = eg @ self.chol().T
         theta = self.m + dtheta
         s = torch.exp(self.log_s)
         # the per-supernova regression on the globals as two broadcast multiply-adds (a
@@ -102,28 +106,65 @@ class PMVNGuide(torch.nn.Module):
         return theta, zeta, logq
 
 
+class _SupernovaTerms(torch.autograd.Function):
+    """sum_s loglike_mu(theta_s, z_s) + sum_{s,n} (photometric likelihood + redshift
+    prior + Jacobian + eps^2/2) as a function of the guide's per-supernova parameters
+    (a, b, log_s) and each draw's (dtheta, theta): the latent redshifts by snia_draw,
+    the distance likelihood and its z- and theta-gradients by cosmo_gaussian_loglike,
+    the remaining terms and the adjoint to the guide by snia_latent_vjp.  Value and
+    gradients come from the one forward pass; the backward scales them."""
+
+    @staticmethod
+    def forward(ctx, a, b, log_s, dtheta, theta, eps, zhat, obs, ivar, dtype):
+        a, b, log_s, dtheta, theta = (t.detach() for t in (a, b, log_s, dtheta, theta))
+        z = cosmo.snia_draw(a, b, log_s, dtheta, eps, dtype)
+        ll, gp, gz = cosmo.cosmo_gaussian_loglike("MU", params_of(theta), z, obs, ivar=ivar)
+        F, gd, ga, gb, gl = cosmo.snia_latent_vjp(a, b, log_s, dtheta, eps, zhat, gz, SIGMA_Z, GAMMA_SHAPE, BETA,
+                                                  dtype)
+        ctx.save_for_backward(ga, gb, gl, gd, gp[:, 1:3])
+        return ll.sum() + F
+
+    @staticmethod
+    def backward(ctx, go):
+        ga, gb, gl, gd, gth = ctx.saved_tensors
+        return go * ga, go * gb, go * gl, go * gd, go * gth, None, None, None, None, None
+
+
+def _planes(guide, muhat, S, dtype):
+    """Observed magnitudes and inverse variances laid out as the latent redshifts
+    (S, N) in the distance precision, kept between steps."""
+    key = (S, dtype, muhat.data_ptr())
+    cache = getattr(guide, "_planes", None)
+    if cache is None or cache[0] != key:
+        N = muhat.shape[0]
+        obs = muhat.to(dtype).expand(S, N).contiguous()
+        ivar = torch.full((S, N), 1.0 / SIGMA_MU ** 2, dtype=dtype, device=muhat.device)
+        guide._planes = cache = (key, obs, ivar)
+    return cache[1], cache[2]
+
+
 def elbo(guide, zhat, muhat, n_samples, gen):
     """Monte-Carlo ELBO estimate (mean over n_samples draws): E_q[log p(theta, z(zeta))
     + sum zeta (the Jacobian of z = exp(zeta)) - log q(theta, zeta)] + const.
 
-    Only the mean over draws is needed, so every per-supernova term (the photometric
-    likelihood, the redshift prior, the Jacobian and the guide's own density) enters
-    one elementwise expression over all (draw, supernova) pairs and one full sum: row
-    sums over a few long rows are slow on the GPU, a full sum is not.  Equal to the
-    mean over draws of log_joint + sum zeta - sample()'s log q - N log(2 pi)/2."""
-    theta, zeta, eg, el = guide.draw(n_samples, gen)
-    S, N = zeta.shape
-    z = torch.exp(zeta).to(guide.dtype)
-    obs = muhat.to(z.dtype).expand(S, N).contiguous()
-    ll_mu = cosmo.gaussian_loglike("MU", params_of(theta), z, obs, SIGMA_MU).sum()
-    zd = z.to(torch.float64)
-    sd = (1.0 + zd) * SIGMA_Z
-    per_sn = (-0.5 * ((zhat.to(torch.float64) - zd) / sd) ** 2 - torch.log(sd)
-              + (GAMMA_SHAPE - 1.0) * torch.log(zd) - BETA * zd + zeta + 0.5 * el ** 2)
+    The per-supernova work (latent redshifts, distance likelihood, photometric
+    likelihood, redshift prior, Jacobian, the guide's density in eps, and all their
+    gradients) runs in the library's kernels (_SupernovaTerms); what stays here is the
+    algebra of the two global parameters.  Equal to the mean over draws of log_joint +
+    sum zeta - sample()'s log q - N log(2 pi)/2 on the same draws."""
+    S = n_samples
+    N = zhat.shape[0]
+    eg, el = guide.normals(S, gen)
+    L = guide.chol()
+    dtheta = eg @ L.T
+    theta = guide.m + dtheta
+    obs, ivar = _planes(guide, muhat, S, guide.dtype)
+    terms = _SupernovaTerms.apply(guide.a, guide.b, guide.log_s, dtheta, theta, el,
+                                  zhat.to(torch.float64).contiguous(), obs, ivar, guide.dtype)
     const = S * N * (GAMMA_SHAPE * math.log(BETA) - math.lgamma(GAMMA_SHAPE)) - 0.5 * S * N * math.log(2 * math.pi)
-    logq_rest = (-0.5 * (eg ** 2).sum() - S * torch.log(torch.diagonal(guide.chol())).sum()
+    logq_rest = (-0.5 * (eg ** 2).sum() - S * torch.log(torch.diagonal(L)).sum()
                  - S * guide.log_s.sum() - 0.5 * S * (N + 2) * math.log(2 * math.pi))
-    return (ll_mu + per_sn.sum() + const - logq_rest) / S
+    return (terms + const - logq_rest) / S
 
 
 def fit(zhat, muhat, steps=2000, n_samples=4, lr=0.02, dtype=torch.float32, seed=0, theta0=(0.3, 0.7)):

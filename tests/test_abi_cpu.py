@@ -126,3 +126,20 @@ def test_between_vjp_argument_errors(lib):
                                           null, null, 0, null) == E_ARG
     assert lib.cosmo_distance_between_vjp(0, 1, dummy, 1, null, dummy, 1, 0, dummy, null, dummy, null, null,
                                           null, null, 0, null) == E_ARG
+
+
+def test_supernova_entry_points_argument_errors(lib):
+    E_ARG, E_DTYPE = -1, -3
+    d = ctypes.c_void_p(0x1000)
+    assert lib.snia_draw(7, 1, 1, d, d, d, d, d, d, None) == E_DTYPE
+    assert lib.snia_draw(0, -1, 1, d, d, d, d, d, d, None) == E_ARG
+    assert lib.snia_draw(0, 2, 3, d, None, d, d, d, d, None) == E_ARG
+    assert lib.snia_draw(0, 0, 3, None, None, None, None, None, None, None) == 0  # nothing to draw
+    for sz, sh, rt in ((0.0, 3.0, 3.0), (0.04, 0.0, 3.0), (0.04, 3.0, -3.0), (float("inf"), 3.0, 3.0)):
+        assert lib.snia_latent_vjp(0, 2, 3, d, d, d, d, d, d, None, sz, sh, rt, d, d, d, d, None, 0, None) == E_ARG
+    assert lib.snia_latent_vjp(0, 2, 3, d, d, d, d, d, d, None, 0.04, 3.0, 3.0, None, d, d, d, None, 0, None) == E_ARG
+    assert lib.snia_latent_vjp(0, 2, 3, d, d, d, d, d, d, None, 0.04, 3.0, 3.0, d, None, d, d, None, 0, None) == E_ARG
+    nb = ctypes.c_size_t()
+    assert lib.snia_workspace_size(4, 1000, ctypes.byref(nb)) == 0 and nb.value >= 8 * 4 * 9
+    assert lib.snia_workspace_size(-1, 1000, ctypes.byref(nb)) == E_ARG
+    assert lib.snia_workspace_size(4, 1000, None) == E_ARG
