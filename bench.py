@@ -344,7 +344,7 @@ def main():
         for path in args.paths.split(","):
             dt = torch.float32 if path == "f32" else torch.float64
             guide = snia.PMVNGuide(zhat, dtype=dt)
-            opt = torch.optim.Adam(guide.parameters(), lr=0.02)
+            opt = torch.optim.Adam(guide.parameters(), lr=0.02, fused=True)
             gsn = torch.Generator(device=dev)
             gsn.manual_seed(1)
 

@@ -575,27 +575,21 @@ struct SniaConst {
     double sigma_z, shape, rate;
 };
 
+// One lane per supernova, the draws in a loop (the per-supernova parameters are read
+// once; each draw's row of z is written coalesced).
 template <typename T>
-__global__ void k_snia_draw(int64_t S, int64_t N, const double *__restrict__ a, const double *__restrict__ b,
-                            const double *__restrict__ log_s, const double *__restrict__ dth,
-                            const double *__restrict__ eps, T *__restrict__ z) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S * N) return;
-    const int64_t s = i / N, n = i - s * N;
-    const double zeta = a[n] + dth[2 * s] * b[2 * n] + dth[2 * s + 1] * b[2 * n + 1] + exp(log_s[n]) * eps[i];
-    z[i] = (T)exp(zeta);
-}
-
-__device__ __forceinline__ double block_sum(double v, double *red) {
-    v = wave_sum(v);
-    const int wave = threadIdx.x >> 6;
-    __syncthreads(); // the previous use of red is complete
-    if ((threadIdx.x & 63) == 0) red[wave] = v;
-    __syncthreads();
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) t += red[w];
-    return t;
+__global__ __launch_bounds__(kBlock) void k_snia_draw(int64_t S, int64_t N, const double *__restrict__ a,
+                                                      const double *__restrict__ b,
+                                                      const double *__restrict__ log_s,
+                                                      const double *__restrict__ dth,
+                                                      const double *__restrict__ eps, T *__restrict__ z) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= N) return;
+    const double an = a[n], b0 = b[2 * n], b1 = b[2 * n + 1], sn = exp(log_s[n]);
+    for (int64_t s = 0; s < S; ++s) {
+        const double zeta = an + dth[2 * s] * b0 + dth[2 * s + 1] * b1 + sn * eps[s * N + n];
+        z[s * N + n] = (T)exp(zeta);
+    }
 }
 
 // One lane per supernova, the draws in a loop.  With G[s][n] the derivative of
@@ -603,8 +597,8 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // with respect to zeta[s][n] (grad_z[s][n] = d loglike_s / dz[s][n], from the fused
 // distance likelihood, enters through dz/dzeta = z):
 //   grad_a[n] = sum_s G,  grad_b[n] = sum_s G dtheta[s],  grad_log_s[n] = sum_s G s_n eps,
-// and per block the partial sums of F's terms and of sum_n G b[n] (the dtheta[s]
-// gradient), part[blk][1 + 2S].
+// and per wave the partial sums of F's terms and of sum_n G b[n] (the dtheta[s]
+// gradient), part[wave][1 + 2S] (wave sums only: no block barrier).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_snia_latent(int64_t S, int64_t N, const double *__restrict__ a,
                                                         const double *__restrict__ b,
@@ -615,16 +609,16 @@ __global__ __launch_bounds__(kBlock) void k_snia_latent(int64_t S, int64_t N, co
                                                         const T *__restrict__ gz, SniaConst k,
                                                         double *__restrict__ ga, double *__restrict__ gb,
                                                         double *__restrict__ gls, double *__restrict__ part) {
-    __shared__ double red[kBlock / 64];
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool act = n < N;
+    const bool lead = (threadIdx.x & 63) == 0;
     double an = 0.0, b0 = 0.0, b1 = 0.0, sn = 0.0, zh = 0.0;
     if (act) {
         an = a[n]; b0 = b[2 * n]; b1 = b[2 * n + 1]; sn = exp(log_s[n]); zh = zhat[n];
     }
     const double isz = 1.0 / k.sigma_z;
     double vsum = 0.0, sa = 0.0, sb0 = 0.0, sb1 = 0.0, sls = 0.0;
-    double *out = part + (int64_t)blockIdx.x * (1 + 2 * S);
+    double *out = part + ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * (1 + 2 * S);
     for (int64_t s = 0; s < S; ++s) {
         const double d0 = dth[2 * s], d1 = dth[2 * s + 1];
         double g = 0.0;
@@ -642,23 +636,35 @@ __global__ __launch_bounds__(kBlock) void k_snia_latent(int64_t S, int64_t N, co
             g = (dv + dl) * ez + 1.0;
             sa += g; sb0 += g * d0; sb1 += g * d1; sls += g * sn * e;
         }
-        const double p0 = block_sum(g * b0, red), p1 = block_sum(g * b1, red);
-        if (threadIdx.x == 0) { out[1 + 2 * s] = p0; out[2 + 2 * s] = p1; }
+        const double p0 = wave_sum(g * b0), p1 = wave_sum(g * b1);
+        if (lead) { out[1 + 2 * s] = p0; out[2 + 2 * s] = p1; }
     }
-    const double v = block_sum(vsum, red);
-    if (threadIdx.x == 0) out[0] = v;
+    const double v = wave_sum(vsum);
+    if (lead) out[0] = v;
     if (act) {
         ga[n] = sa; gb[2 * n] = sb0; gb[2 * n + 1] = sb1; gls[n] = sls;
     }
 }
 
-// out[q] = sum over blocks of part[blk][q], q < nq (one block per quantity).
-__global__ __launch_bounds__(kBlock) void k_sum_parts(const double *__restrict__ part, int64_t nblk, int64_t nq,
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads(); // the previous use of red is complete
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+    return t;
+}
+
+// out[q] = sum over rows of part[row][q], q < nq (one block per quantity).
+__global__ __launch_bounds__(kBlock) void k_sum_parts(const double *__restrict__ part, int64_t nrow, int64_t nq,
                                                       double *__restrict__ out) {
     __shared__ double red[kBlock / 64];
     const int64_t q = blockIdx.x;
     double v = 0.0;
-    for (int64_t t = threadIdx.x; t < nblk; t += kBlock) v += part[t * nq + q];
+    for (int64_t t = threadIdx.x; t < nrow; t += kBlock) v += part[t * nq + q];
     v = block_sum(v, red);
     if (threadIdx.x == 0) out[q] = v;
 }
@@ -987,13 +993,13 @@ int check_grid(int64_t n_cosmo, int64_t n_z) {
 }
 
 size_t snia_ws_bytes(int64_t n_draws, int64_t n_sn) {
-    const int64_t nblk = (n_sn + kBlock - 1) / kBlock;
-    return align256(sizeof(double) * (size_t)nblk * (size_t)(1 + 2 * n_draws));
+    const int64_t nwave = (n_sn + kBlock - 1) / kBlock * (kBlock / 64);
+    return align256(sizeof(double) * (size_t)nwave * (size_t)(1 + 2 * n_draws));
 }
 
 bool snia_sizes_ok(int64_t n_draws, int64_t n_sn) {
     if (n_draws < 0 || n_sn < 0) return false;
-    if (n_draws > 0 && n_sn > ((int64_t)0xFFFFFFFFll * kBlock) / n_draws) return false; // one lane per (draw, SN)
+    if (n_draws > 0 && n_sn > ((int64_t)0xFFFFFFFFll * kBlock) / n_draws) return false; // (draw, SN) pairs in 32-bit block counts
     if (2 * n_draws + 1 > 0x7FFFFFFFll) return false;
     return true;
 }
@@ -1250,8 +1256,7 @@ int snia_draw(cosmo_dtype dt, int64_t n_draws, int64_t n_sn, const double *a, co
     if (n_draws == 0 || n_sn == 0) return COSMO_OK;
     if (!a || !b || !log_s || !dtheta || !eps || !z) return COSMO_E_ARG;
     hipStream_t s = (hipStream_t)stream;
-    const int64_t tot = n_draws * n_sn;
-    const dim3 grid((unsigned)((tot + kBlock - 1) / kBlock));
+    const dim3 grid((unsigned)((n_sn + kBlock - 1) / kBlock));
     if (dt == COSMO_F32) hipLaunchKernelGGL(k_snia_draw<float>, grid, dim3(kBlock), 0, s, n_draws, n_sn, a, b, log_s, dtheta, eps, (float *)z);
     else hipLaunchKernelGGL(k_snia_draw<double>, grid, dim3(kBlock), 0, s, n_draws, n_sn, a, b, log_s, dtheta, eps, (double *)z);
     return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
@@ -1297,8 +1302,8 @@ int snia_latent_vjp(cosmo_dtype dt, int64_t n_draws, int64_t n_sn, const double 
         hipLaunchKernelGGL(k_snia_latent<double>, dim3((unsigned)nblk), dim3(kBlock), 0, s, n_draws, n_sn, a, b,
                            log_s, dtheta, eps, zhat, (const double *)grad_z, k, grad_a, grad_b, grad_log_s, part);
     if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
-    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)(1 + 2 * n_draws)), dim3(kBlock), 0, s, part, nblk,
-                       1 + 2 * n_draws, value_dtheta);
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)(1 + 2 * n_draws)), dim3(kBlock), 0, s, part,
+                       nblk * (kBlock / 64), 1 + 2 * n_draws, value_dtheta);
     return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
 }
 

@@ -170,7 +170,7 @@ def elbo(guide, zhat, muhat, n_samples, gen):
 def fit(zhat, muhat, steps=2000, n_samples=4, lr=0.02, dtype=torch.float32, seed=0, theta0=(0.3, 0.7)):
     """Maximise the ELBO with Adam; returns the guide and the ELBO trace."""
     guide = PMVNGuide(zhat, theta0=theta0, dtype=dtype)
-    opt = torch.optim.Adam(guide.parameters(), lr=lr)
+    opt = torch.optim.Adam(guide.parameters(), lr=lr, fused=True)  # one fused update kernel per step
     gen = torch.Generator(device=zhat.device)
     gen.manual_seed(seed)
     trace = []
