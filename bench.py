@@ -395,6 +395,35 @@ def main():
             others[name] = rec
         results["other_workloads"] = others
 
+        # the launch-bound small case (1 cosmology x 1000 redshifts): mu and its gradient
+        # per call, eager vs one HIP graph replay of the same call (set-up + adjoint +
+        # reductions captured with a caller-supplied workspace)
+        p1, z1 = workloads.config1()
+        gr = {"workload": "mu + gradient, 1 cosmology x 1000 redshifts, per call"}
+        for path in args.paths.split(","):
+            dt = torch.float32 if path == "f32" else torch.float64
+            pp = torch.tensor(p1, device=dev)
+            zz = torch.tensor(z1, dtype=dt, device=dev)
+            ww = torch.ones((1, z1.size), dtype=dt, device=dev)
+            w1 = torch.empty(cosmo.workspace_size(1, z1.size), dtype=torch.uint8, device=dev)
+
+            def one():
+                return cosmo.cosmo_distance_vjp("MU", pp, zz, ww, want_value=True, workspace=w1)
+            one()
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                one()
+            graph.replay()
+            e_ev, e_wall, _ = timed(one, 50, stream, torch)
+            g_ev, g_wall, _ = timed(graph.replay, 50, stream, torch)
+            gr[f"{path}_eager_us"] = float(np.median(e_ev)) * 1e3
+            gr[f"{path}_eager_wall_us"] = e_wall * 1e3
+            gr[f"{path}_graph_replay_us"] = float(np.median(g_ev)) * 1e3
+            gr[f"{path}_graph_replay_wall_us"] = g_wall * 1e3
+            del graph
+        results["graph_small"] = gr
+
     if args.copy_check:
         a = torch.empty(2 ** 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
