@@ -172,11 +172,13 @@ __device__ double cubic_resid(double q2, double q1, double q0, cx<double> x) {
 }
 
 __device__ cx<double> newton_polish(double q2, double q1, double q0, cx<double> x) {
+    double rx = cubic_resid(q2, q1, q0, x); // carried over: the accepted step's residual
     for (int it = 0; it < 4; ++it) {
         cx<double> d = cubic_d(q2, q1, x);
         if (norm2(d) == 0.0) break;
         cx<double> xn = x - cdiv(cubic_at(q2, q1, q0, x), d);
-        if (cubic_resid(q2, q1, q0, xn) < cubic_resid(q2, q1, q0, x)) x = xn; else break;
+        const double rn = cubic_resid(q2, q1, q0, xn);
+        if (rn < rx) { x = xn; rx = rn; } else break;
     }
     return x;
 }
