@@ -300,6 +300,14 @@ def main():
             ev, _, _ = timed(fbv, max(2, args.steps // 2), stream, torch)
             btw[f"{path}_DA_lens_value_and_grad_ms"] = float(np.median(ev))
             btw[f"{path}_DA_lens_value_and_grad_evals_per_s"] = evals / (np.median(ev) * 1e-3)
+
+            # the age t(z, inf) with its gradients (parameters by the Leibniz quadrature)
+            def fag():
+                return cosmo.cosmo_distance_between_vjp("T", p, za, zinf, wb, want_value=True, workspace=ws)
+            fag()
+            ev, _, _ = timed(fag, 2, stream, torch)
+            btw[f"{path}_T_age_value_and_grad_ms"] = float(np.median(ev))
+            btw[f"{path}_T_age_value_and_grad_evals_per_s"] = evals / (np.median(ev) * 1e-3)
             del a, b, za, zinf, wb
             torch.cuda.empty_cache()
         results["between"] = btw

@@ -131,16 +131,19 @@ int cosmo_distance_between(cosmo_kind kind, cosmo_dtype dt, const double *params
                            void *out, int32_t *info, void *workspace, size_t workspace_bytes,
                            void *stream);
 
-/* cosmo_distance_between_vjp -- adjoint of cosmo_distance_between for the distance
- * kinds COSMO_DC, COSMO_DM and COSMO_DA (other kinds: COSMO_E_KIND), through the
- * Carlson derivatives of eq. 3.7 (eq. 2.10) with both limits' square roots per
- * element and the root Jacobian (app. A); limits by the fundamental theorem of
- * calculus.  cot: [n_cosmo][n_z] of dtype.
+/* cosmo_distance_between_vjp -- adjoint of cosmo_distance_between for COSMO_DC,
+ * COSMO_DM, COSMO_DA and COSMO_T (other kinds: COSMO_E_KIND).  The distance kinds through
+ * the Carlson derivatives of eq. 3.7 (eq. 2.10) with both limits' square roots per
+ * element and the root Jacobian (app. A); T (value by eq. 3.8) with parameter
+ * derivatives by the Leibniz rule (eq. 2.4 differentiated under the integral), by
+ * Gauss-Legendre quadrature in s = (1+z)^(-1/2), which is finite for z2 = inf; limits
+ * by the fundamental theorem of calculus.  cot: [n_cosmo][n_z] of dtype.
  * out        : nullable; the observable from the same pass.
  * grad_params: [n_cosmo][4] FP64, sum over elements of cot * d out/d(H0, Om0, OL0,
- *              Or0); nullable.  NaN for a cosmology with an infinite upper limit and
- *              Or0 = 0 (d chi(z, inf)/d Or0 is -inf there), and for near-multiple-root
- *              cosmologies (whose gradient is the Leibniz quadrature) with z2 = inf.
+ *              Or0); nullable.  For the distance kinds NaN for a cosmology with an
+ *              infinite upper limit and Or0 = 0 (d chi(z, inf)/d Or0 is -inf there),
+ *              and for near-multiple-root cosmologies (whose gradient is the Leibniz
+ *              quadrature from z = 0) with z2 = inf.
  * grad_z1, grad_z2: dtype, nullable; [n_z] summed over cosmologies when
  *              z_cosmo_stride == 0, else [n_cosmo][n_z]; d/dz2 is 0 where z2 = inf.
  * workspace  : cosmo_workspace_size(n_cosmo, n_z) bytes (NULL allowed).            */

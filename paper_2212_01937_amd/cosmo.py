@@ -228,7 +228,7 @@ def cosmo_distance_between(kind, params, z1, z2, info=False, workspace=None):
 
 def cosmo_distance_between_vjp(kind, params, z1, z2, cot, want_params=True, want_z=True, info=False,
                                workspace=None, want_value=False):
-    """Adjoint of cosmo_distance_between for 'DC', 'DM', 'DA': (grad_params [n_cosmo, 4]
+    """Adjoint of cosmo_distance_between for 'DC', 'DM', 'DA', 'T': (grad_params [n_cosmo, 4]
     float64 or None, grad_z1, grad_z2 like the limits (summed over cosmologies when
     shared) or None); with want_value=True the observable first."""
     lib = load()
@@ -475,7 +475,7 @@ class _Between(torch.autograd.Function):
 
 
 def distance_between(kind, params, z1, z2):
-    """Differentiable observable between two redshifts ('DC', 'DM', 'DA'): autograd
+    """Differentiable observable between two redshifts ('DC', 'DM', 'DA', 'T'): autograd
     through cosmo_distance_between / cosmo_distance_between_vjp."""
     return _Between.apply(kind, params, z1, z2)
 

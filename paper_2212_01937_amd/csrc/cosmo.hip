@@ -316,7 +316,7 @@ __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_vjp(
     }
 }
 
-// Adjoint of the observables between two redshifts (D_C family): the structure of k_vjp
+// Adjoint of the observables between two redshifts (D_C family and T): the structure of k_vjp
 // (ZPT pairs per lane, per-wave partial sums of the same accumulator slots, finalised by
 // k_finalize_params) with two redshift gradients; for limits shared by all cosmologies
 // the z1- and z2-gradients are summed over the tile in thread-private LDS slots.
@@ -936,6 +936,7 @@ int launch_between_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T 
     case COSMO_DC: COSMO_BVJP(COSMO_DC); break;
     case COSMO_DM: COSMO_BVJP(COSMO_DM); break;
     case COSMO_DA: COSMO_BVJP(COSMO_DA); break;
+    case COSMO_T: COSMO_BVJP(COSMO_T); break;
     }
 #undef COSMO_BVJP
 #undef COSMO_BVJP_Z
@@ -1095,7 +1096,7 @@ int cosmo_distance_between_vjp(cosmo_kind kind, cosmo_dtype dt, const double *pa
                                const void *z1, const void *z2, int64_t n_z, int64_t z_cosmo_stride, const void *cot,
                                void *out, double *grad_params, void *grad_z1, void *grad_z2, int32_t *info,
                                void *workspace, size_t workspace_bytes, void *stream) {
-    if (!(kind == COSMO_DC || kind == COSMO_DM || kind == COSMO_DA)) return COSMO_E_KIND;
+    if (!(kind == COSMO_DC || kind == COSMO_DM || kind == COSMO_DA || kind == COSMO_T)) return COSMO_E_KIND;
     if (!valid_dtype(dt)) return COSMO_E_DTYPE;
     if (n_cosmo < 0 || n_z < 0 || z_cosmo_stride < 0) return COSMO_E_ARG;
     if (n_cosmo > 0 && !params) return COSMO_E_ARG;

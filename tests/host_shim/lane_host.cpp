@@ -67,3 +67,27 @@ extern "C" void host_between(const double *prm, int kind, int dt, const double *
         else out[i] = r.pair ? btw<double, true>(r, kind, z1[i], z2[i]) : btw<double, false>(r, kind, z1[i], z2[i]);
     }
 }
+
+// Leibniz-rule derivatives of t/(1/H0) between z1 and z2 (gl_time_between), d/d(Om, OL,
+// Or) per pair into out[3 n].  dt: 0 FP32, 1 FP64; z2 = inf allowed.
+template <typename T, bool PAIR> static void tgb(const CosmoRec &r, T z1, T z2, double *o) {
+    T q[3];
+    gl_time_between<T, PAIR>(lane_of<T>(r), z1, z2, z2 == Fp<T>::inf(), q);
+    o[0] = q[0]; o[1] = q[1]; o[2] = q[2];
+}
+extern "C" void host_time_between_grad(const double *prm, int dt, const double *z1, const double *z2, long n,
+                                       double *out) {
+    CosmoRec r;
+    setup_cosmo(prm, r);
+    for (long i = 0; i < n; ++i) {
+        double *o = out + 3 * i;
+        if (!r.valid) { o[0] = o[1] = o[2] = __builtin_nan(""); continue; }
+        if (dt == 0) {
+            if (r.pair) tgb<float, true>(r, (float)z1[i], (float)z2[i], o);
+            else tgb<float, false>(r, (float)z1[i], (float)z2[i], o);
+        } else {
+            if (r.pair) tgb<double, true>(r, z1[i], z2[i], o);
+            else tgb<double, false>(r, z1[i], z2[i], o);
+        }
+    }
+}

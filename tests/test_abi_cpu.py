@@ -118,7 +118,7 @@ def test_between_vjp_argument_errors(lib):
     E_ARG, E_KIND = -1, -2
     dummy = ctypes.c_void_p(0x1000)
     null = None
-    for k in (4, 2, 3, 5, 7):  # T, DL, MU, X, VC
+    for k in (2, 3, 5, 7):  # DL, MU, X, VC
         assert lib.cosmo_distance_between_vjp(k, 1, dummy, 1, dummy, dummy, 1, 0, dummy, null, dummy, null, null,
                                               null, null, 0, null) == E_KIND
     # a missing cotangent or limit

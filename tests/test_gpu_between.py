@@ -207,12 +207,12 @@ def ref_between_vjp(kind, params, z1, z2, w):
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
-@pytest.mark.parametrize("kind", ["DC", "DM", "DA"])
+@pytest.mark.parametrize("kind", ["DC", "DM", "DA", "T"])
 def test_between_vjp_workloads(kind, dt):
     """grad_params, grad_z1 and grad_z2 of cosmo_distance_between_vjp against the oracle's
     Leibniz-rule and fundamental-theorem derivatives, per-cosmology limits on the flat,
     non-flat and near-degenerate subsets (close, long and reversed limits; z2 = inf for
-    D_C and D_M on cosmologies with radiation)."""
+    D_C and D_M on cosmologies with radiation, for T on all)."""
     rng = np.random.default_rng(29)
     p1, _ = workloads.config1()
     p2, _ = workloads.config2(n_cosmo=16, n_z=8)
@@ -225,7 +225,8 @@ def test_between_vjp_workloads(kind, dt):
             z1[c], z2[c] = pairs(rng, 400, inf_share=0.0)
         # an infinite upper limit where the gradient is defined (radiation present, roots
         # well separated) and the observable is not D_A (zero there)
-        ok_inf = (params[:, 3] > 0) & (kind != "DA")
+        # (T: the age t(z, inf) and its gradient are finite for every cosmology)
+        ok_inf = np.ones(n_c, bool) if kind == "T" else (params[:, 3] > 0) & (kind != "DA")
         z2[ok_inf, :40] = np.inf
         w = rng.standard_normal((n_c, 400))
         p = torch.tensor(params, device=DEV)
@@ -273,8 +274,8 @@ def test_between_vjp_shared_limits_and_autograd(dt):
 
 
 def test_between_vjp_edge_cases():
-    """Empty inputs; invalid cosmologies give NaN rows; T and the other kinds are
-    rejected by the adjoint."""
+    """Empty inputs; invalid cosmologies give NaN rows; kinds other than D_C, D_M, D_A
+    and T are rejected by the adjoint."""
     good = [70.0, 0.3, 0.7 - 9e-5, 9e-5]
     bad = [70.0, 0.05, 1.3, 0.0]
     p = torch.tensor([good, bad], dtype=torch.float64, device=DEV)
@@ -290,7 +291,7 @@ def test_between_vjp_edge_cases():
     gp, g1, g2 = cosmo.cosmo_distance_between_vjp("DC", p[:0], z1, z2, torch.empty((0, 300), dtype=torch.float64,
                                                                                       device=DEV))
     assert gp.shape == (0, 4) and torch.equal(g1, torch.zeros_like(g1)) and torch.equal(g2, torch.zeros_like(g2))
-    for k in ("T", "X", "MU"):
+    for k in ("X", "MU", "DL", "VC"):
         with pytest.raises(cosmo.CosmoError):
             cosmo.cosmo_distance_between_vjp(k, p, z1, z2, w)
 
@@ -380,3 +381,24 @@ def test_between_vjp_full_size_sampled(dt):
     scale = sp * (n_z / zi.size)  # sampled estimate of sum_z |w dD_A/dtheta| per cosmology
     e = np.abs(gp.cpu().numpy() - gsum) / scale
     assert e.max() <= tol, (dt, e.max(0))
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_between_vjp_age_shared(dt):
+    """The age t(z, inf) with redshifts shared by all cosmologies (the benchmark's age
+    workload on 8 of its cosmologies): parameter gradients and the z-gradient summed
+    over cosmologies against the oracle; the z2-gradient is zero at infinity."""
+    params, _ = workloads.config5(n_cosmo=8, n_z=8)
+    za = workloads.age_redshifts(n=600)
+    p = torch.tensor(params, device=DEV)
+    a = torch.tensor(za, dtype=dt, device=DEV)
+    b = torch.full_like(a, float("inf"))
+    w = torch.tensor(np.random.default_rng(2).standard_normal((8, za.size)), dtype=dt, device=DEV)
+    val, gp, g1, g2 = cosmo.cosmo_distance_between_vjp("T", p, a, b, w, want_value=True)
+    ar, wr = a.double().cpu().numpy(), w.double().cpu().numpy()
+    rgp, sp, r1, _, s1, _ = ref_between_vjp("T", params, ar, np.full_like(ar, np.inf), wr)
+    tol = GTOL[dt]
+    assert np.max(np.abs(gp.cpu().numpy() - rgp) / sp) <= 5 * tol
+    assert np.max(np.abs(g1.double().cpu().numpy() - r1.sum(0)) / s1.sum(0)) <= tol
+    assert torch.equal(g2, torch.zeros_like(g2))
+    check("T", dt, params, ar, np.full_like(ar, np.inf), val, "age value from the adjoint")

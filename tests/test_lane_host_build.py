@@ -191,3 +191,35 @@ def test_between_formulas_match_oracle(libs, kind, model):
             e = np.abs(got - ref)[fin] / np.maximum(scale[fin], 1e-300)
             assert e.size and e.max() <= tol, (kind, model, dt, c, e.max(), a[fin][np.argmax(e)], b[fin][np.argmax(e)])
             assert np.all(got[a == b] == 0.0)
+
+
+def host_time_between_grad(lib, p, dt, z1, z2):
+    z1 = np.ascontiguousarray(z1, dtype=np.float64)
+    z2 = np.ascontiguousarray(z2, dtype=np.float64)
+    out = np.zeros((z1.size, 3))
+    lib.host_time_between_grad(np.ascontiguousarray(p, dtype=np.float64).ctypes.data_as(ctypes.c_void_p), dt,
+                               z1.ctypes.data_as(ctypes.c_void_p), z2.ctypes.data_as(ctypes.c_void_p),
+                               ctypes.c_long(z1.size), out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def test_time_between_gradient_matches_oracle(libs):
+    """gl_time_between (the Leibniz-rule derivatives of t(z1, z2) in s = (1+z)^(-1/2),
+    to z2 = inf) against the oracle's Leibniz derivatives from its own quadrature in
+    u = ln(1+z): FP64 <= 1e-10, FP32 <= 1e-4 of |d t/d theta| + 1e-3 |t| (the floor
+    where a derivative crosses zero), on the non-flat and near-degenerate sets."""
+    rng = np.random.default_rng(9)
+    params = _between_cases()
+    for c in range(params.shape[0]):
+        z1, z2 = between_pairs(rng, 40)
+        th = 977.7922216807892 / params[c, 0]
+        for dt, tol in ((1, 1e-10), (0, 1e-4)):
+            a = z1.astype(np.float32).astype(np.float64) if dt == 0 else z1
+            b = z2.astype(np.float32).astype(np.float64) if dt == 0 else z2
+            val, g = oracle.between("T", params[c:c + 1], a, b, grad=True)
+            ref = g[0, :, 1:4] / th
+            got = host_time_between_grad(libs["exact"], params[c], dt, a, b)
+            fin = np.isfinite(ref).all(1)
+            scale = np.abs(ref) + 1e-3 * np.abs(val[0] / th)[:, None]
+            e = np.abs(got - ref)[fin] / scale[fin]
+            assert e.size and e.max() <= tol, (dt, c, params[c], float(e.max()))
