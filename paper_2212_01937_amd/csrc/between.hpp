@@ -300,20 +300,25 @@ __device__ __forceinline__ void chi_grad_between(const LaneConst<T> &k, T z1, T 
 // R(a) = a^4 E^2(1/a) = Or + Om a + Ok a^2 + OL a^4 = beta (a - sigma) prod_j (1 - rho_j a),
 // and z2 = inf is s2 = 0.  With Ok eliminated, dR/d(Om, OL, Or) = (a - a^2, a^4 - a^2,
 // 1 - a^2), so d/dtheta = int -s^3 dR/dtheta R^(-3/2) ds.  Gauss-Legendre panels are laid
-// from the upper end of the s-range down, each no wider than 0.4 of the distance from
-// its upper end to the nearest zero of R(s^2) in the complex s-plane (s = +-i sqrt(-sigma),
+// from the upper end of the s-range down, each no wider than half the distance from its
+// upper end to the nearest zero of R(s^2) in the complex s-plane (s = +-i sqrt(-sigma),
 // s = +-rho_j^(-1/2)), so the zeros stay outside a Bernstein ellipse of parameter above
-// 5.8 (error below 1e-30 with 20 nodes, 1e-12 with 8).  Towards z2 = inf the panels
+// 3.7 (error below 1e-22 with 20 nodes, 1e-9 with 8).  Towards z2 = inf the panels
 // shrink geometrically onto the radiation zeros s = +-i sqrt(-sigma), which resolves the
 // change of the integrand from radiation to matter domination even for Or0 ~ 1e-20
-// (about 50 panels; at most 96).
-template <typename Q> __device__ __forceinline__ Q dist_to_sqrt(Q s, Q pre, Q pim) {
-    // distance from the real point s >= 0 to the nearer of +-sqrt(p), p = pre + i pim
+// (about 35 panels; at most 96).
+// The zero s = +-sqrt(p) of R(s^2) for a = p = 1/rho (principal root; the real s-range
+// is s >= 0, so the root with non-negative real part is the nearer one).
+template <typename Q> struct SZero {
+    Q re, im;
+};
+template <typename Q> __device__ __forceinline__ SZero<Q> sqrt_zero(Q pre, Q pim) {
     const Q m = Fp<Q>::sqrt(pre * pre + pim * pim);
-    const Q sr = Fp<Q>::sqrt(Q(0.5) * (m + pre));
-    const Q si = (pim >= Q(0) ? Q(1) : Q(-1)) * Fp<Q>::sqrt(Q(0.5) * Fp<Q>::abs(m - pre));
-    const Q dr = Fp<Q>::abs(s) - Fp<Q>::abs(sr);
-    return Fp<Q>::sqrt(dr * dr + si * si);
+    return SZero<Q>{Fp<Q>::sqrt(Q(0.5) * (m + pre)), Fp<Q>::sqrt(Q(0.5) * Fp<Q>::abs(m - pre))};
+}
+template <typename Q> __device__ __forceinline__ Q dist2_to(Q s, SZero<Q> z) {
+    const Q dr = s - z.re;
+    return dr * dr + z.im * z.im;
 }
 
 template <typename Q, bool PAIR>
@@ -335,37 +340,27 @@ __device__ void gl_time_between(const LaneConst<Q> &k, Q z1, Q z2, bool zinf, Q 
     }
     const Q omhi = zlo * Fp<Q>::rcp(xlo);
     const Q sgn = up ? Q(1) : Q(-1);
-    // zeros of R(s^2): a = sigma (s = +-i sqrt(-sigma)) and a = 1/rho_j
+    // zeros of R(s^2), once per lane: a = sigma (s = +-i sqrt(-sigma)) and a = 1/rho_j
     const Q sig2 = k.sigma == Q(0) ? Q(-1) : (-k.sigma > Q(1e-30) ? -k.sigma : Q(1e-30));
-    Q p0re, p1re, p1im, p2re;
-    p0re = Fp<Q>::rcp(k.r0);
-    if (PAIR) {
-        const Q m2 = k.r1re * k.r1re + k.r1im * k.r1im;
-        p1re = k.r1re * Fp<Q>::rcp(m2);
-        p1im = -k.r1im * Fp<Q>::rcp(m2);
-        p2re = Q(0);
-    } else {
-        p1re = Fp<Q>::rcp(k.r1re);
-        p1im = Q(0);
-        p2re = Fp<Q>::rcp(k.r2);
-    }
+    const SZero<Q> e0 = sqrt_zero<Q>(Fp<Q>::rcp(k.r0), Q(0));
     const Q q1m2 = k.r1re * k.r1re + k.r1im * k.r1im;
+    const SZero<Q> e1 = PAIR ? sqrt_zero<Q>(k.r1re * Fp<Q>::rcp(q1m2), -k.r1im * Fp<Q>::rcp(q1m2))
+                             : sqrt_zero<Q>(Fp<Q>::rcp(k.r1re), Q(0));
+    const SZero<Q> e2 = PAIR ? e1 : sqrt_zero<Q>(Fp<Q>::rcp(k.r2), Q(0));
     Q g0 = Q(0), g1 = Q(0), g2 = Q(0);
     Q done = Q(0); // offset from s_hi covered so far
     for (int p = 0; p < 96 && done < width; ++p) {
         const Q top = shi - done;
-        Q d = dist_to_sqrt<Q>(top, p0re, Q(0));
-        Q t = dist_to_sqrt<Q>(top, p1re, p1im);
-        d = t < d ? t : d;
-        if (!PAIR) {
-            t = dist_to_sqrt<Q>(top, p2re, Q(0));
-            d = t < d ? t : d;
-        }
+        Q d2 = dist2_to<Q>(top, e0);
+        Q t = dist2_to<Q>(top, e1);
+        d2 = t < d2 ? t : d2;
+        t = dist2_to<Q>(top, e2);
+        d2 = t < d2 ? t : d2;
         if (sig2 > Q(0)) {
-            t = Fp<Q>::sqrt(top * top + sig2);
-            d = t < d ? t : d;
+            t = top * top + sig2;
+            d2 = t < d2 ? t : d2;
         }
-        Q w = Q(0.4) * d;
+        Q w = Q(0.5) * Fp<Q>::sqrt(d2);
         if (w > width - done || p == 95) w = width - done;
         const Q half = Q(0.5) * w, cen = done + half;
         for (int i = 0; i < GlRule<Q>::n; ++i) {
