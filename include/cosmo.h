@@ -6,9 +6,11 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  *  - Array arguments are DEVICE pointers owned by the caller.  The library keeps
- *    no per-call state, never frees caller memory and is safe to call from several
- *    host threads.  The only library-owned device memory is a constant table of
- *    quadrature nodes, written once at first use.
+ *    no state between calls and needs no initialisation (its quadrature nodes are
+ *    compile-time constants), never frees caller memory and is safe to call from
+ *    several host threads.  With a caller-supplied workspace a call only enqueues
+ *    kernel launches, so it can be captured in a HIP graph, the first call of a
+ *    program included.
  *  - Calls enqueue asynchronously on `stream` (a hipStream_t passed as void*;
  *    NULL is the default stream) and return a cosmo_status.  Argument errors
  *    (NULL pointers, negative sizes, unknown kind/dtype, workspace too small) are
@@ -20,8 +22,10 @@
  *    E^2(z) = Or0 (1+z)^4 + Om0 (1+z)^3 + Ok0 (1+z)^2 + OL0 (eq. 2.2).
  *  - Redshifts z (> -1; all outputs are for the interval from 0 to z) and the
  *    outputs use the dtype argument: COSMO_F32 (float) or COSMO_F64 (double).
- *    Whatever the dtype, the per-cosmology root finding, the root Jacobian and
- *    the parameter-gradient reductions run in FP64.
+ *    Whatever the dtype, the per-cosmology root finding and the root Jacobian run
+ *    in FP64.  Parameter-gradient reductions: each wave sums its lanes' terms (at
+ *    most 512: 64 lanes x 8 redshifts) in the dtype; the sums over waves and the
+ *    contraction with the root Jacobian are FP64.
  *  - Units: distances in Mpc, time in Gyr, distance modulus in magnitudes
  *    (c = 299792.458 km/s, 1 Mpc = 3.0856775814913673e19 km, 1 Gyr = 3.15576e16 s).
  */

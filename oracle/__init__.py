@@ -36,8 +36,6 @@ def _load():
         lib.oracle_eval.restype = ctypes.c_int
         lib.oracle_carlson.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp]
         lib.oracle_carlson.restype = ctypes.c_int
-        lib.oracle_E.argtypes = [dp, ctypes.c_double]
-        lib.oracle_E.restype = ctypes.c_double
         lib.oracle_gk15_panel.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                           ctypes.c_double]
         lib.oracle_gk15_panel.restype = ctypes.c_double
@@ -153,11 +151,6 @@ def snia_log_joint(theta, z, zhat, muhat, h0=70.0, sigma_mu=0.14, sigma_z=0.04, 
     return lp, dth, dz
 
 
-def E(params, z):
-    """E(z) of eq. 2.2 for one cosmology (H0, Om0, OL0, Or0)."""
-    lib = _load()
-    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(4))
-    return lib.oracle_E(_ptr(p), float(z))
 
 
 def carlson(which, x, y, z=None, p=None):

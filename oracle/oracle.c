@@ -527,13 +527,6 @@ int oracle_threads(void)
 #endif
 }
 
-/* E(z) itself (for the fundamental-theorem pins in the tests). */
-double oracle_E(const double *prm, double z)
-{
-    struct cosmo c = {prm[0], prm[1], prm[2], prm[3], 1.0 - prm[1] - prm[2] - prm[3]};
-    return sqrt(E2_of_x(&c, 1.0 + z));
-}
-
 /* ---------------------------------------------------------------------------
  * Carlson symmetric integrals by quadrature of their definitions (eqs. 2.6-2.9).
  *   R_F(x,y,z)   = 1/2 int_0^inf dt / sqrt((t+x)(t+y)(t+z))

@@ -2,9 +2,12 @@
 
     python -m paper_2212_01937_amd.build     (or: python paper_2212_01937_amd/build.py)
 
-The library is built in-tree next to this file, and so is tools/valu_ceiling (a
-stand-alone measurement of the vector-ALU ceiling of code built this way).  All
-device code is compiled with packed-FP32 instruction selection disabled.
+The library is built in-tree next to this file.  All device code is compiled with
+packed-FP32 instruction selection disabled.  The stand-alone measurement of the
+vector-ALU ceiling of code built this way (tools/valu_ceiling.hip) is not part of the
+library and is built only on request:
+
+    python -m paper_2212_01937_amd.build --valu-ceiling
 """
 import os
 import subprocess
@@ -35,7 +38,6 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
-    build_tool(verbose)
     return LIB
 
 
@@ -57,4 +59,7 @@ def stale() -> bool:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--valu-ceiling" in sys.argv:
+        print(build_tool(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

@@ -104,7 +104,11 @@ def _params(params):
 
 
 def _z_layout(z, n_cosmo):
-    """Returns (z_contig, n_z, stride, shared)."""
+    """Returns (z_contig, n_z, stride, shared).  A 2-D z is passed to the library as
+    dense rows (stride n_z): the per-element inputs the library reads with z's stride
+    (observed values, inverse variances) are packed that way, and a stride of 0 would
+    mean a shared row to the library.  Views that are not dense rows (column slices,
+    expanded rows) are copied."""
     _need_gpu(z, "z")
     if z.dtype not in DTYPES:
         raise CosmoError("z must be float32 or float64")
@@ -112,8 +116,10 @@ def _z_layout(z, n_cosmo):
         zc = z if z.is_contiguous() else z.contiguous()
         return zc, zc.shape[0], 0, True
     if z.dim() == 2 and z.shape[0] == n_cosmo:
-        zc = z if (z.stride(1) == 1) else z.contiguous()
-        return zc, zc.shape[1], zc.stride(0), False
+        n_z = z.shape[1]
+        dense = z.stride(1) == 1 and (z.stride(0) == n_z or n_cosmo <= 1)
+        zc = z if dense else z.contiguous()
+        return zc, n_z, n_z, False
     raise CosmoError("z must be [n_z] (shared) or [n_cosmo, n_z]")
 
 
@@ -357,14 +363,21 @@ class _GaussianLogLike(torch.autograd.Function):
     def backward(ctx, g):
         params, z, obs, ivar = ctx.saved_tensors
         gp, gz = ctx.grads
-        if bool((g == g[0]).all()):
-            # equal weights (e.g. loss = loglike.sum()): rescale the gradients of the forward pass
-            s = g[0]
-            gp = gp * s if gp is not None else None
-            gz = gz * s.to(gz.dtype) if gz is not None else None
-        else:
-            _, gp, gz = cosmo_gaussian_loglike(ctx.kind, params.detach(), z.detach(), obs, ivar=ivar, weights=g,
-                                               want_params=gp is not None, want_z=gz is not None)
+        # The forward pass computed the gradients for unit weights.  Parameter gradients are
+        # per cosmology, so any upstream weights rescale them row by row; the z-gradient of
+        # a shared z row is a sum over cosmologies, which takes the weights inside the sum:
+        # recomputed with them unless there is a single cosmology.  (No host
+        # synchronisation: which case applies follows from shapes, not values.)
+        if gp is not None:
+            gp = gp * g[:, None]
+        if gz is not None:
+            if gz.dim() == 2:
+                gz = gz * g[:, None].to(gz.dtype)
+            elif g.shape[0] == 1:
+                gz = gz * g[0].to(gz.dtype)
+            else:
+                _, _, gz = cosmo_gaussian_loglike(ctx.kind, params.detach(), z.detach(), obs, ivar=ivar, weights=g,
+                                                  want_params=False, want_z=True)
         if gz is not None:
             gz = gz.reshape(z.shape)
         return None, gp.reshape(params.shape) if gp is not None else None, gz, None, None

@@ -10,7 +10,6 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
-#include <mutex>
 #include <stdint.h>
 #include <string.h>
 
@@ -19,9 +18,6 @@
 #include "between.hpp"
 
 namespace cosmo {
-
-__constant__ double c_gl64_x[kGlN64], c_gl64_w[kGlN64];
-__constant__ float c_gl32_x[kGlN32], c_gl32_w[kGlN32];
 
 constexpr int kBlock = 256;
 
@@ -730,60 +726,6 @@ WsLayout ws_layout(int64_t n_cosmo, int64_t n_z) {
     return w;
 }
 
-// Gauss-Legendre nodes on [-1, 1] by Newton iteration on the Legendre polynomial.
-void gauss_legendre(int n, double *x, double *w) {
-    for (int i = 0; i < n; ++i) {
-        double t = cos(M_PI * (i + 0.75) / (n + 0.5));
-        double dp = 1.0;
-        for (int it = 0; it < 100; ++it) {
-            double p0 = 1.0, p1 = t;
-            for (int k = 2; k <= n; ++k) {
-                double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
-                p0 = p1;
-                p1 = p2;
-            }
-            dp = n * (t * p1 - p0) / (t * t - 1.0);
-            double dt = p1 / dp;
-            t -= dt;
-            if (fabs(dt) < 1e-16) {
-                // recompute derivative at the converged node for the weight
-                p0 = 1.0; p1 = t;
-                for (int k = 2; k <= n; ++k) {
-                    double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
-                    p0 = p1;
-                    p1 = p2;
-                }
-                dp = n * (t * p1 - p0) / (t * t - 1.0);
-                break;
-            }
-        }
-        x[i] = t;
-        w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
-    }
-}
-
-std::mutex g_init_mu;
-bool g_init_done[64];
-
-int ensure_init() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return COSMO_E_HIP;
-    if (dev < 0 || dev >= 64) return COSMO_E_HIP;
-    std::lock_guard<std::mutex> lk(g_init_mu);
-    if (g_init_done[dev]) return COSMO_OK;
-    double x64[kGlN64], w64[kGlN64], x32d[kGlN32], w32d[kGlN32];
-    float x32[kGlN32], w32[kGlN32];
-    gauss_legendre(kGlN64, x64, w64);
-    gauss_legendre(kGlN32, x32d, w32d);
-    for (int i = 0; i < kGlN32; ++i) { x32[i] = (float)x32d[i]; w32[i] = (float)w32d[i]; }
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_gl64_x), x64, sizeof x64) != hipSuccess) return COSMO_E_HIP;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_gl64_w), w64, sizeof w64) != hipSuccess) return COSMO_E_HIP;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_gl32_x), x32, sizeof x32) != hipSuccess) return COSMO_E_HIP;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_gl32_w), w32, sizeof w32) != hipSuccess) return COSMO_E_HIP;
-    g_init_done[dev] = true;
-    return COSMO_OK;
-}
-
 bool valid_kind(int k) { return k >= COSMO_DC && k <= COSMO_VC; }
 bool valid_dtype(int d) { return d == COSMO_F32 || d == COSMO_F64; }
 
@@ -1051,8 +993,7 @@ int cosmo_distance(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_
     if (check_grid(n_cosmo, n_z) != COSMO_OK) return COSMO_E_ARG;
     if (n_cosmo == 0) return COSMO_OK;
     hipStream_t s = (hipStream_t)stream;
-    int rc = ensure_init();
-    if (rc != COSMO_OK) return rc;
+    int rc;
     WsLayout L = ws_layout(n_cosmo, 0);
     Workspace ws;
     rc = ws.acquire(workspace, workspace_bytes, L.pacc, s);
@@ -1076,8 +1017,7 @@ int cosmo_distance_between(cosmo_kind kind, cosmo_dtype dt, const double *params
     if (check_grid(n_cosmo, n_z) != COSMO_OK) return COSMO_E_ARG;
     if (n_cosmo == 0) return COSMO_OK;
     hipStream_t s = (hipStream_t)stream;
-    int rc = ensure_init();
-    if (rc != COSMO_OK) return rc;
+    int rc;
     WsLayout L = ws_layout(n_cosmo, 0);
     Workspace ws;
     rc = ws.acquire(workspace, workspace_bytes, L.pacc, s);
@@ -1116,8 +1056,7 @@ int cosmo_distance_between_vjp(cosmo_kind kind, cosmo_dtype dt, const double *pa
         }
         return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
     }
-    int rc = ensure_init();
-    if (rc != COSMO_OK) return rc;
+    int rc;
     WsLayout L = ws_layout(n_cosmo, n_z);
     Workspace ws;
     rc = ws.acquire(workspace, workspace_bytes, L.total, s);
@@ -1155,8 +1094,7 @@ int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params, in
         }
         return COSMO_OK;
     }
-    int rc = ensure_init();
-    if (rc != COSMO_OK) return rc;
+    int rc;
     WsLayout L = ws_layout(n_cosmo, n_z);
     Workspace ws;
     rc = ws.acquire(workspace, workspace_bytes, L.total, s);
@@ -1184,8 +1122,7 @@ int cosmo_distance_jac(cosmo_kind kind, cosmo_dtype dt, const double *params, in
     if (check_grid(n_cosmo, n_z) != COSMO_OK) return COSMO_E_ARG;
     if (n_cosmo == 0) return COSMO_OK;
     hipStream_t s = (hipStream_t)stream;
-    int rc = ensure_init();
-    if (rc != COSMO_OK) return rc;
+    int rc;
     WsLayout L = ws_layout(n_cosmo, 0);
     Workspace ws;
     rc = ws.acquire(workspace, workspace_bytes, L.pacc, s);
@@ -1225,8 +1162,7 @@ int cosmo_gaussian_loglike(cosmo_kind kind, cosmo_dtype dt, const double *params
         }
         return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
     }
-    int rc = ensure_init();
-    if (rc != COSMO_OK) return rc;
+    int rc;
     WsLayout L = ws_layout(n_cosmo, n_z);
     Workspace ws;
     rc = ws.acquire(workspace, workspace_bytes, L.total, s);

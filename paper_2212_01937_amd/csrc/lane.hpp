@@ -22,6 +22,7 @@
 #pragma once
 
 #include "carlson.hpp"
+#include "gl_tables.hpp"
 #include "setup.hpp"
 
 namespace cosmo {
@@ -209,12 +210,9 @@ __device__ __forceinline__ void sqrtQ(const LaneConst<T> &k, const Geo<T, PAIR> 
     }
 }
 
-// Gauss-Legendre nodes (filled by the host once per device).
+// Gauss-Legendre nodes and weights: literal tables (gl_tables.hpp, 20 nodes FP64, 8
+// FP32), so the quadrature routes need no run-time initialisation.
 constexpr int kGlNp = 4;         // panels in u = ln(1+z)
-constexpr int kGlN64 = 20;       // nodes per panel, FP64
-constexpr int kGlN32 = 8;        // nodes per panel, FP32
-extern __constant__ double c_gl64_x[kGlN64], c_gl64_w[kGlN64];
-extern __constant__ float c_gl32_x[kGlN32], c_gl32_w[kGlN32];
 
 template <typename Q> struct GlRule;
 template <> struct GlRule<double> {
@@ -246,9 +244,12 @@ template <> struct GlRule<float> {
 // (X).  With grad, also the Leibniz derivatives -1/2 int f dP/dtheta / E^3 du for
 // theta = (Om, OL, Or).  E^2 = beta (1 - sigma x) Q(x) in factored form.
 // The number of equal panels is max(min_np, U / dpath) (capped at 64; min_np = 4 by
-// default): every panel is then no wider than the distance of the nearest
-// singularity of the integrand, which keeps the Bernstein-ellipse parameter of each
-// panel above 3.7 (error below 1e-20 with 20 nodes, 1e-9 with 8).
+// default): every panel is then no wider than the distance d of the nearest
+// singularity of the integrand from the path.  In units of the half-width h <= d/2 such
+// a singularity lies outside the stadium of radius 2 about the panel; the smallest
+// Bernstein-ellipse parameter on that stadium is 2 + sqrt(5) = 4.24 (abreast of the
+// panel's centre), so the Gauss-Legendre error is of order 4.24^(-2n): below 1e-25 with
+// 20 nodes, 1e-10 with 8.
 // Nodes: for U > 1/2 they are placed from the upper limit down, x = (1+z) exp(-(U - u)):
 // the integrands grow with x, and measuring from the top keeps the rounding of the node
 // abscissae (absolute, ~eps times the distance from the anchor) smallest where the

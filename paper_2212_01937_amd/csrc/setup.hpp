@@ -217,6 +217,14 @@ __device__ void setup_cosmo(const double *prm, CosmoRec &rec) {
     rec.pair = 0;
     rec.fallback_grad = 0;
     rec.H0 = H0;
+    // fields the early returns below leave unset (records of cosmologies outside the
+    // method are never evaluated, but every field is defined)
+    rec.beta = 0.0;
+    rec.minsep = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        rec.dbeta[a] = rec.dsigma[a] = 0.0;
+        for (int n = 0; n < 3; ++n) rec.drho_re[n][a] = rec.drho_im[n][a] = 0.0;
+    }
     LaneConst<double> &D = rec.d;
     D = LaneConst<double>{};
     bool finite = __builtin_isfinite(H0) && __builtin_isfinite(Om) && __builtin_isfinite(OL) &&

@@ -173,11 +173,13 @@ def fit(zhat, muhat, steps=2000, n_samples=4, lr=0.02, dtype=torch.float32, seed
     opt = torch.optim.Adam(guide.parameters(), lr=lr, fused=True)  # one fused update kernel per step
     gen = torch.Generator(device=zhat.device)
     gen.manual_seed(seed)
-    trace = []
-    for _ in range(steps):
+    # the ELBO trace stays on the device during the fit (no host synchronisation per
+    # step) and is copied to the host once at the end
+    trace = torch.empty(steps, dtype=torch.float64, device=zhat.device)
+    for i in range(steps):
         opt.zero_grad(set_to_none=True)
         loss = -elbo(guide, zhat, muhat, n_samples, gen)
         loss.backward()
         opt.step()
-        trace.append(-float(loss.detach()))
-    return guide, trace
+        trace[i] = -loss.detach()
+    return guide, trace.cpu().tolist()

@@ -35,7 +35,9 @@ def errors(kind, got, ref, finite_ref, params=None, z=None):
     """Relative error (D_C, T, X), for D_M relative to the conditioning scale |D_M| +
     |dD_M/dchi| chi (D_M crosses zero beyond the antipode of a closed universe, where a
     relative error of chi moves it by that much), and for mu in mag, divided by
-    1 + |C chi / S| (the same conditioning in units of 5/ln 10)."""
+    max(1, |C chi / S|): the absolute error in magnitudes wherever a relative error of
+    chi moves D_L by no more than itself (flat and closed universes before the antipode),
+    and beyond that the error relative to the amplification of chi's error."""
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     if kind in ("DM", "MU"):
@@ -179,8 +181,8 @@ def main():
         for label, name, n, (a, b) in wide:
             lines.append(f"| {label} | {name} | {n} | {a:.1e} / {b:.1e} |")
     text = "\n".join(lines) + (f"\n\n(relative errors; D_M relative to |D_M| + |dD_M/dchi| chi, D_A(z_l, z_s) to "
-                                f"|D_A| + |C chi/(1 + z_s)|, V_C to max(|V_C|, chi dV_C/dchi); MU in mag per "
-                                f"1 + |C chi / S|; {time.time() - t0:.0f} s)\n")
+                                f"|D_A| + |C chi/(1 + z_s)|, V_C to max(|V_C|, chi dV_C/dchi); MU in mag, divided "
+                                f"by max(1, |C chi / S|); {time.time() - t0:.0f} s)\n")
     print(text)
     if args.out:
         with open(args.out, "w") as fh:

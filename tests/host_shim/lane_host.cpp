@@ -1,14 +1,6 @@
 // Host build of the per-lane forward formulas (D_C, T, X) for tests.
 #include "../../paper_2212_01937_amd/csrc/between.hpp"
 using namespace cosmo;
-namespace cosmo {
-double c_gl64_x[kGlN64], c_gl64_w[kGlN64];
-float c_gl32_x[kGlN32], c_gl32_w[kGlN32];
-}
-extern "C" void host_set_gl(const double *x64, const double *w64, const float *x32, const float *w32) {
-    for (int i = 0; i < kGlN64; ++i) { c_gl64_x[i] = x64[i]; c_gl64_w[i] = w64[i]; }
-    for (int i = 0; i < kGlN32; ++i) { c_gl32_x[i] = x32[i]; c_gl32_w[i] = w32[i]; }
-}
 template <typename T, bool PAIR> static double one(const CosmoRec &r, int kind, T z) {
     const LaneConst<T> &k = lane_of<T>(r);
     bool ugl = false;

@@ -5,20 +5,31 @@ For a cotangent w, the reference vector-Jacobian products are
     grad_params[c] = sum_z w[c,z] d out[c,z] / d(H0, Om0, OL0, Or0)
     grad_z[z]      = sum_c w[c,z] d out[c,z] / dz        (shared z; per-cosmology otherwise)
 and errors are measured against the natural scale of each sum, sum |w d out/d theta|.
-Bounds: FP64 path 1e-10; FP32 path 1e-4 (the Or0 component, whose chain through the
-radiation root is the worst conditioned, 5e-4).
+Bounds: FP64 path 1e-10; FP32 path 1e-4, except the Or0 component on the FP32 path,
+5e-4: its chain through the radiation root cancels by about 0.35/Or0 (4e3 at the
+workloads' Or0 = 9e-5), which multiplies the FP32 rounding of the lane partials.
+Where the cotangent is formed from the GPU's own value (a likelihood residual), the
+bound also allows the error that value's rounding puts into the cotangent, measured:
+max|d mu| / sigma^2 times sum |d out/d theta|.
 """
 import numpy as np
 import pytest
 import torch
 
 import oracle
+from margins import note
 from paper_2212_01937_amd import cosmo, workloads
 
 pytestmark = pytest.mark.gpu
 
 KINDS = ["DC", "DM", "DL", "MU", "T", "X", "DA", "VC"]
 TOL = {torch.float64: 1e-10, torch.float32: 1e-4}
+
+
+def ptol(dt):
+    """Per-component bounds of grad_params (H0, Om0, OL0, Or0)."""
+    t = TOL[dt]
+    return np.array([t, t, t, 5 * t if dt == torch.float32 else t])
 
 
 def ref_vjp(kind, params, z, w, shared):
@@ -50,9 +61,10 @@ def compare(label, dt, gp, gz, ref):
     ep = np.abs(gp - rgp) / np.maximum(sp, 1e-300)
     ez = np.abs(gz - rgz) / np.maximum(sz, 1e-300)
     tol = TOL[dt]
-    ptol = np.array([tol, tol, tol, 5 * tol if dt == torch.float32 else tol])
     assert np.all(np.isfinite(gp)) and np.all(np.isfinite(gz)), label
-    assert np.all(ep.max(0) <= ptol), f"{label} {dt} grad_params err {ep.max(0)}"
+    note(f"vjp {label} {dt} grad_params", (ep.max(0) / ptol(dt)).max(), 1.0)
+    note(f"vjp {label} {dt} grad_z", ez.max(), tol)
+    assert np.all(ep.max(0) <= ptol(dt)), f"{label} {dt} grad_params err {ep.max(0)}"
     assert ez.max() <= tol, f"{label} {dt} grad_z err {ez.max():.3e}"
 
 
@@ -95,7 +107,8 @@ def test_vjp_config4_families(dev, dt):
         for f in "ABCD":
             m = fam == f
             assert np.all(np.isfinite(gp[m])), (kind, f)
-            assert ep[m].max() <= 5 * TOL[dt], f"config4-{f} {kind} {dt} {ep[m].max(0)}"
+            note(f"vjp config4-{f} {kind} {dt}", (ep[m].max(0) / ptol(dt)).max(), 1.0)
+            assert np.all(ep[m].max(0) <= ptol(dt)), f"config4-{f} {kind} {dt} {ep[m].max(0)}"
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
@@ -112,18 +125,24 @@ def test_autograd_likelihood_config3_small(dev, dt):
     loss = (-(mo[None, :] - mu) ** 2 / (2 * 0.1 ** 2)).sum()
     loss.backward()
     zr = zt.detach().double().cpu().numpy()
+    mo_r = mo.double().cpu().numpy()  # the observed values as the GPU sees them
     ref_mu, g = oracle.distance("MU", th, zr, grad=True)
-    r = (mu_obs[None, :] - ref_mu) / 0.1 ** 2
-    ref_loss = (-(mu_obs[None, :] - ref_mu) ** 2 / (2 * 0.1 ** 2)).sum()
+    r = (mo_r[None, :] - ref_mu) / 0.1 ** 2
+    ref_loss = (-(mo_r[None, :] - ref_mu) ** 2 / (2 * 0.1 ** 2)).sum()
     assert abs(loss.item() - ref_loss) <= (1e-9 if dt == torch.float64 else 1e-3) * abs(ref_loss)
+    dr = np.max(np.abs(mu.detach().double().cpu().numpy() - ref_mu)) / 0.1 ** 2  # cotangent error
     rgp = np.einsum("cz,czk->ck", r, g[..., :4])
     sp = np.einsum("cz,czk->ck", np.abs(r), np.abs(g[..., :4]))
-    ep = np.abs(p.grad.cpu().numpy() - rgp) / sp
-    assert ep[:, :3].max() <= TOL[dt] * 10, ep
+    sp_r = dr * np.abs(g[..., :4]).sum(1)
+    ep = np.abs(p.grad.cpu().numpy() - rgp) / (TOL[dt] * sp + sp_r)
+    note(f"autograd-likelihood {dt} grad_params", ep[:, :3].max(), 1.0)
+    assert ep[:, :3].max() <= 1.0, ep
     rgz = (r * g[..., 4]).sum(0)
     sz = np.abs(r * g[..., 4]).sum(0)
-    ez = np.abs(zt.grad.double().cpu().numpy() - rgz) / sz
-    assert ez.max() <= TOL[dt] * 10, ez.max()
+    sz_r = dr * np.abs(g[..., 4]).sum(0)
+    ez = np.abs(zt.grad.double().cpu().numpy() - rgz) / (TOL[dt] * sz + sz_r)
+    note(f"autograd-likelihood {dt} grad_z", ez.max(), 1.0)
+    assert ez.max() <= 1.0, ez.max()
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
@@ -148,19 +167,22 @@ def test_vjp_config5_full_size_sampled(dev, dt):
     wr = w[torch.tensor(ci, device=dev), torch.tensor(zi, device=dev)].double().cpu().numpy()
     rgp = np.zeros((n_c, 4))
     sp = np.zeros((n_c, 4))
-    rgz = {}
+    rgz, sgz = {}, {}
     for c, i, ww in zip(ci, zi, wr):
         _, g = oracle.distance("MU", params[c:c + 1], np.array([zr[i]]), grad=True)
         rgp[c] += ww * g[0, 0, :4]
         sp[c] += np.abs(ww * g[0, 0, :4])
         rgz[i] = rgz.get(i, 0.0) + ww * g[0, 0, 4]
+        sgz[i] = sgz.get(i, 0.0) + abs(ww * g[0, 0, 4])
     touched = np.unique(ci)
     ep = np.abs(gp[touched] - rgp[touched]) / sp[touched]
-    assert ep[:, :3].max() <= TOL[dt], ep.max(0)
+    note(f"vjp config5-full {dt} grad_params", (ep.max(0) / ptol(dt)).max(), 1.0)
+    assert np.all(ep.max(0) <= ptol(dt)), ep.max(0)
     untouched = np.setdiff1d(np.arange(n_c), touched)
     assert np.all(gp[untouched] == 0.0)
-    for i, v in rgz.items():
-        assert abs(gz[i] - v) <= TOL[dt] * abs(v) * 10, (i, gz[i], v)
+    ez = max(abs(gz[i] - v) / sgz[i] for i, v in rgz.items())
+    note(f"vjp config5-full {dt} grad_z", ez, TOL[dt])
+    assert ez <= TOL[dt], ez
     mask = np.ones(n_z, dtype=bool)
     mask[list(rgz.keys())] = False
     assert np.all(gz[mask] == 0.0)
@@ -218,13 +240,33 @@ def test_config3_full_size_likelihood(dev):
         zr = zt.detach().double().cpu().numpy()
         got = mu.detach()[torch.tensor(ci, device=dev), torch.tensor(zi, device=dev)].double().cpu().numpy()
         ref = np.array([oracle.distance("MU", th[c:c + 1], np.array([zr[i]]))[0, 0] for c, i in zip(ci, zi)])
-        assert np.max(np.abs(got - ref)) < (1e-11 if dt == torch.float64 else 1e-4)
+        assert np.max(np.abs(got - ref)) < (2.2e-12 if dt == torch.float64 else 1e-4)
         res[dt] = (loss.item(), p.grad.cpu().numpy(), zt.grad.double().cpu().numpy())
     l64, g64, z64 = res[torch.float64]
     l32, g32, z32 = res[torch.float32]
+    # The FP64 GPU path meets the oracle to 1e-10 element by element (tests above), so it
+    # stands in for the oracle at this size.  The FP32 loss gradient is held to the FP32
+    # bound relative to its natural scales sum |r d mu/d theta|, sum_c |r d mu/dz| (r =
+    # (obs - mu)/sigma^2), plus the error the FP32 forward puts into r, measured
+    # (max |mu32 - mu64| / sigma^2 times sum |d mu/d theta|), from the FP64 Jacobian.
+    p64 = torch.tensor(th, device=dev)
+    z64t = torch.tensor(zs, dtype=torch.float64, device=dev)
+    mu64, jac = cosmo.cosmo_distance_jac("MU", p64, z64t)
+    mu32 = cosmo.cosmo_distance("MU", p64, torch.tensor(zs, dtype=torch.float32, device=dev)).double()
+    dr = ((mu32 - mu64).abs().max() / 0.1 ** 2).item()
+    r = (torch.tensor(mo, device=dev)[None, :] - mu64) / 0.1 ** 2
+    sp = torch.stack([(r.abs() * jac[q].abs()).sum(1) for q in range(3)], 1).cpu().numpy()
+    sp_r = dr * torch.stack([jac[q].abs().sum(1) for q in range(3)], 1).cpu().numpy()
+    sz = (r.abs() * jac[4].abs()).sum(0).cpu().numpy()
+    sz_r = dr * jac[4].abs().sum(0).cpu().numpy()
+    del jac, r
+    ep = np.abs(g32[:, :3] - g64[:, :3]) / (TOL[torch.float32] * sp + sp_r)
+    ez = np.abs(z32 - z64) / (TOL[torch.float32] * sz + sz_r)
+    note("likelihood config3-full FP32 grad_params", ep.max(), 1.0)
+    note("likelihood config3-full FP32 grad_z", ez.max(), 1.0)
+    assert ep.max() <= 1.0, ep.max(0)
+    assert ez.max() <= 1.0, ez.max()
     assert abs(l32 - l64) <= 5e-4 * abs(l64)
-    assert np.max(np.abs(g32[:, :3] - g64[:, :3]) / np.maximum(np.abs(g64[:, :3]), 1e-3 * np.abs(g64[:, :3]).max())) < 1e-2
-    assert np.max(np.abs(z32 - z64)) <= 1e-3 * np.max(np.abs(z64))
 
 
 def jac_check(kind, dt, params, z, shared, label, dev):
@@ -281,8 +323,9 @@ def jac_check(kind, dt, params, z, shared, label, dev):
                 + (v4 * chi ** 5 / 15 * (1 + np.abs(ok * chi ** 2)))[..., None])
         scale[..., 1:4] = np.maximum(scale[..., 1:4], np.where(undef[..., None], 0.0, curv))
     e = np.where(undef[..., None], 0.0, np.abs(jac - g) / np.maximum(scale, 1e-300))
-    tol = np.array([TOL[dt]] * 3 + [5 * TOL[dt] if dt == torch.float32 else TOL[dt], TOL[dt]])
+    tol = np.concatenate([ptol(dt), [TOL[dt]]])
     worst = e.reshape(-1, 5).max(0)
+    note(f"jac {label} {kind} {dt}", (worst / tol).max(), 1.0)
     assert np.all(worst <= tol), f"{label} {kind} {dt} jac err per component {worst}"
     return jac
 
@@ -350,14 +393,20 @@ def test_gaussian_loglike_config3_small(dev, dt):
     ref_ll = -0.5 * (r * (obs[None, :] - ref_mu)).sum(1)
     tol_ll = 1e-10 if dt == torch.float64 else 1e-5
     assert np.all(np.abs(ll.cpu().numpy() - ref_ll) <= tol_ll * np.abs(ref_ll)), (ll, ref_ll)
+    mu_gpu = cosmo.cosmo_distance("MU", p, zt).double().cpu().numpy()
+    dr = np.max(np.abs(mu_gpu - ref_mu)) / 0.1 ** 2  # error of the lanes' residuals
     rgp = np.einsum("cz,czk->ck", r, g[..., :4])
     sp = np.einsum("cz,czk->ck", np.abs(r), np.abs(g[..., :4]))
-    ep = np.abs(gp.cpu().numpy() - rgp) / sp
-    assert ep[:, :3].max() <= TOL[dt] * 10, ep
+    sp_r = dr * np.abs(g[..., :4]).sum(1)
+    ep = np.abs(gp.cpu().numpy() - rgp) / (TOL[dt] * sp + sp_r)
+    note(f"loglike config3-small {dt} grad_params", ep[:, :3].max(), 1.0)
+    assert ep[:, :3].max() <= 1.0, ep
     rgz = (r * g[..., 4]).sum(0)
     sz = np.abs(r * g[..., 4]).sum(0)
-    ez = np.abs(gz.double().cpu().numpy() - rgz) / sz
-    assert ez.max() <= TOL[dt] * 10, ez.max()
+    sz_r = dr * np.abs(g[..., 4]).sum(0)
+    ez = np.abs(gz.double().cpu().numpy() - rgz) / (TOL[dt] * sz + sz_r)
+    note(f"loglike config3-small {dt} grad_z", ez.max(), 1.0)
+    assert ez.max() <= 1.0, ez.max()
 
 
 def test_gaussian_loglike_matches_composition(dev):
@@ -443,7 +492,48 @@ def test_volume_config5_full_size_sampled(dev, dt):
     touched = np.unique(ci)
     ep = np.abs(gp[touched] - rgp[touched]) / sp[touched]
     tol = TOL[dt]
-    assert np.all(ep.max(0) <= np.array([tol, tol, tol, 5 * tol if dt == torch.float32 else tol])), ep.max(0)
+    note(f"vjp volume-full {dt} grad_params", (ep.max(0) / ptol(dt)).max(), 1.0)
+    assert np.all(ep.max(0) <= ptol(dt)), ep.max(0)
     assert np.all(gp[np.setdiff1d(np.arange(n_c), touched)] == 0.0)
     for i, r in rgz.items():
         assert abs(gz[i] - r) <= tol * sgz[i], (i, gz[i], r)
+
+
+def test_strided_and_expanded_redshift_views(dev):
+    """Redshift rows passed as views that are not dense rows: a column slice (row stride
+    above n_z) and a shared row expanded over the cosmologies (row stride 0).  The
+    forward, the adjoint, the fused likelihood (whose observed values and inverse
+    variances are laid out as z) and autograd must equal the same calls on a dense copy."""
+    params, zbig = workloads.config2(n_cosmo=5, n_z=400, seed=31)
+    p = torch.tensor(params, device=dev)
+    zb = torch.tensor(zbig, device=dev)
+    zs = zb[:, :300]
+    assert zs.stride(0) == 400
+    zc = zs.contiguous()
+    w = torch.tensor(np.random.default_rng(4).normal(size=(5, 300)), device=dev)
+    obs = cosmo.cosmo_distance("MU", p, zc) + 0.05
+    for kind in ("MU", "T"):
+        assert torch.equal(cosmo.cosmo_distance(kind, p, zs), cosmo.cosmo_distance(kind, p, zc)), kind
+        a = cosmo.cosmo_distance_vjp(kind, p, zs, w, want_value=True)
+        b = cosmo.cosmo_distance_vjp(kind, p, zc, w, want_value=True)
+        assert all(torch.equal(x, y) for x, y in zip(a, b)), kind
+    a = cosmo.cosmo_gaussian_loglike("MU", p, zs, obs, sigma=0.1)
+    b = cosmo.cosmo_gaussian_loglike("MU", p, zc, obs, sigma=0.1)
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+    # a shared row expanded over the cosmologies: per-element rows, gradient summed back
+    # over the expansion by autograd, equal to the shared-row adjoint
+    z1 = zc[0].clone()
+    ze = z1.expand(5, -1)
+    assert ze.stride(0) == 0
+    dense = z1[None, :].repeat(5, 1)
+    assert torch.equal(cosmo.cosmo_distance("DC", p, ze), cosmo.cosmo_distance("DC", p, dense))
+    obs_e = cosmo.cosmo_distance("MU", p, dense) + 0.05
+    a = cosmo.cosmo_gaussian_loglike("MU", p, ze, obs_e, sigma=0.1)
+    b = cosmo.cosmo_gaussian_loglike("MU", p, dense, obs_e, sigma=0.1)
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+    zr = z1.clone().requires_grad_(True)
+    (cosmo.distance("DC", p, zr.expand(5, -1)) * w).sum().backward()
+    _, gz_shared = cosmo.cosmo_distance_vjp("DC", p, z1, w)
+    _, gz_rows = cosmo.cosmo_distance_vjp("DC", p, dense, w)
+    assert torch.allclose(zr.grad, gz_rows.sum(0), rtol=1e-13, atol=0)
+    assert torch.allclose(zr.grad, gz_shared, rtol=1e-12, atol=0)

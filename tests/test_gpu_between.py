@@ -11,6 +11,7 @@ import pytest
 import torch
 
 import oracle
+from margins import note
 from paper_2212_01937_amd import cosmo, workloads
 
 pytestmark = pytest.mark.gpu
@@ -176,7 +177,15 @@ def test_between_full_size_sampled(dt):
 
 
 # --------------------------------------------------------------------------- adjoint
+# Bounds of the gradients relative to their natural scales: FP64 1e-10, FP32 1e-4; the
+# Or0 component on the FP32 path 5e-4 (its chain through the radiation root cancels by
+# about 0.35/Or0).
 GTOL = {torch.float64: 1e-10, torch.float32: 1e-4}
+
+
+def gptol(dt):
+    t = GTOL[dt]
+    return np.array([t, t, t, 5 * t if dt == torch.float32 else t])
 
 
 def ref_between_vjp(kind, params, z1, z2, w):
@@ -242,10 +251,11 @@ def test_between_vjp_workloads(kind, dt):
         assert not (direct & ~np.isinf(br).any(1)).any(), (label, kind)
         ep = np.abs(gp - rgp)[~direct] / np.maximum(sp[~direct], 1e-300)
         tol = GTOL[dt]
-        ptol = np.array([tol, tol, tol, 5 * tol if dt == torch.float32 else tol])
-        assert np.all(ep.max(0) <= ptol), (label, kind, dt, ep.max(0))
+        note(f"between-vjp {label} {kind} {dt} grad_params", (ep.max(0) / gptol(dt)).max(), 1.0)
+        assert np.all(ep.max(0) <= gptol(dt)), (label, kind, dt, ep.max(0))
         for got, ref, sc in ((g1, r1, s1), (g2, r2, s2)):
             e = np.abs(got.double().cpu().numpy() - ref) / np.maximum(sc, 1e-300 + 1e-12 * sc.max())
+            note(f"between-vjp {label} {kind} {dt} grad_z", e.max(), tol)
             assert e.max() <= tol, (label, kind, dt, float(e.max()))
         check(kind, dt, params, ar, br, val, label + " value from the adjoint")
 
@@ -268,7 +278,9 @@ def test_between_vjp_shared_limits_and_autograd(dt):
     ar, br, wr = a.detach().double().cpu().numpy(), b.detach().double().cpu().numpy(), w.double().cpu().numpy()
     rgp, sp, r1, r2, s1, s2 = ref_between_vjp("DA", params, ar, br, wr)
     tol = GTOL[dt]
-    assert np.max(np.abs(gp.cpu().numpy() - rgp) / sp) <= 5 * tol
+    ep = (np.abs(gp.cpu().numpy() - rgp) / sp).max(0)
+    note(f"between-vjp shared DA {dt} grad_params", (ep / gptol(dt)).max(), 1.0)
+    assert np.all(ep <= gptol(dt)), ep
     for got, ref, sc in ((g1, r1.sum(0), s1.sum(0)), (g2, r2.sum(0), s2.sum(0))):
         assert np.max(np.abs(got.double().cpu().numpy() - ref) / sc) <= tol
 
@@ -332,8 +344,9 @@ def test_between_vjp_eight_pairs_per_lane(kind, shared, dt):
     wt = torch.tensor(w, dtype=dt, device=DEV)
     val, gp, g1, g2 = cosmo.cosmo_distance_between_vjp(kind, p, a, b, wt, want_value=True)
     tol = GTOL[dt]
-    ep = np.abs(gp.cpu().numpy() - rgp) / sp
-    assert ep.max() <= (5 * tol if dt == torch.float32 else tol), (kind, dt, ep.max(0))
+    ep = (np.abs(gp.cpu().numpy() - rgp) / sp).max(0)
+    note(f"between-vjp 8-per-lane {kind} {dt} grad_params", (ep / gptol(dt)).max(), 1.0)
+    assert np.all(ep <= gptol(dt)), (kind, dt, ep)
     if shared:
         r1, r2, s1, s2 = r1.sum(0), r2.sum(0), s1.sum(0), s2.sum(0)
     for got, ref, sc in ((g1, r1, s1), (g2, r2, s2)):
@@ -345,11 +358,11 @@ def test_between_vjp_eight_pairs_per_lane(kind, shared, dt):
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
 def test_between_vjp_full_size_sampled(dt):
     """The benchmark's launch: D_A from lens to source, the 256 cosmologies of the large
-    batch x 1e6 shared pairs, value and gradients in one pass.  The limit gradients
-    (sums over all cosmologies) at 32 seeded sampled pairs against the oracle; the
-    parameter gradients (sums over all 1e6 pairs) against the sum of four launches over
-    quarters of the pairs, to the tolerance relative to a sampled estimate of the sum of
-    |w dD_A/dtheta|."""
+    batch x 1e6 shared pairs, value and gradients in one pass.  With a dense cotangent:
+    the limit gradients (sums over all cosmologies) at 32 seeded sampled pairs and the
+    values there, against the oracle.  With a cotangent supported on 300 sampled
+    (cosmology, pair) elements, in a second launch of the same size: every parameter
+    gradient (a sum over the sampled elements only) against the oracle's."""
     params, _ = workloads.config5()
     z1, z2 = workloads.lensing_pairs()
     n_c, n_z = params.shape[0], z1.size
@@ -370,17 +383,34 @@ def test_between_vjp_full_size_sampled(dt):
     for got, ref, sc in ((g1, r1.sum(0), s1.sum(0)), (g2, r2.sum(0), s2.sum(0))):
         got = got[torch.tensor(zi, device=DEV)].double().cpu().numpy()
         e = np.abs(got - ref) / sc
+        note(f"between-vjp full-size {dt} grad_z", e.max(), tol)
         assert e.max() <= tol, (dt, float(e.max()))
     check("DA", dt, params, ar, br, val[:, torch.tensor(zi, device=DEV)], "full-size value from the adjoint")
-    del val, g1, g2
-    q = n_z // 4
-    parts = [cosmo.cosmo_distance_between_vjp("DA", p, a[k * q:(k + 1) * q], b[k * q:(k + 1) * q],
-                                              w[:, k * q:(k + 1) * q].contiguous(), want_z=False)[0]
-             for k in range(4)]
-    gsum = sum(parts).cpu().numpy()
-    scale = sp * (n_z / zi.size)  # sampled estimate of sum_z |w dD_A/dtheta| per cosmology
-    e = np.abs(gp.cpu().numpy() - gsum) / scale
-    assert e.max() <= tol, (dt, e.max(0))
+    del val, g1, g2, w
+    # sampled-support cotangent: the parameter gradients are sums the oracle can form
+    ci, zj = workloads.subsample(n_c, n_z, 300, seed=779)
+    key = ci * n_z + zj
+    _, first = np.unique(key, return_index=True)
+    ci, zj = ci[first], zj[first]
+    wv = np.random.default_rng(9).normal(size=ci.shape[0])
+    w = torch.zeros((n_c, n_z), dtype=dt, device=DEV)
+    cit, zjt = torch.tensor(ci, device=DEV), torch.tensor(zj, device=DEV)
+    w[cit, zjt] = torch.tensor(wv, dtype=dt, device=DEV)
+    gp, _, _ = cosmo.cosmo_distance_between_vjp("DA", p, a, b, w, want_z=False)
+    gp = gp.cpu().numpy()
+    wr = w[cit, zjt].double().cpu().numpy()
+    ar, br = a.double().cpu().numpy(), b.double().cpu().numpy()
+    rgp = np.zeros((n_c, 4))
+    spp = np.zeros((n_c, 4))
+    for c in np.unique(ci):
+        m = ci == c
+        g_, s_, _, _, _, _ = ref_between_vjp("DA", params[c:c + 1], ar[zj[m]], br[zj[m]], wr[m][None, :])
+        rgp[c], spp[c] = g_[0], s_[0]
+    touched = np.unique(ci)
+    ep = (np.abs(gp[touched] - rgp[touched]) / spp[touched]).max(0)
+    note(f"between-vjp full-size {dt} grad_params", (ep / gptol(dt)).max(), 1.0)
+    assert np.all(ep <= gptol(dt)), (dt, ep)
+    assert np.all(gp[np.setdiff1d(np.arange(n_c), touched)] == 0.0)
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
@@ -398,7 +428,9 @@ def test_between_vjp_age_shared(dt):
     ar, wr = a.double().cpu().numpy(), w.double().cpu().numpy()
     rgp, sp, r1, _, s1, _ = ref_between_vjp("T", params, ar, np.full_like(ar, np.inf), wr)
     tol = GTOL[dt]
-    assert np.max(np.abs(gp.cpu().numpy() - rgp) / sp) <= 5 * tol
+    ep = (np.abs(gp.cpu().numpy() - rgp) / sp).max(0)
+    note(f"between-vjp age {dt} grad_params", (ep / gptol(dt)).max(), 1.0)
+    assert np.all(ep <= gptol(dt)), ep
     assert np.max(np.abs(g1.double().cpu().numpy() - r1.sum(0)) / s1.sum(0)) <= tol
     assert torch.equal(g2, torch.zeros_like(g2))
     check("T", dt, params, ar, np.full_like(ar, np.inf), val, "age value from the adjoint")

@@ -1,29 +1,33 @@
 """GPU parity of the forward path against the CPU oracle (element by element).
 
 FP64 path: max relative error <= 1e-12 (D_C, D_M, D_L, D_A, T, X); mu absolute
-<= 1e-11 mag.  FP32 path (FP64 roots): max relative error <= 1e-6, mu <= 1e-4 mag
-absolute (these are the stated bounds of the method's two precisions).
+<= 2.2e-12 mag (a relative error 1e-12 of D_L moves mu by 5/ln 10 x 1e-12).  FP32 path
+(FP64 roots): max relative error <= 1e-6, mu <= 1e-4 mag absolute (the stated bounds
+of the method's two precisions).  Beyond the antipode of a closed universe D_M and mu
+are measured against the size a relative error of chi moves them by (cond_scale).
 """
 import numpy as np
 import pytest
 import torch
 
 import oracle
+from margins import note
 from paper_2212_01937_amd import cosmo, workloads
 
 pytestmark = pytest.mark.gpu
 
 KINDS = ["DC", "DM", "DL", "MU", "T", "X", "DA", "VC"]
 TOL = {torch.float64: 1e-12, torch.float32: 1e-6}
-MU_TOL = {torch.float64: 1e-11, torch.float32: 1e-4}
+MU_TOL = {torch.float64: 2.2e-12, torch.float32: 1e-4}
 
 
 def cond_scale(kind, params, z, ref):
     """Error scale of an observable that applies the curvature transform sinn to
     chi = D_C/D_H: a relative error eps in chi moves it by eps |d out/d chi| chi, which
     beyond the antipode of a closed universe (sin near zero) exceeds eps |out|.
-    Returns |out| + |d out/d chi| chi (mu: 1 + |C chi / S| in units of 5/ln 10; the
-    comoving volume: max(|V|, chi dV/dchi))."""
+    Returns |out| + |d out/d chi| chi (mu, in magnitudes: max(1, |C chi / S|), the
+    factor by which a relative error of chi exceeds the relative error of D_L it causes,
+    which is 1 for a flat universe; the comoving volume: max(|V|, chi dV/dchi))."""
     params = np.asarray(params, dtype=np.float64).reshape(-1, 4)
     n = params.shape[0]
     ref2 = np.asarray(ref, dtype=np.float64).reshape(n, -1)
@@ -38,7 +42,8 @@ def cond_scale(kind, params, z, ref):
     sk = np.where(ok == 0, 1.0, np.sqrt(np.abs(ok)))
     s = np.where(ok == 0, chi, np.where(ok < 0, np.sin(x), np.sinh(x)) / sk)
     if kind == "MU":
-        out = 1.0 + np.abs(c * chi / s)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            out = np.maximum(1.0, np.abs(c * chi / s))
     elif kind == "VC":
         # V_C = 4 pi D_H^3 G(chi): a relative error eps in chi moves it by eps chi dV/dchi
         # = eps 4 pi D_H^3 chi S^2 (about 3 |V| for small curvature)
@@ -89,6 +94,7 @@ def check(kind, dt, got, ref, label="", params=None, z=None):
     e = errs(kind, got, ref, scale)
     tol = MU_TOL[dt] if kind == "MU" else TOL[dt]
     i = int(np.argmax(e))
+    note(f"fwd {label} {kind} {dt}", e[i], tol)
     assert e[i] <= tol, f"{label} {kind} {dt}: max err {e[i]:.3e} at flat index {i}"
 
 

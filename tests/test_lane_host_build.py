@@ -30,11 +30,7 @@ def _build(out, noise):
         subprocess.run(["g++", *flags, "-mfma", src, "-o", out], check=True)
     except subprocess.CalledProcessError:
         subprocess.run(["g++", *flags, src, "-o", out], check=True)
-    lib = ctypes.CDLL(out)
-    x64, w64 = np.polynomial.legendre.leggauss(20)
-    x32, w32 = (a.astype(np.float32) for a in np.polynomial.legendre.leggauss(8))
-    lib.host_set_gl(*(a.ctypes.data_as(ctypes.c_void_p) for a in (x64, w64, x32, w32)))
-    return lib
+    return ctypes.CDLL(out)
 
 
 @pytest.fixture(scope="module")
