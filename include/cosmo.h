@@ -10,7 +10,8 @@
  *    compile-time constants), never frees caller memory and is safe to call from
  *    several host threads.  With a caller-supplied workspace a call only enqueues
  *    kernel launches, so it can be captured in a HIP graph, the first call of a
- *    program included.
+ *    program included.  The one exception is cosmo_distance_vjp_noalloc, which
+ *    works in a fixed device array of the library (see there).
  *  - Calls enqueue asynchronously on `stream` (a hipStream_t passed as void*;
  *    NULL is the default stream) and return a cosmo_status.  Argument errors
  *    (NULL pointers, negative sizes, unknown kind/dtype, workspace too small) are
@@ -45,8 +46,14 @@ typedef enum {
     COSMO_E_KIND = -2,      /* unknown cosmo_kind                                */
     COSMO_E_DTYPE = -3,     /* unknown cosmo_dtype                               */
     COSMO_E_HIP = -4,       /* a HIP runtime call or kernel launch failed       */
-    COSMO_E_WORKSPACE = -5  /* workspace too small (see cosmo_workspace_size)   */
+    COSMO_E_WORKSPACE = -5, /* workspace too small (see cosmo_workspace_size)   */
+    COSMO_E_SCRATCH = -6    /* problem too large for the fixed device array of
+                               cosmo_distance_vjp_noalloc                       */
 } cosmo_status;
+
+/* Size in bytes of the fixed device array that cosmo_distance_vjp_noalloc works in
+ * (one per GPU, held until the process ends).                                    */
+#define COSMO_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 
 typedef enum { COSMO_F32 = 0, COSMO_F64 = 1 } cosmo_dtype;
 
@@ -173,6 +180,34 @@ int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params,
                        int64_t n_cosmo, const void *z, int64_t n_z, int64_t z_cosmo_stride,
                        const void *cot, void *out, double *grad_params, void *grad_z,
                        int32_t *info, void *workspace, size_t workspace_bytes, void *stream);
+
+/* cosmo_distance_vjp_noalloc -- cosmo_distance_vjp for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops that forbid
+ * hipMalloc): the same kernels and results (bit for bit), with the per-cosmology
+ * records and partial sums in a fixed device array of the library instead of a
+ * workspace.  It calls no hipMalloc, hipFree or other allocating routine; the
+ * caller passes every input and output as in cosmo_distance_vjp.
+ *  - The array holds COSMO_NOALLOC_SCRATCH_BYTES per GPU.  A call needs the record
+ *    table (under 1 KB per cosmology); with grad_params, 44 B (FP32) or 88 B (FP64)
+ *    per cosmology per 512 redshifts (per 64 redshifts when n_z < 8192); with a
+ *    shared-z grad_z and more than one tile of cosmologies (tiles of up to 16),
+ *    one dtype element per redshift per tile.  It fits whenever
+ *    cosmo_workspace_size(n_cosmo, n_z) <= COSMO_NOALLOC_SCRATCH_BYTES, and often
+ *    beyond (64 cosmologies x 1e6 shared redshifts fit in either dtype).  Larger
+ *    problems return COSMO_E_SCRATCH, detected on the host before any HIP call.
+ *  - The first call on a GPU resolves the array's device address there
+ *    (hipGetSymbolAddress, with that GPU current); make that first call outside a
+ *    graph capture if the capture must hold kernel launches only.
+ *  - All calls on one GPU share its array: calls that overlap in time on one GPU
+ *    (different streams or host threads without ordering) race and give wrong
+ *    results.  Calls ordered on one stream are safe: each call writes every byte
+ *    of the array it reads before reading it.
+ * Arguments and errors otherwise as cosmo_distance_vjp.                         */
+int cosmo_distance_vjp_noalloc(cosmo_kind kind, cosmo_dtype dt, const double *params,
+                               int64_t n_cosmo, const void *z, int64_t n_z,
+                               int64_t z_cosmo_stride, const void *cot, void *out,
+                               double *grad_params, void *grad_z, int32_t *info,
+                               void *stream);
 
 /* cosmo_distance_jac -- the observable with its materialised per-evaluation
  * Jacobian: the same derivatives as cosmo_distance_vjp (Carlson derivatives,

@@ -21,14 +21,15 @@ LIB_PATH = os.path.join(_HERE, "libcosmo.so")
 KINDS = {"DC": 0, "DM": 1, "DL": 2, "MU": 3, "T": 4, "X": 5, "DA": 6, "VC": 7}
 DTYPES = {torch.float32: 0, torch.float64: 1}
 STATUS = {0: "COSMO_OK", -1: "COSMO_E_ARG", -2: "COSMO_E_KIND", -3: "COSMO_E_DTYPE",
-          -4: "COSMO_E_HIP", -5: "COSMO_E_WORKSPACE"}
+          -4: "COSMO_E_HIP", -5: "COSMO_E_WORKSPACE", -6: "COSMO_E_SCRATCH"}
+NOALLOC_SCRATCH_BYTES = 64 << 20  # COSMO_NOALLOC_SCRATCH_BYTES
 INFO = {"CUBIC": 0x1, "QUARTIC": 0x2, "THREE_REAL": 0x4, "YELLOW": 0x8, "RED": 0x10,
         "DOMAIN": 0x20, "ROOT_NOCONV": 0x40, "NEAR_MULTIROOT": 0x80, "X_QUADRATURE": 0x100}
 
 # every function declared in include/cosmo.h
 EXPORTS = ("cosmo_workspace_size", "cosmo_roots", "carlson_rf", "carlson_rd", "carlson_rj",
            "carlson_rc", "cosmo_distance", "cosmo_distance_between", "cosmo_distance_between_vjp",
-           "cosmo_distance_vjp", "cosmo_distance_jac",
+           "cosmo_distance_vjp", "cosmo_distance_vjp_noalloc", "cosmo_distance_jac",
            "cosmo_gaussian_loglike", "snia_draw", "snia_latent_vjp", "snia_workspace_size", "cosmo_version")
 
 _lib = None
@@ -61,6 +62,8 @@ def load():
                                                vp, vp, i32p, vp, ctypes.c_size_t, vp]
     lib.cosmo_distance_vjp.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, vp, vp,
                                        i32p, vp, ctypes.c_size_t, vp]
+    lib.cosmo_distance_vjp_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, vp, vp,
+                                               i32p, vp]
     lib.cosmo_distance_jac.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, i32p, vp,
                                        ctypes.c_size_t, vp]
     lib.cosmo_gaussian_loglike.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, vp, vp, vp,
@@ -266,11 +269,7 @@ def cosmo_distance_between_vjp(kind, params, z1, z2, cot, want_params=True, want
     return res + (inf,) if info else res
 
 
-def cosmo_distance_vjp(kind, params, z, cot, want_params=True, want_z=True, info=False, workspace=None,
-                       want_value=False):
-    """Adjoint: (grad_params [n_cosmo, 4] float64 or None, grad_z like z or None).
-    With want_value=True the observable is computed in the same pass and returned
-    first: (value [n_cosmo, n_z], grad_params, grad_z)."""
+def _vjp_call(name, kind, params, z, cot, want_params, want_z, info, workspace, want_value):
     lib = load()
     p = _params(params)
     n_c = p.shape[0]
@@ -283,14 +282,35 @@ def cosmo_distance_vjp(kind, params, z, cot, want_params=True, want_z=True, info
         gz = torch.empty(n_z if shared else (n_c, n_z), dtype=zc.dtype, device=p.device)
     val = torch.empty((n_c, n_z), dtype=zc.dtype, device=p.device) if want_value else None
     inf = torch.empty(n_c, dtype=torch.int32, device=p.device) if info else None
-    ws = workspace if workspace is not None else _workspace(n_c, n_z, p.device)
+    args = (KINDS[kind], DTYPES[zc.dtype], _ptr(p), n_c, _ptr(zc), n_z, stride, _ptr(c), _ptr(val), _ptr(gp),
+            _ptr(gz), _ptr(inf))
     with torch.cuda.device(p.device):
-        rc = lib.cosmo_distance_vjp(KINDS[kind], DTYPES[zc.dtype], _ptr(p), n_c, _ptr(zc), n_z, stride,
-                                    _ptr(c), _ptr(val), _ptr(gp), _ptr(gz), _ptr(inf), _ptr(ws), ws.numel(),
-                                    _stream(p.device))
-    _check(rc, "cosmo_distance_vjp")
+        if name == "cosmo_distance_vjp":
+            ws = workspace if workspace is not None else _workspace(n_c, n_z, p.device)
+            rc = lib.cosmo_distance_vjp(*args, _ptr(ws), ws.numel(), _stream(p.device))
+        else:
+            rc = lib.cosmo_distance_vjp_noalloc(*args, _stream(p.device))
+    _check(rc, name)
     res = ((val,) if want_value else ()) + (gp, gz)
     return res + (inf,) if info else res
+
+
+def cosmo_distance_vjp(kind, params, z, cot, want_params=True, want_z=True, info=False, workspace=None,
+                       want_value=False):
+    """Adjoint: (grad_params [n_cosmo, 4] float64 or None, grad_z like z or None).
+    With want_value=True the observable is computed in the same pass and returned
+    first: (value [n_cosmo, n_z], grad_params, grad_z)."""
+    return _vjp_call("cosmo_distance_vjp", kind, params, z, cot, want_params, want_z, info, workspace, want_value)
+
+
+def cosmo_distance_vjp_noalloc(kind, params, z, cot, want_params=True, want_z=True, info=False,
+                               want_value=False):
+    """cosmo_distance_vjp with the library's fixed per-GPU device array in place of a
+    workspace (the C entry point allocates nothing; the outputs returned here are
+    torch tensors allocated by this wrapper).  Problems beyond NOALLOC_SCRATCH_BYTES
+    raise CosmoError (COSMO_E_SCRATCH); calls overlapping in time on one GPU race."""
+    return _vjp_call("cosmo_distance_vjp_noalloc", kind, params, z, cot, want_params, want_z, info, None,
+                     want_value)
 
 
 def cosmo_distance_jac(kind, params, z, want_value=True, info=False, workspace=None):

@@ -9,6 +9,7 @@
 // (cosmology tile, z block) with z blocks fastest.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -726,6 +727,49 @@ WsLayout ws_layout(int64_t n_cosmo, int64_t n_z) {
     return w;
 }
 
+// Device memory of cosmo_distance_vjp_noalloc, for callers that cannot allocate:
+// the record table, the wave partial sums and the tile partials of a shared-z
+// gradient in place of a workspace.  Every GPU the library runs on holds its own
+// copy until the process ends; calls on one GPU share it (every byte a call reads is
+// written by the same call first, so nothing needs clearing between calls, but calls
+// that overlap in time on one GPU race).  Host code never names the array in a
+// kernel argument or copy: its name is a host-side stand-in there, and the device
+// address comes from hipGetSymbolAddress, resolved once per device.
+constexpr size_t kScratchBytes = COSMO_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::atomic<void *> g_scratch_addr[kMaxDevices];
+
+// Address of `scratch` on the current device (resolved on the first call there; two
+// threads racing on the first call store the same address).
+int scratch_address(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return COSMO_E_HIP;
+    void *p = g_scratch_addr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return COSMO_E_HIP;
+        g_scratch_addr[dev].store(p, std::memory_order_release);
+    }
+    *out = p;
+    return COSMO_OK;
+}
+
+// Layout of the adjoint's device memory packed for the fixed scratch array: the
+// partial sums in the lane precision and only the tile-partial plane this call uses.
+template <typename T>
+WsLayout noalloc_layout(int64_t n_cosmo, int64_t n_z, int64_t zstride, bool want_params, bool want_z) {
+    Tiling t = tiling(n_cosmo, n_z, vjp_zpt(n_z));
+    WsLayout w;
+    w.recs = 0;
+    w.pacc = align256(sizeof(CosmoRec) * (size_t)n_cosmo);
+    const size_t np = want_params ? sizeof(T) * kAcc * (size_t)n_cosmo * (size_t)t.nzb * (kBlock / 64) : 0;
+    w.gzp = w.pacc + align256(np);
+    const bool part = want_z && zstride == 0 && t.ntile > 1 && n_z > 0;
+    w.total = w.gzp + (part ? align256(sizeof(T) * (size_t)t.ntile * (size_t)n_z) : 0);
+    return w;
+}
+
 bool valid_kind(int k) { return k >= COSMO_DC && k <= COSMO_VC; }
 bool valid_dtype(int d) { return d == COSMO_F32 || d == COSMO_F64; }
 
@@ -1109,6 +1153,45 @@ int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params, in
     return launch_vjp<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, (const double *)cot,
                               nullptr, nullptr, nullptr, (double *)out, grad_params, (double *)grad_z, info, L,
                               (char *)ws.ptr, s);
+}
+
+int cosmo_distance_vjp_noalloc(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo,
+                               const void *z, int64_t n_z, int64_t z_cosmo_stride, const void *cot, void *out,
+                               double *grad_params, void *grad_z, int32_t *info, void *stream) {
+    if (!valid_kind(kind)) return COSMO_E_KIND;
+    if (!valid_dtype(dt)) return COSMO_E_DTYPE;
+    if (n_cosmo < 0 || n_z < 0 || z_cosmo_stride < 0) return COSMO_E_ARG;
+    if (n_cosmo > 0 && !params) return COSMO_E_ARG;
+    if (n_cosmo > 0 && n_z > 0 && (!z || !cot)) return COSMO_E_ARG;
+    if (check_grid(n_cosmo, n_z) != COSMO_OK) return COSMO_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_cosmo == 0) {
+        if (grad_z && n_z > 0 && z_cosmo_stride == 0) {
+            unsigned nb = (unsigned)((n_z + kBlock - 1) / kBlock);
+            if (dt == COSMO_F32) hipLaunchKernelGGL(k_fill_zero<float>, dim3(nb), dim3(kBlock), 0, s, (float *)grad_z, n_z);
+            else hipLaunchKernelGGL(k_fill_zero<double>, dim3(nb), dim3(kBlock), 0, s, (double *)grad_z, n_z);
+            if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
+        }
+        return COSMO_OK;
+    }
+    const WsLayout L = dt == COSMO_F32
+                           ? noalloc_layout<float>(n_cosmo, n_z, z_cosmo_stride, grad_params != nullptr, grad_z != nullptr)
+                           : noalloc_layout<double>(n_cosmo, n_z, z_cosmo_stride, grad_params != nullptr, grad_z != nullptr);
+    // checked before any HIP call: a problem beyond the fixed array is refused whole
+    if (L.total > kScratchBytes) return COSMO_E_SCRATCH;
+    void *base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc != COSMO_OK) return rc;
+    CosmoRec *recs = (CosmoRec *)base;
+    rc = launch_setup(params, n_cosmo, recs, info, s);
+    if (rc != COSMO_OK) return rc;
+    if (dt == COSMO_F32)
+        return launch_vjp<float>(kind, recs, n_cosmo, (const float *)z, n_z, z_cosmo_stride, (const float *)cot,
+                                 nullptr, nullptr, nullptr, (float *)out, grad_params, (float *)grad_z, info, L,
+                                 (char *)base, s);
+    return launch_vjp<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, (const double *)cot,
+                              nullptr, nullptr, nullptr, (double *)out, grad_params, (double *)grad_z, info, L,
+                              (char *)base, s);
 }
 
 int cosmo_distance_jac(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo, const void *z,

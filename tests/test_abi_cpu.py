@@ -143,3 +143,25 @@ def test_supernova_entry_points_argument_errors(lib):
     assert lib.snia_workspace_size(4, 1000, ctypes.byref(nb)) == 0 and nb.value >= 8 * 4 * 9
     assert lib.snia_workspace_size(-1, 1000, ctypes.byref(nb)) == E_ARG
     assert lib.snia_workspace_size(4, 1000, None) == E_ARG
+
+
+def test_noalloc_refuses_problems_beyond_its_array(lib):
+    """cosmo_distance_vjp_noalloc checks the problem against its fixed device array on
+    the host, before any HIP call (so these run without a GPU)."""
+    E_ARG, E_KIND, E_SCRATCH = -1, -2, -6
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced on these paths
+    null = None
+    f = lib.cosmo_distance_vjp_noalloc
+    assert f(42, 0, dummy, 1, dummy, 1, 0, dummy, null, dummy, dummy, null, null) == E_KIND
+    assert f(3, 0, dummy, 1, dummy, 1, 0, null, null, dummy, dummy, null, null) == E_ARG
+    assert f(3, 0, dummy, -1, dummy, 1, 0, dummy, null, dummy, dummy, null, null) == E_ARG
+    # record table alone beyond the array (1e5 cosmologies, ~88 MB of records)
+    assert f(3, 1, dummy, 100000, dummy, 1, 0, dummy, null, null, null, null, null) == E_SCRATCH
+    # 256 cosmologies x 1e6 shared redshifts, FP64: the parameter partials fit (44 MB),
+    # the 16 tile planes of the shared-z gradient (128 MB) do not
+    assert f(3, 1, dummy, 256, dummy, 10 ** 6, 0, dummy, null, dummy, dummy, null, null) == E_SCRATCH
+    # 4096 cosmologies x 65536 shared redshifts, FP32: 256 tile planes (67 MB)
+    assert f(3, 0, dummy, 4096, dummy, 65536, 0, dummy, null, null, dummy, null, null) == E_SCRATCH
+    assert cosmo.NOALLOC_SCRATCH_BYTES == 64 << 20
+    src = open(os.path.join(ROOT, "include", "cosmo.h")).read()
+    assert "#define COSMO_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)" in src
