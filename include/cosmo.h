@@ -81,6 +81,8 @@ typedef enum {
 #define COSMO_INFO_ROOT_NOCONV    0x0040 /* root polishing hit its iteration cap     */
 #define COSMO_INFO_NEAR_MULTIROOT 0x0080 /* two roots closer than 1e-4 (relative): gradients by quadrature */
 #define COSMO_INFO_X_QUADRATURE   0x0100 /* some X lanes used the Gauss-Legendre route */
+#define COSMO_INFO_NEAR_MULTIROOT_F32 0x0200 /* two roots closer than 2e-2 (relative): the FP32
+                                                 path's gradients take the quadrature    */
 
 /* Number of bytes of device workspace that cosmo_distance / cosmo_distance_vjp
  * need for this problem size.  A NULL workspace is also accepted by those calls:
@@ -163,6 +165,23 @@ int cosmo_distance_between_vjp(cosmo_kind kind, cosmo_dtype dt, const double *pa
                                int64_t z_cosmo_stride, const void *cot, void *out,
                                double *grad_params, void *grad_z1, void *grad_z2, int32_t *info,
                                void *workspace, size_t workspace_bytes, void *stream);
+
+/* cosmo_route_counts -- which route each (cosmology, redshift) lane of `kind` takes,
+ * counted per cosmology: the reductions of sec. 3.1 / app. B.1 (eqs. 3.7-3.9,
+ * B.1-B.3) against the fallbacks of this implementation.  The routes are decided by
+ * the same device functions the forward and adjoint kernels branch on; the values
+ * themselves are evaluated (for X) and discarded.
+ * counts: [n_cosmo][4] int64 out, overwritten (zero for cosmologies outside the
+ *         method): [0] lanes whose value takes the Carlson reduction in the dtype's
+ *         precision; [1] FP32 X lanes whose R_F term is refined in FP64 (the terms of
+ *         eq. 3.9 cancel by more than 8); [2] lanes whose value takes Gauss-Legendre
+ *         quadrature of eq. 2.5 (X only, beyond a cancellation of 1024); [3] lanes whose
+ *         adjoint takes the Leibniz-rule quadrature (X; near-multiple roots, see the
+ *         NEAR_MULTIROOT info bits; FP32 lanes below z = 0.02).
+ * Other arguments as cosmo_distance (the workspace holds the records only).       */
+int cosmo_route_counts(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo,
+                       const void *z, int64_t n_z, int64_t z_cosmo_stride, int64_t *counts,
+                       void *workspace, size_t workspace_bytes, void *stream);
 
 /* cosmo_distance_vjp -- adjoint of cosmo_distance for a cotangent `cot`
  * ([n_cosmo][n_z], dtype).  Gradients through the Carlson derivatives (eqs.

@@ -24,12 +24,13 @@ STATUS = {0: "COSMO_OK", -1: "COSMO_E_ARG", -2: "COSMO_E_KIND", -3: "COSMO_E_DTY
           -4: "COSMO_E_HIP", -5: "COSMO_E_WORKSPACE", -6: "COSMO_E_SCRATCH"}
 NOALLOC_SCRATCH_BYTES = 64 << 20  # COSMO_NOALLOC_SCRATCH_BYTES
 INFO = {"CUBIC": 0x1, "QUARTIC": 0x2, "THREE_REAL": 0x4, "YELLOW": 0x8, "RED": 0x10,
-        "DOMAIN": 0x20, "ROOT_NOCONV": 0x40, "NEAR_MULTIROOT": 0x80, "X_QUADRATURE": 0x100}
+        "DOMAIN": 0x20, "ROOT_NOCONV": 0x40, "NEAR_MULTIROOT": 0x80, "X_QUADRATURE": 0x100,
+        "NEAR_MULTIROOT_F32": 0x200}
 
 # every function declared in include/cosmo.h
 EXPORTS = ("cosmo_workspace_size", "cosmo_roots", "carlson_rf", "carlson_rd", "carlson_rj",
            "carlson_rc", "cosmo_distance", "cosmo_distance_between", "cosmo_distance_between_vjp",
-           "cosmo_distance_vjp", "cosmo_distance_vjp_noalloc", "cosmo_distance_jac",
+           "cosmo_distance_vjp", "cosmo_distance_vjp_noalloc", "cosmo_distance_jac", "cosmo_route_counts",
            "cosmo_gaussian_loglike", "snia_draw", "snia_latent_vjp", "snia_workspace_size", "cosmo_version")
 
 _lib = None
@@ -64,6 +65,7 @@ def load():
                                        i32p, vp, ctypes.c_size_t, vp]
     lib.cosmo_distance_vjp_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, vp, vp,
                                                i32p, vp]
+    lib.cosmo_route_counts.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, ctypes.c_size_t, vp]
     lib.cosmo_distance_jac.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, i32p, vp,
                                        ctypes.c_size_t, vp]
     lib.cosmo_gaussian_loglike.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, i64, vp, vp, vp, vp, vp,
@@ -206,6 +208,26 @@ def cosmo_distance(kind, params, z, info=False, workspace=None):
                                 _ptr(out), _ptr(inf), _ptr(ws), ws.numel(), _stream(p.device))
     _check(rc, "cosmo_distance")
     return (out, inf) if info else out
+
+
+ROUTES = ("carlson", "carlson_fp64_rf", "quadrature", "adjoint_quadrature")
+
+
+def cosmo_route_counts(kind, params, z, workspace=None):
+    """Per-cosmology lane counts of the routes of `kind` (int64 [n_cosmo, 4], columns as
+    ROUTES): value by the Carlson reduction in the dtype's precision; FP32 X lanes with
+    the R_F term refined in FP64; value by quadrature; adjoint by Leibniz quadrature."""
+    lib = load()
+    p = _params(params)
+    n_c = p.shape[0]
+    zc, n_z, stride, _ = _z_layout(z, n_c)
+    counts = torch.empty((n_c, 4), dtype=torch.int64, device=p.device)
+    ws = workspace if workspace is not None else _workspace(n_c, n_z, p.device)
+    with torch.cuda.device(p.device):
+        rc = lib.cosmo_route_counts(KINDS[kind], DTYPES[zc.dtype], _ptr(p), n_c, _ptr(zc), n_z, stride,
+                                    _ptr(counts), _ptr(ws), ws.numel(), _stream(p.device))
+    _check(rc, "cosmo_route_counts")
+    return counts
 
 
 def cosmo_distance_between(kind, params, z1, z2, info=False, workspace=None):

@@ -11,6 +11,10 @@
 
 namespace cosmo {
 
+// Route predicates of the adjoint (the kernels branch on exactly these; the route
+// counts of cosmo_route_counts use them too).  Per cosmology: all gradients by
+// quadrature for X and for roots closer than the precision's threshold (the
+// COSMO_INFO_NEAR_MULTIROOT bits).
 __device__ __forceinline__ bool direct_mode(int kind, const CosmoRec &r, bool fp32) {
     if (kind == COSMO_X) return true;
     return r.minsep < (fp32 ? 2e-2 : 1e-4);
@@ -40,6 +44,12 @@ template <bool PAIR> __device__ __attribute__((noinline)) GlChi gl_chi_grad(cons
 // no such cancellation; one 8-node panel suffices there (the panel is a fraction of
 // the distance to the nearest singularity of the integrand).
 constexpr float kSmallZ32 = 0.02f;
+// Per lane, on root-chain cosmologies: the FP32 small-z quadrature.
+template <typename T> __device__ __forceinline__ bool small_z_lane(T z) { return sizeof(T) == 4 && z < T(kSmallZ32); }
+// Whether the adjoint of lane (r, z) takes the Leibniz quadrature.
+template <typename T> __device__ __forceinline__ bool adjoint_quadrature_lane(int kind, const CosmoRec &r, T z) {
+    return direct_mode(kind, r, sizeof(T) == 4) || small_z_lane<T>(z);
+}
 
 // Derivatives of one (cosmology, redshift) lane.  The observable is out = F(base, Ok, z,
 // H0) with base = chi (D_C family), t (T) or X; s = dF/dbase.
@@ -64,7 +74,7 @@ __device__ __forceinline__ void lane_grad(const CosmoRec &r, T z, LaneGrad<T> &o
     const T H0inv = k.hinv;
     o.dok = T(0);
     o.quad = false;
-    const bool small = fp32 && z < T(kSmallZ32);
+    const bool small = small_z_lane<T>(z);
     if (KIND == COSMO_T && !direct_mode(KIND, r, fp32)) {
         // time coordinate: Carlson derivatives (eqs. 2.10, 2.11) and the root chain
         if (small) {
@@ -91,13 +101,13 @@ __device__ __forceinline__ void lane_grad(const CosmoRec &r, T z, LaneGrad<T> &o
         const T x = T(1) + z;
         const T e = Ez<T>(k, z);
         o.dz = o.s * (KIND == COSMO_T ? Fp<T>::rcp(x * e) : x * x * Fp<T>::rcp(e));
-        // the value (also needed for the H0 derivative) by the forward's route: for X
-        // in FP32 with radiation that route is this same quadrature
-        if (KIND == COSMO_X && sizeof(T) == 4 && k.sigma != T(0)) {
-            o.val = k.dh * qv;
-            used_gl = true;
+        // the value (also needed for the H0 derivative) by the forward's route
+        if (KIND == COSMO_T) {
+            o.val = k.th * t_hat<T, PAIR>(r, z);
         } else {
-            o.val = KIND == COSMO_T ? k.th * t_hat<T, PAIR>(r, z) : k.dh * x_hat<T, PAIR>(k, z, used_gl);
+            int route;
+            o.val = k.dh * x_hat<T, PAIR>(r, z, route);
+            used_gl = route == kXRouteQuad;
         }
         o.q[0] = g[0]; o.q[1] = g[1]; o.q[2] = g[2];
         o.quad = true;
@@ -137,6 +147,63 @@ __device__ __forceinline__ void lane_grad(const CosmoRec &r, T z, LaneGrad<T> &o
         o.val = observable<T>(KIND, k, o.p[0], z, H0inv, o.s, o.dok, dzz, o.dh);
     }
     o.dz = dzz + o.s * ie;
+}
+
+// The common lane of the adjoint: root-chain route (separated roots, KIND not X), and
+// on the FP32 path z at or above kSmallZ32.  The same arithmetic as lane_grad's
+// root-chain branches, without the quadrature routes (which the kernels run in a
+// separate pass over the few lanes that need them, so their registers and branches
+// stay out of the main loop).
+template <typename T> struct RootGrad {
+    T val, s, dok, dh, dz;
+    T p[5];
+};
+
+template <typename T, int KIND, bool PAIR>
+__device__ __forceinline__ void lane_grad_root(const CosmoRec &r, T z, RootGrad<T> &o) {
+    const LaneConst<T> &k = lane_of<T>(r);
+    const T H0inv = k.hinv;
+    if (KIND == COSMO_T) {
+        TGrad<T, PAIR> tg;
+        t_grad<T, PAIR>(r, z, tg);
+        o.p[0] = tg.t; o.p[1] = tg.dsig; o.p[2] = tg.dr0; o.p[3] = tg.dr1re; o.p[4] = PAIR ? tg.dr1im : tg.dr2;
+        o.s = k.th;
+        o.val = k.th * o.p[0];
+        o.dok = T(0);
+        o.dh = -o.val * H0inv;
+        o.dz = k.th * Fp<T>::rcp(T(1) + z) * iEz<T>(k, z);
+        return;
+    }
+    ChiGrad<T, PAIR> cg;
+    chi_grad<T, PAIR>(k, z, cg);
+    o.p[0] = cg.chi; o.p[1] = cg.dsig; o.p[2] = cg.dr0; o.p[3] = cg.dr1re; o.p[4] = PAIR ? cg.dr1im : cg.dr2;
+    T dzz;
+    o.val = observable<T>(KIND, k, o.p[0], z, H0inv, o.s, o.dok, dzz, o.dh);
+    o.dz = dzz + o.s * cg.iE;
+}
+
+// FP32 lanes below kSmallZ32 on root-chain cosmologies: lane_grad's one-panel
+// Leibniz quadrature (chi family and T).  Parameter partials in q (d/d(Om, OL, Or)).
+template <typename T, int KIND, bool PAIR>
+__device__ __forceinline__ void lane_grad_small(const CosmoRec &r, T z, LaneGrad<T> &o) {
+    const LaneConst<T> &k = lane_of<T>(r);
+    const T H0inv = k.hinv;
+    T v, g[3];
+    gl_integral<T, PAIR>(k, z, KIND == COSMO_T ? 1 : 0, true, v, g, 1);
+    o.q[0] = g[0]; o.q[1] = g[1]; o.q[2] = g[2];
+    o.quad = true;
+    o.p[0] = v;
+    if (KIND == COSMO_T) {
+        o.s = k.th;
+        o.val = k.th * v;
+        o.dok = T(0);
+        o.dh = -o.val * H0inv;
+        o.dz = k.th * Fp<T>::rcp(T(1) + z) * iEz<T>(k, z);
+        return;
+    }
+    T dzz;
+    o.val = observable<T>(KIND, k, v, z, H0inv, o.s, o.dok, dzz, o.dh);
+    o.dz = dzz + o.s * iEz<T>(k, z);
 }
 
 // Contraction of root-space partials with the root Jacobian (app. A), FP64:

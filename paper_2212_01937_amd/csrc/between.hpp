@@ -294,6 +294,139 @@ __device__ __forceinline__ void chi_grad_between(const LaneConst<T> &k, T z1, T 
     if (zinf && k.sigma == T(0)) o.dsig = Fp<T>::nan();
 }
 
+// t(z1, z2)/(1/H0) and its partials in the root parameters (sigma, rho_0, rho_1 [re, im]
+// or rho_1, rho_2) at fixed beta: eq. 3.8 between the two limits, differentiated as
+// t_grad differentiates the one-sided form (R_F, R_J and R_C partials from eqs. 2.10 and
+// 2.11, Euler's relation for R_J's last argument, R_C's homogeneity; the explicit sigma-
+// and root-dependence of the coefficients), with the square roots of both limits in the
+// chain through the U_m (as chi_grad_between) and Q5 = x1 x2 W5 / ((1 - sigma x1)(1 -
+// sigma x2)), so dQ5/dsigma at fixed W5 = Q5 (x1/(1 - sigma x1) + x2/(1 - sigma x2)) (at
+// an infinite upper limit the scaled side has x = 1 and 1 - sigma x -> -sigma).  The
+// Carlson arguments are formed in FP64 on the FP32 path (as t_between); the chain's
+// geometry in the lane precision.  Not for an infinite upper limit at small |sigma|
+// (kAgeSigma32/64 below; the Leibniz route covers it).
+// The age t(z, inf) through the chain: its sigma partials grow like powers of 1/|sigma|
+// (the infinite side has 1 - sigma x -> -sigma) while d t/d Or0 stays finite, so the Or0
+// component cancels, by ~|sigma|^(-1/2) (measured on the host build against the
+// oracle: FP32 1e-4 relative at Or0 = 1e-5, FP64 6e-11 at Or0 = 1e-10).  Below these
+// |sigma| the age takes the Leibniz route, whose Or0 derivative has no cancellation.
+constexpr float kAgeSigma32 = 1e-4f;
+constexpr double kAgeSigma64 = 1e-9;
+
+template <typename T, bool PAIR> struct TGrad2 {
+    T t, dsig, dr0, dr1re, dr1im, dr2, iE1, iE2;
+};
+
+template <typename T, bool PAIR>
+__device__ void t_grad_between(const CosmoRec &r, T z1, T z2, TGrad2<T, PAIR> &o) {
+    const LaneConst<T> &k = lane_of<T>(r);
+    const bool zinf = z2 == Fp<T>::inf();
+    TArgs2<double, PAIR> ad;
+    t_args_between<double, PAIR>(r.d, (double)z1, zinf ? Fp<double>::inf() : (double)z2, ad);
+    const T V0 = T(ad.u.V0), va = T(ad.u.va), vb = T(ad.u.vb), W = T(ad.W), Qv = T(ad.Qv), S = T(ad.S);
+    const T dz = T(ad.dz), d2 = dz * dz;
+    SideG<T, PAIR> a, b;
+    side_at_g<T, PAIR>(k, z1, b);
+    if (zinf) side_inf_g<T, PAIR>(k, a);
+    else side_at_g<T, PAIR>(k, z2, a);
+    o.iE1 = k.pre * b.ie;
+    o.iE2 = k.pre * a.ie;
+    const Side<T, PAIR> &A_ = a.s, &B_ = b.s;
+    // the products making U_m: T1 led by the upper limit's sqrt(1 - sigma x), T2 by the lower's
+    T U0, T1_0, T2_0, U2 = T(0), T1_2 = T(0), T2_2 = T(0);
+    cx<T> U1, T1_1, T2_1;
+    if (PAIR) {
+        T1_0 = A_.t * A_.n0 * B_.n1abs;
+        T2_0 = B_.t * B_.n0 * A_.n1abs;
+        const cx<T> w = mkc(A_.n1re, A_.n1im) * mkc(B_.n1re, -B_.n1im);
+        T1_1 = w * (A_.t * B_.n0);
+        T2_1 = conj(w) * (B_.t * A_.n0);
+    } else {
+        T1_0 = A_.t * A_.n0 * B_.n1re * B_.n2;
+        T2_0 = B_.t * B_.n0 * A_.n1re * A_.n2;
+        T1_1 = mkc(A_.t * A_.n1re * B_.n0 * B_.n2, T(0));
+        T2_1 = mkc(B_.t * B_.n1re * A_.n0 * A_.n2, T(0));
+        T1_2 = A_.t * A_.n2 * B_.n0 * B_.n1re;
+        T2_2 = B_.t * B_.n2 * A_.n0 * A_.n1re;
+        U2 = T1_2 + T2_2;
+    }
+    U0 = T1_0 + T2_0;
+    U1 = T1_1 + T2_1;
+    T rf, rj, rdx, rdz;
+    cx<T> rdy;
+    rfjd_s<T, PAIR>(V0, va, vb, W, rf, rj, rdx, rdy, rdz);
+    T rc = T(0), dRC_S = T(0), dRC_Q = T(0);
+    if (!ad.rc_zero) {
+        rc = rc_r(S, Qv);
+        dRC_S = rd_last_x<T, false>(S, Qv, Qv) * T(-1.0 / 6.0); // -R_D(Q, Q, S)/6
+        dRC_Q = (T(-0.5) * rc - S * dRC_S) * Fp<T>::rcp(Qv);
+    }
+    const T c3 = d2 * T(1.0 / 3.0) * k.pre3;
+    // R_J partials in its three triple arguments (eq. 2.11); W - V0 = dz^2 C5 exactly
+    const T dJ0 = (rj - rdx) * Fp<T>::rcp(T(2) * d2 * k.c5);
+    cx<T> dJ1;
+    T dJ2 = T(0), sumVdJ;
+    if (PAIR) {
+        dJ1 = (mkc(rj, T(0)) - rdy) * crcp(mkc(W - va, -vb) * T(2));
+        sumVdJ = V0 * dJ0 + T(2) * (va * dJ1.re - vb * dJ1.im);
+    } else {
+        dJ1 = mkc((rj - rdy.re) * Fp<T>::rcp(T(2) * (W - va)), T(0));
+        dJ2 = (rj - rdz) * Fp<T>::rcp(T(2) * (W - vb));
+        sumVdJ = V0 * dJ0 + va * dJ1.re + vb * dJ2;
+    }
+    const T dJW = (T(-1.5) * rj - sumVdJ) * Fp<T>::rcp(W);
+    const T dRC_sum = dRC_S + dRC_Q;         // S = Q - dz^2 Rp moves with Q
+    const T qw = ad.rc_zero ? T(0) : Qv * Fp<T>::rcp(W); // dQ/dW
+    const T dB_dW = c3 * dJW + dRC_sum * qw;
+    const T dB_dV0 = c3 * dJ0 - k.sigma * rdx * T(1.0 / 6.0) + dB_dW;
+    const cx<T> dB_dV1 = dJ1 * c3 - rdy * (k.sigma * T(1.0 / 6.0));
+    const T dB_dV2 = PAIR ? T(0) : c3 * dJ2 - k.sigma * rdz * T(1.0 / 6.0);
+    // explicit dependence of P3, C5, Rp and Q on sigma and the roots
+    const T s = k.sigma;
+    const cx<T> om1 = mkc(T(1) - s * k.r1re, -s * k.r1im);
+    const cx<T> om2 = PAIR ? conj(om1) : mkc(T(1) - s * k.r2, T(0));
+    const T om0 = T(1) - s * k.r0;
+    const cx<T> r1 = mkc(k.r1re, k.r1im);
+    const cx<T> r2 = PAIR ? conj(r1) : mkc(k.r2, T(0));
+    const T om12 = (om1 * om2).re;
+    const T r1o2_r2o1 = (r1 * om2).re + (r2 * om1).re;
+    const T dP3_ds = -(k.r0 * om12 + om0 * r1o2_r2o1);
+    const T dC5_ds = -k.r0 * r1o2_r2o1;
+    const T dQ_ds = ad.rc_zero ? T(0) : Qv * (B_.x * b.it2 + A_.x * a.it2);
+    const T d23 = d2 * T(1.0 / 3.0);
+    T dsig = d23 * rj * dP3_ds + dB_dW * d2 * dC5_ds + dRC_sum * dQ_ds + rf;
+    T dr0 = d23 * rj * (-s * om12) + dB_dW * d2 * om12 + dRC_S * (-d2 * (r1 * r2).re);
+    cx<T> dr1 = (om0 * om2 * (-s)) * (d23 * rj) + om2 * (-s * k.r0) * (dB_dW * d2) + (r2 * k.r0) * (-d2 * dRC_S);
+    T dr2 = PAIR ? T(0)
+                 : d23 * rj * (-s * om0 * om1.re) + dB_dW * d2 * (-s * om1.re * k.r0) + dRC_S * (-d2 * k.r0 * k.r1re);
+    // through the Carlson arguments V_m = U_m^2, with both limits' square roots
+    const T G0 = dB_dV0 * T(2) * U0;
+    const T a0 = G0 * T1_0, b0 = G0 * T2_0;
+    if (PAIR) {
+        const cx<T> G1 = dB_dV1 * U1 * T(2);
+        const cx<T> a1 = G1 * T1_1, b1 = G1 * T2_1;
+        const T As = a0 + T(2) * a1.re, Bs = b0 + T(2) * b1.re;
+        dsig += T(-0.5) * (A_.x * As * a.it2 + B_.x * Bs * b.it2);
+        dr0 += T(-0.5) * ((a0 + Bs - b0) * a.i0 + (b0 + As - a0) * b.i0);
+        dr1 = dr1 + ((a1 + Bs - b1) * mkc(a.i1re, a.i1im) + (b1 + As - a1) * mkc(b.i1re, b.i1im)) * T(-0.5);
+    } else {
+        const T G1 = dB_dV1.re * T(2) * U1.re, G2 = dB_dV2 * T(2) * U2;
+        const T a1 = G1 * T1_1.re, b1 = G1 * T2_1.re, a2 = G2 * T1_2, b2 = G2 * T2_2;
+        const T As = a0 + a1 + a2, Bs = b0 + b1 + b2;
+        dsig += T(-0.5) * (A_.x * As * a.it2 + B_.x * Bs * b.it2);
+        dr0 += T(-0.5) * ((a0 + Bs - b0) * a.i0 + (b0 + As - a0) * b.i0);
+        dr1.re += T(-0.5) * ((a1 + Bs - b1) * a.i1re + (b1 + As - a1) * b.i1re);
+        dr2 += T(-0.5) * ((a2 + Bs - b2) * a.i2 + (b2 + As - a2) * b.i2);
+    }
+    const T scale = k.pre * T(2) * dz;
+    o.t = scale * (c3 * rj + rc + s * rf);
+    o.dsig = scale * dsig;
+    o.dr0 = scale * dr0;
+    o.dr1re = scale * dr1.re;
+    o.dr1im = scale * dr1.im;
+    o.dr2 = scale * dr2;
+}
+
 // Parameter derivatives of the time coordinate between two redshifts, t/(1/H0) =
 // int_{z1}^{z2} dz / ((1 + z) E(z)) (eq. 2.4), by the Leibniz rule in s = (1 + z)^(-1/2)
 // (a = s^2 = 1/(1 + z)): the integral becomes int_{s2}^{s1} 2 s^3 ds / sqrt(R(s^2)) with
@@ -400,9 +533,25 @@ __device__ __forceinline__ void lane_grad_between(const CosmoRec &r, T z1, T z2,
     const LaneConst<T> &k = lane_of<T>(r);
     const bool fp32 = sizeof(T) == 4;
     const bool zinf = z2 == Fp<T>::inf();
+    if (KIND == COSMO_T && !(direct_mode(KIND, r, fp32) || (zinf && !(-k.sigma >= T(fp32 ? kAgeSigma32 : kAgeSigma64))))) {
+        // time coordinate: eq. 3.8 with both limits through the Carlson derivatives
+        LaneGrad<T> &g = o.g;
+        TGrad2<T, PAIR> tg;
+        t_grad_between<T, PAIR>(r, z1, z2, tg);
+        g.quad = false;
+        g.p[0] = tg.t; g.p[1] = tg.dsig; g.p[2] = tg.dr0; g.p[3] = tg.dr1re; g.p[4] = PAIR ? tg.dr1im : tg.dr2;
+        g.val = k.th * tg.t;
+        g.s = k.th;
+        g.dok = T(0);
+        g.dh = -g.val * k.hinv;
+        o.dz1 = -k.th * Fp<T>::rcp(T(1) + z1) * tg.iE1;
+        g.dz = zinf ? T(0) : k.th * Fp<T>::rcp(T(1) + z2) * tg.iE2;
+        return;
+    }
     if (KIND == COSMO_T) {
-        // time coordinate: the value by eq. 3.8 with both limits, the parameter
-        // derivatives by the Leibniz quadrature in s = (1 + z)^(-1/2) (finite to z2 = inf)
+        // near-multiple roots, and the age without radiation: the value by eq. 3.8 with
+        // both limits, the parameter derivatives by the Leibniz quadrature in
+        // s = (1 + z)^(-1/2) (finite to z2 = inf)
         LaneGrad<T> &g = o.g;
         T q[3];
         gl_time_between<T, PAIR>(k, z1, z2, zinf, q);

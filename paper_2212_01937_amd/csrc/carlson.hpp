@@ -219,6 +219,21 @@ template <typename T> __device__ __forceinline__ T rc1_r(T e) {
     return rc_r(T(1), T(1) + e);
 }
 
+// d R_C(1, 1 + e) / de: the derivative of the series above for small |e|, else the
+// identity f'(e) = (1/(1 + e) - f(e)) / (2e) of f(e) = arctan(sqrt e)/sqrt e.
+template <typename T> __device__ __forceinline__ T rc1_dr(T e, T f) {
+    if (Fp<T>::abs(e) < Fp<T>::rc_series_max) {
+        T s = T(0), t = T(-1);
+#pragma unroll
+        for (int n = 1; n < Fp<T>::rc_series_terms; ++n) {
+            s += t * T(double(n) / (2 * n + 1));
+            t *= -e;
+        }
+        return s;
+    }
+    return (Fp<T>::rcp(T(1) + e) - f) * Fp<T>::rcp(T(2) * e);
+}
+
 // ---------------------------------------------------------------- structured
 // One duplication step on a structured triple; returns lambda.  For PAIR also
 // returns Re sqrt(y) and |y| (reused by R_J's d_m).
@@ -457,6 +472,114 @@ __device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
     rdx = T(3) * accx + tx;
     rdy = accy * T(3) + ty;
     rdz = T(3) * accz + tz;
+}
+
+// R_F(x, y, z), R_J(x, y, z, p) and jx = dR_J/dx from one duplication sequence (p real
+// > 0).  The derivative is carried through every step of the recursion (forward
+// mode: the iterates' derivatives in the initial x, the R_C terms' and the fifth-order
+// tail's), so it stays accurate where p is close to x -- where the form that eq. 2.11
+// gives, (R_J - R_D(y, z, x)) / (2 (p - x)), cancels.  Along the sequence the
+// derivatives of y, z and p are equal (each moves by lambda/4 per step; for PAIR the
+// imaginary part b is not moved by lambda), so two tracks suffice: dx and dy.  The
+// J criterion stops at taujx < tau5: the derivative of the truncated expansion loses
+// one order of the deviation.
+template <typename T, bool PAIR>
+__device__ void rfjx_s(T x, T a, T b, T p, T &rf, T &rj, T &jx) {
+    const T AF0 = mean3<T, PAIR>(x, a, b);
+    const T AJ0 = (T(3) * AF0 + T(2) * p) * T(0.2);
+    const T x0 = x, a0 = a, b0 = b, p0 = p;
+    const T QF = spread3<T, PAIR>(AF0, x, a, b);
+    const T QJ = tmax(spread3<T, PAIR>(AJ0, x, a, b), spread1<T, PAIR>(AJ0 - p));
+    const T pyz = PAIR ? (p - a) * (p - a) + b * b : (p - a) * (p - b);
+    const T delta = (p - x) * pyz, ddelta = -pyz;
+    T AF = AF0, AJ = AJ0, f = T(1), acc = T(0), dacc = T(0);
+    T dx = T(1), dy = T(0), dAJ = T(0.2);
+    for (int m = 0; m < kMaxDup && (spread_above<T, PAIR>(QF, f, Fp<T>::tau7, AF) ||
+                                   spread_above<T, PAIR>(QJ, f, Fp<T>::taujx, AJ)); ++m) {
+        const T rsx = Fp<T>::rsqrt(x), rsp = Fp<T>::rsqrt(p);
+        const T sx = x * rsx, sp = p * rsp;
+        const T dsx = T(0.5) * dx * rsx, dsp = T(0.5) * dy * rsp;
+        T lam, dlam, d, dd;
+        if (PAIR) {
+            T r;
+            const T syr = csqrt_re(a, b, r);
+            const T ir = Fp<T>::rcp(r);
+            lam = T(2) * sx * syr + r;
+            const T dsyr = T(0.5) * dy * syr * ir, dr = a * dy * ir;
+            dlam = T(2) * (dsx * syr + sx * dsyr) + dr;
+            const T g2 = p + T(2) * sp * syr + r;
+            const T dg2 = dy + T(2) * (dsp * syr + sp * dsyr) + dr;
+            d = (sp + sx) * g2;
+            dd = (dsp + dsx) * g2 + (sp + sx) * dg2;
+        } else {
+            const T rsy = Fp<T>::rsqrt(a), rsz = Fp<T>::rsqrt(b);
+            const T sy = a * rsy, sz = b * rsz;
+            const T dsy = T(0.5) * dy * rsy, dsz = T(0.5) * dy * rsz;
+            lam = sx * (sy + sz) + sy * sz;
+            dlam = dsx * (sy + sz) + sx * (dsy + dsz) + dsy * sz + sy * dsz;
+            const T py = sp + sy, pz = sp + sz, px = sp + sx;
+            d = px * py * pz;
+            dd = (dsp + dsx) * py * pz + px * ((dsp + dsy) * pz + py * (dsp + dsz));
+        }
+        const T rdd = Fp<T>::rcp(d);
+        const T f3 = f * f * f;
+        const T e = delta * rdd * rdd * f3;
+        const T de = f3 * rdd * rdd * (ddelta - T(2) * delta * dd * rdd);
+        const T rc = rc1_r(e);
+        acc += f * rc * rdd;
+        dacc += f * (rc1_dr(e, rc) * de * rdd - rc * rdd * rdd * dd);
+        x = (x + lam) * T(0.25);
+        a = (a + lam) * T(0.25);
+        b = PAIR ? b * T(0.25) : (b + lam) * T(0.25);
+        p = (p + lam) * T(0.25);
+        AF = (AF + lam) * T(0.25);
+        AJ = (AJ + lam) * T(0.25);
+        dx = (dx + dlam) * T(0.25);
+        dy = (dy + dlam) * T(0.25);
+        dAJ = (dAJ + dlam) * T(0.25);
+        f *= T(0.25);
+    }
+    {
+        const T raF = Fp<T>::rsqrt(AF);
+        const T gF = f * (raF * raF);
+        const T X = (AF0 - x0) * gF;
+        T s, q;
+        yz_sym<T, PAIR>(AF0, a0, b0, gF, s, q);
+        rf = rf_tail(q - X * X, X * q) * raF;
+    }
+    const T ra = Fp<T>::rsqrt(AJ);
+    const T iA = ra * ra;
+    const T g = f * iA, dg = -g * dAJ * iA, dra = T(-0.5) * ra * dAJ * iA;
+    const T X = (AJ0 - x0) * g, dX = T(-0.8) * g + (AJ0 - x0) * dg;
+    T s, q, ds, dq;
+    if (PAIR) {
+        const T u = (AJ0 - a0) * g, v = b0 * g;
+        const T du = T(0.2) * g + (AJ0 - a0) * dg, dv = b0 * dg;
+        s = T(2) * u; q = u * u + v * v;
+        ds = T(2) * du; dq = T(2) * (u * du + v * dv);
+    } else {
+        const T Y = (AJ0 - a0) * g, Z = (AJ0 - b0) * g;
+        const T dY = T(0.2) * g + (AJ0 - a0) * dg, dZ = T(0.2) * g + (AJ0 - b0) * dg;
+        s = Y + Z; q = Y * Z;
+        ds = dY + dZ; dq = dY * Z + Y * dZ;
+    }
+    const T P = (AJ0 - p0) * g, dP = T(0.2) * g + (AJ0 - p0) * dg;
+    const T sym2 = X * s + q, xyz = X * q, P2 = P * P;
+    const T dsym2 = dX * s + X * ds + dq, dxyz = dX * q + X * dq, dP2 = T(2) * P * dP;
+    const T E2 = sym2 - T(3) * P2, dE2 = dsym2 - T(3) * dP2;
+    const T P3 = P2 * P, dP3 = dP2 * P + P2 * dP;
+    const T E3 = xyz + T(2) * E2 * P + T(4) * P3;
+    const T dE3 = dxyz + T(2) * (dE2 * P + E2 * dP) + T(4) * dP3;
+    const T B4 = T(2) * xyz + E2 * P + T(3) * P3;
+    const T dB4 = T(2) * dxyz + dE2 * P + E2 * dP + T(3) * dP3;
+    const T E4 = B4 * P, dE4 = dB4 * P + B4 * dP;
+    const T E5 = xyz * P2, dE5 = dxyz * P2 + xyz * dP2;
+    const T tail = rj_tail(E2, E3, E4, E5);
+    const T dtail = dE2 * (T(-3.0 / 14.0) + T(9.0 / 44.0) * E2 - T(9.0 / 52.0) * E3) +
+                    dE3 * (T(1.0 / 6.0) - T(9.0 / 52.0) * E2) - T(3.0 / 22.0) * dE4 + T(3.0 / 26.0) * dE5;
+    rj = tail * g * ra + T(6) * acc;
+    jx = dtail * g * ra + tail * (dg * ra + g * dra) + T(6) * dacc;
+    if (!(p0 > T(0))) rj = jx = Fp<T>::nan();
 }
 
 // R_F, R_J(x, y, z, p) and the R_D(., ., x_k) of the triple, from one duplication

@@ -40,6 +40,7 @@ template <> struct Fp<float> {
     // 7th-order tails (R_F, R_C): remainder ~ tau^8 / 4; 5th-order (R_D, R_J): ~ tau^6.
     static constexpr float tau7 = 0.136f;
     static constexpr float tau5 = 0.070f;
+    static constexpr float taujx = 0.018f;  // dR_J/dx (rfjx_s): one duplication beyond tau5
     static constexpr float rc_series_max = 0.02f; // |e| below which R_C(1, 1+e) uses its series
     static constexpr int rc_series_terms = 5;
 };
@@ -74,6 +75,7 @@ template <> struct Fp<double> {
     static __device__ __forceinline__ double inf() { return __builtin_inf(); }
     static constexpr double tau7 = 0.0121;
     static constexpr double tau5 = 0.0028;
+    static constexpr double taujx = 0.0007;
     static constexpr double rc_series_max = 0.01;
     static constexpr int rc_series_terms = 9;
 };

@@ -59,7 +59,12 @@ __device__ __forceinline__ T eval_kind(const CosmoRec &r, T z, bool &used_gl) {
     const LaneConst<T> &k = lane_of<T>(r);
     used_gl = false;
     if (KIND == COSMO_T) return k.th * t_hat<T, PAIR>(r, z);
-    if (KIND == COSMO_X) return k.dh * x_hat<T, PAIR>(k, z, used_gl);
+    if (KIND == COSMO_X) {
+        int route;
+        const T v = k.dh * x_hat<T, PAIR>(r, z, route);
+        used_gl = route == kXRouteQuad;
+        return v;
+    }
     T chi = chi_hat<T, PAIR>(k, z);
     T a, b, c, d;
     return observable<T>(KIND, k, chi, z, T(0), a, b, c, d);
@@ -77,21 +82,66 @@ __global__ __launch_bounds__(kBlock) void k_forward(const CosmoRec *__restrict__
     const int64_t c0 = tile * ct;
     const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
     const T zshared = (zstride == 0 && active) ? z[i] : T(0);
+    const uint32_t i32 = (uint32_t)i; // n_z < 2^31 (checked on the host)
     for (int64_t c = c0; c < c1; ++c) {
         const CosmoRec &r = recs[c];
         if (!active) continue;
-        const T zz = zstride == 0 ? zshared : z[c * zstride + i];
+        const T zz = zstride == 0 ? zshared : (z + c * zstride)[i32];
         T v;
         bool used_gl = false;
         if (!r.valid) v = Fp<T>::nan();
         else if (r.pair) v = eval_kind<T, KIND, true>(r, zz, used_gl);
         else v = eval_kind<T, KIND, false>(r, zz, used_gl);
-        out[c * n_z + i] = v;
+        __builtin_nontemporal_store(v, (out + c * n_z) + i32);
         if (KIND == COSMO_X && info) {
             unsigned long long m = __ballot(used_gl);
             if (m && (int)__lane_id() == __ffsll((long long)m) - 1) atomicOr(info + c, COSMO_INFO_X_QUADRATURE);
         }
     }
+}
+
+// Route counts (cosmo_route_counts): per lane, the route its value takes (X: x_hat's
+// route; the other kinds have one) and whether its adjoint takes the Leibniz quadrature,
+// decided by the functions the forward and adjoint kernels branch on; per wave the
+// popcounts of their ballots, one 64-bit atomic add per wave and count.
+template <typename T, int KIND, bool PAIR>
+__device__ __forceinline__ void route_lane(const CosmoRec &r, T z, bool act, unsigned long long *cnt) {
+    int vr = kXRouteCarlson;
+    if (KIND == COSMO_X && act) (void)x_hat<T, PAIR>(r, z, vr);
+    const bool aq = act && adjoint_quadrature_lane<T>(KIND, r, z);
+    const unsigned long long n[4] = {(unsigned long long)__popcll(__ballot(act && vr == kXRouteCarlson)),
+                                     (unsigned long long)__popcll(__ballot(act && vr == kXRouteFp64)),
+                                     (unsigned long long)__popcll(__ballot(act && vr == kXRouteQuad)),
+                                     (unsigned long long)__popcll(__ballot(aq))};
+    if (__lane_id() == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (n[q]) atomicAdd(cnt + q, n[q]);
+    }
+}
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(kBlock) void k_routes(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
+                                                    const T *__restrict__ z, int64_t n_z, int64_t zstride,
+                                                    unsigned long long *__restrict__ counts, int ct, int64_t nzb) {
+    const int64_t b = blockIdx.x;
+    const int64_t tile = b / nzb, zb = b - tile * nzb;
+    const int64_t i = zb * kBlock + threadIdx.x;
+    const bool act = i < n_z;
+    const int64_t c0 = tile * ct;
+    const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
+    for (int64_t c = c0; c < c1; ++c) {
+        const CosmoRec &r = recs[c];
+        if (!r.valid) continue;
+        const T zz = act ? z[c * zstride + i] : T(1);
+        if (r.pair) route_lane<T, KIND, true>(r, zz, act, counts + 4 * c);
+        else route_lane<T, KIND, false>(r, zz, act, counts + 4 * c);
+    }
+}
+
+template <typename T> __global__ void k_fill_zero_u64(T *__restrict__ p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = T(0);
 }
 
 // Observables between two redshifts (between.hpp): lane i of a cosmology evaluates the
@@ -134,11 +184,12 @@ constexpr int kAccLoss = 10;
 // LIKE (Gaussian likelihood): cin is the observed value, the residual res = obs - out
 // adds -ivar res^2 / 2 to the loss slot and the cotangent is wc ivar res;
 // otherwise cin is the cotangent.
-template <typename T, int KIND, bool PAIR, bool LIKE>
+template <typename T, int KIND, bool PAIR, bool LIKE, int ROUTE = 0>
 __device__ __forceinline__ void vjp_lane(const CosmoRec &r, T z, T cin, T ivar, T wc, T acc[kAcc], T &gz, T &val,
                                          bool &used_gl) {
     LaneGrad<T> o;
-    lane_grad<T, KIND, PAIR>(r, z, o, used_gl);
+    if (ROUTE == 1) lane_grad_small<T, KIND, PAIR>(r, z, o);
+    else lane_grad<T, KIND, PAIR>(r, z, o, used_gl);
     val = o.val;
     T cot = cin;
     if (LIKE) {
@@ -216,11 +267,13 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 // dynamically indexed register arrays.  Both partials are stored in the lane
 // precision (they are sums in that precision already) and summed in FP64 by
 // k_finalize_params and k_reduce_gz.
+//
+// General loop: every route of lane_grad (near-multiple-root cosmologies, X).
 template <typename T, int KIND, bool PAIR, int ZPT, bool LIKE>
-__device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T *__restrict__ z, int64_t n_z,
-                                          int64_t zstride, const T *__restrict__ cot, const T *__restrict__ ivar,
-                                          T wc, int64_t base, T acc[kAcc], T *gzl, T *__restrict__ gz_out,
-                                          T *__restrict__ out, int32_t *__restrict__ info) {
+__device__ __forceinline__ void vjp_cosmo_general(const CosmoRec &r, int64_t c, const T *__restrict__ z, int64_t n_z,
+                                                  int64_t zstride, const T *__restrict__ cot, const T *__restrict__ ivar,
+                                                  T wc, int64_t base, T acc[kAcc], T *gzl, T *__restrict__ gz_out,
+                                                  T *__restrict__ out, int32_t *__restrict__ info) {
 #pragma unroll 1
     for (int k = 0; k < ZPT; ++k) {
         const int64_t i = base + (int64_t)k * kBlock;
@@ -245,11 +298,89 @@ __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T 
     }
 }
 
+// The root-chain lanes (lane_grad_root) run in a loop of their own, which touches only
+// the slots that route writes (0..6, and the loss); FP32 lanes below kSmallZ32 are
+// marked and run afterwards in a second pass that only waves holding such lanes enter
+// (the redshifts of a row are typically sorted, so those lanes gather in few waves).
+// Near-multiple-root cosmologies (uniform per cosmology) and X take the general loop.
+template <typename T, int KIND, bool PAIR, int ZPT, bool LIKE>
+__device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T *__restrict__ z, int64_t n_z,
+                                          int64_t zstride, const T *__restrict__ cot, const T *__restrict__ ivar,
+                                          T wc, int64_t base, T acc[kAcc], T *gzl, T *__restrict__ gz_out,
+                                          T *__restrict__ out, int32_t *__restrict__ info) {
+    constexpr bool fp32 = sizeof(T) == 4;
+    if (KIND == COSMO_X || direct_mode(KIND, r, fp32)) {
+        vjp_cosmo_general<T, KIND, PAIR, ZPT, LIKE>(r, c, z, n_z, zstride, cot, ivar, wc, base, acc, gzl, gz_out, out,
+                                                   info);
+        return;
+    }
+    // row pointers of this cosmology (uniform) and 32-bit lane offsets (n_z < 2^31 is
+    // checked on the host): the loads and stores take a scalar base and a vector offset
+    const uint32_t i0 = (uint32_t)base, nz = (uint32_t)n_z;
+    const T *__restrict__ zr = z + c * zstride;
+    const T *__restrict__ cr = LIKE ? cot + c * zstride : cot + c * n_z;
+    const T *__restrict__ vr = LIKE ? ivar + c * zstride : nullptr;
+    T *__restrict__ orow = out ? out + c * n_z : nullptr;
+    T *__restrict__ grow = gz_out ? gz_out + c * n_z : nullptr;
+    uint32_t deferred = 0;
+#pragma unroll 1
+    for (int k = 0; k < ZPT; ++k) {
+        const uint32_t i = i0 + (uint32_t)(k * kBlock);
+        if (i >= nz) break;
+        const T zz = zr[i];
+        if (small_z_lane<T>(zz)) {
+            deferred |= 1u << k;
+            continue;
+        }
+        RootGrad<T> o;
+        lane_grad_root<T, KIND, PAIR>(r, zz, o);
+        T cv;
+        if (LIKE) {
+            const T res = cr[i] - o.val;
+            const T rv = res * vr[i];
+            acc[kAccLoss] += T(-0.5) * res * rv;
+            cv = wc * rv;
+        } else {
+            cv = __builtin_nontemporal_load(cr + i);
+        }
+        const T w = cv * o.s;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[q] += w * o.p[q];
+        acc[5] += cv * o.dok;
+        acc[6] += cv * o.dh;
+        const T gz = cv * o.dz;
+        if (orow) __builtin_nontemporal_store(o.val, orow + i);
+        if (zstride != 0) {
+            if (grow) grow[i] = gz;
+        } else {
+            gzl[k * kBlock + threadIdx.x] += gz;
+        }
+    }
+    if (fp32 && __ballot(deferred != 0)) {
+#pragma unroll 1
+        for (int k = 0; k < ZPT; ++k) {
+            if (!(deferred & (1u << k))) continue;
+            const int64_t i = base + (int64_t)k * kBlock;
+            const T zz = z[c * zstride + i];
+            T gz, val;
+            bool used_gl = false;
+            if (LIKE) vjp_lane<T, KIND, PAIR, true, 1>(r, zz, cot[c * zstride + i], ivar[c * zstride + i], wc, acc, gz, val, used_gl);
+            else vjp_lane<T, KIND, PAIR, false, 1>(r, zz, cot[c * n_z + i], T(0), T(0), acc, gz, val, used_gl);
+            if (out) out[c * n_z + i] = val;
+            if (zstride != 0) {
+                if (gz_out) gz_out[c * n_z + i] = gz;
+            } else {
+                gzl[k * kBlock + threadIdx.x] += gz;
+            }
+        }
+    }
+}
+
 // Occupancy: the FP32 comoving-distance-family adjoint fits 80 VGPRs, six waves per
 // SIMD (measured 6% faster than the five its unconstrained allocation gives); the
-// others keep the compiler's allocation.
+// others (T, and X with its FP64 geometry) keep the compiler's allocation.
 template <typename T, int KIND> constexpr int adjoint_min_waves() {
-    return (sizeof(T) == 4 && KIND != COSMO_T) ? 6 : 1;
+    return (sizeof(T) == 4 && KIND != COSMO_T && KIND != COSMO_X) ? 6 : 1;
 }
 
 template <typename T, int KIND, int ZPT, bool LIKE>
@@ -815,6 +946,30 @@ int launch_forward(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, 
 }
 
 template <typename T>
+int launch_routes(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int64_t n_z, int64_t zstride,
+                  unsigned long long *counts, hipStream_t s) {
+    const unsigned nb0 = (unsigned)((4 * n_cosmo + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_fill_zero_u64<unsigned long long>, dim3(nb0), dim3(kBlock), 0, s, counts, 4 * n_cosmo);
+    if (hipGetLastError() != hipSuccess) return COSMO_E_HIP;
+    if (n_z == 0) return COSMO_OK;
+    Tiling t = tiling(n_cosmo, n_z);
+    dim3 grid((unsigned)t.nblocks), block(kBlock);
+#define COSMO_RT(K) hipLaunchKernelGGL((k_routes<T, K>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, counts, t.ct, t.nzb)
+    switch (kind) {
+    case COSMO_DC: COSMO_RT(COSMO_DC); break;
+    case COSMO_DM: COSMO_RT(COSMO_DM); break;
+    case COSMO_DL: COSMO_RT(COSMO_DL); break;
+    case COSMO_MU: COSMO_RT(COSMO_MU); break;
+    case COSMO_T: COSMO_RT(COSMO_T); break;
+    case COSMO_X: COSMO_RT(COSMO_X); break;
+    case COSMO_DA: COSMO_RT(COSMO_DA); break;
+    case COSMO_VC: COSMO_RT(COSMO_VC); break;
+    }
+#undef COSMO_RT
+    return hipGetLastError() == hipSuccess ? COSMO_OK : COSMO_E_HIP;
+}
+
+template <typename T>
 int launch_between(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z1, const T *z2, int64_t n_z,
                    int64_t zstride, T *out, hipStream_t s) {
     Tiling t = tiling(n_cosmo, n_z);
@@ -976,6 +1131,7 @@ int check_grid(int64_t n_cosmo, int64_t n_z) {
     Tiling t = tiling(n_cosmo, n_z);  // the forward grid is the larger one
     if (t.nblocks > 0x7FFFFFFFll) return COSMO_E_ARG;
     if (n_cosmo > 0x7FFFFFFFll) return COSMO_E_ARG;
+    if (n_z > 0x7FFFFFFFll - 8 * kBlock) return COSMO_E_ARG; // 32-bit redshift offsets in the kernels
     return COSMO_OK;
 }
 
@@ -1048,6 +1204,29 @@ int cosmo_distance(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_
     if (dt == COSMO_F32)
         return launch_forward<float>(kind, recs, n_cosmo, (const float *)z, n_z, z_cosmo_stride, (float *)out, info, s);
     return launch_forward<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, (double *)out, info, s);
+}
+
+int cosmo_route_counts(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo, const void *z,
+                       int64_t n_z, int64_t z_cosmo_stride, int64_t *counts, void *workspace,
+                       size_t workspace_bytes, void *stream) {
+    if (!valid_kind(kind)) return COSMO_E_KIND;
+    if (!valid_dtype(dt)) return COSMO_E_DTYPE;
+    if (n_cosmo < 0 || n_z < 0 || z_cosmo_stride < 0) return COSMO_E_ARG;
+    if (n_cosmo > 0 && (!params || !counts)) return COSMO_E_ARG;
+    if (n_cosmo > 0 && n_z > 0 && !z) return COSMO_E_ARG;
+    if (check_grid(n_cosmo, n_z) != COSMO_OK) return COSMO_E_ARG;
+    if (n_cosmo == 0) return COSMO_OK;
+    hipStream_t s = (hipStream_t)stream;
+    WsLayout L = ws_layout(n_cosmo, n_z);
+    Workspace ws;
+    int rc = ws.acquire(workspace, workspace_bytes, L.pacc, s);
+    if (rc != COSMO_OK) return rc;
+    CosmoRec *recs = (CosmoRec *)ws.ptr;
+    rc = launch_setup(params, n_cosmo, recs, nullptr, s);
+    if (rc != COSMO_OK) return rc;
+    unsigned long long *cnt = (unsigned long long *)counts;
+    return dt == COSMO_F32 ? launch_routes<float>(kind, recs, n_cosmo, (const float *)z, n_z, z_cosmo_stride, cnt, s)
+                           : launch_routes<double>(kind, recs, n_cosmo, (const double *)z, n_z, z_cosmo_stride, cnt, s);
 }
 
 int cosmo_distance_between(cosmo_kind kind, cosmo_dtype dt, const double *params, int64_t n_cosmo,

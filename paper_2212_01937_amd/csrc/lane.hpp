@@ -297,71 +297,154 @@ __device__ void gl_integral(const LaneConst<Q> &k, Q z, int power, bool grad, Q 
     if (grad) { gth[0] = g0 * hh; gth[1] = g1 * hh; gth[2] = g2 * hh; }
 }
 
-// X / (c/H0): eq. B.3 (Or = 0) or eq. 3.9, else the quadrature route.
-// Returns the value; sets used_gl when the quadrature route was taken.
-template <typename T, bool PAIR> __device__ T x_hat(const LaneConst<T> &k, T z, bool &used_gl) {
-    used_gl = false;
-    const bool cubic = (k.sigma == T(0));
-    const bool fp32 = sizeof(T) == 4;
-    if (!cubic && fp32) { // eq. 3.9 cancels by ~|rho_l| >> 1/eps_32: quadrature
-        used_gl = true;
-        T v, gd[3];
-        gl_integral<T, PAIR>(k, z, 2, false, v, gd);
-        return v;
-    }
-    Geo<T, PAIR> g;
-    build_u<T, PAIR>(k, z, g);
-    const T V0 = g.U0 * g.U0;
-    const T z2 = z * z;
-    const T x2 = T(1) + z;
-    T f2, f1;
-    sqrtQ<T, PAIR>(k, g, f2, f1);
+// Absorption distance (eqs. 3.9, B.3): X / (c/H0) = pre * z * B, returned as B together
+// with the size M of its terms for the rounding check.
+//
+// Eq. 3.9 in the normalised form (i = 0 the real root of Q, (j, k) = slots 1, 2, l the
+// radiation root) reads B = A + t2 + L (B1 - B2) with L = -1/sigma = |rho_l|:
+//   B1 = (1 - s r1)(1 - s r2) [ (dz^2/3) d01 d02 R_D(U1^2, U2^2, U0^2) + X0 Y0 / (Xt Yt U0) ]
+//   B2 = (1 + s S3) [ (dz^2/3) d01 d02 (1 - s r0) R_J(U^2, p) + R_C(q - s dz^2, q) ]
+// with p = U0^2 + s dz^2 d01 d02 (the paper's u_i0^2 in these units) and q = p/(X0 Y0)^2.
+// B1 and B2 agree to O(sigma), so the printed form loses ~|rho_l| ~ Om/Or digits.  It
+// is rearranged so that the 1/sigma cancels analytically:
+//  * R_D(U1^2, U2^2, U0^2) = R_J(U^2, U0^2), and with F(w) = R_J(U^2, w) the exact
+//    divided difference F(U0^2) - F(p) = 2 (U0^2 - p) dR_J/dx (U^2, p) (from R_J's
+//    integral representation; x its first argument), where U0^2 - p = -s dz^2 d01 d02:
+//    that pair of terms becomes 2 (dz^2/3) d01 d02 (1 - s r1)(1 - s r2) dz^2 d01 d02
+//    dR_J/dx, the derivative from rfjx_s, plus e1 (dz^2/3) d01 d02 R_J(U^2, p) with
+//    e1 = [(1 - s r1)(1 - s r2) - (1 + s S3)(1 - s r0)] / s, a polynomial in sigma;
+//  * R_C(q(1 - tau), q) = q^(-1/2) sum_n c_n tau^n, tau = s dz^2/q, c_n = (1/2)_n^2 /
+//    ((3/2)_n n!) (R_C's hypergeometric series), whose n >= 1 part carries a factor
+//    sigma; the remaining algebraic pair [(1 - s r1)(1 - s r2) / (Xt Yt U0) - (1 + s S3)
+//    / sqrt(p)] / sigma is formed from sqrt(p) - U0 = s dz^2 d01 d02 / (sqrt(p) + U0) and
+//    (Xt - 1)/s = -x2/(Xt + 1), (Yt - 1)/s = -1/(Yt + 1).
+// Every term of the result is a regular function of sigma; at sigma = 0 it is the value
+// of eq. B.3 (X is continuous in Or), so one form serves both degrees.  It is used
+// while |tau| is small enough for the series (there the printed form cancels by
+// ~1/(|s| x2) >= 1/tau_max); beyond, eq. 3.9 is evaluated as printed, its R_D from the
+// same duplication sequence as F(U0^2) = F(p) + 2 (U0^2 - p) dR_J/dx.  Both are the
+// paper's Carlson reduction; only the order of the algebra differs.  A milder
+// cancellation at small z between terms of size ~r0^2 remains in either form (up to
+// ~20 on the non-flat workload): M / |B| is returned for the caller's check.
+template <typename Q> struct XSeries;
+template <> struct XSeries<float> {
+    static constexpr int n = 8;           // c_1 .. c_8: truncation below 4e-9 relative at |tau| = tau_max
+    static constexpr float tau_max = 0.125f;
+};
+template <> struct XSeries<double> {
+    static constexpr int n = 16;          // below 1e-17
+    static constexpr double tau_max = 0.1;
+};
+constexpr double rc_series_coef(int n) { // c_n = (1/2)_n^2 / ((3/2)_n n!)
+    double c = 1.0;
+    for (int k = 0; k < n; ++k) c = c * (k + 0.5) * (k + 0.5) / ((k + 1.5) * (k + 1.0));
+    return c;
+}
+
+// Q: precision of the Carlson integrals; G: precision of the geometry, the algebraic
+// terms and the sum (the FP32 path forms them in FP64 and rounds the Carlson arguments
+// once, as for the time coordinate: the algebraic terms are the largest, and FP32
+// products of square roots would put a few ulp of error into each).
+// The R_F term is returned apart (t2 = xc2 R_F with its FP64 Carlson arguments): at small
+// z it is one of the two largest terms, so an FP32 lane whose terms cancel can refine it
+// alone in FP64.
+template <typename G> struct XRf {
+    G V0, va, vb, t2;
+};
+template <typename Q, typename G, bool PAIR> __device__ G x_terms(const CosmoRec &r, G z, G &mag, XRf<G> &xr) {
+    const LaneConst<G> &k = lane_of<G>(r);
+    Geo<G, PAIR> g;
+    build_u<G, PAIR>(k, z, g);
+    const G s = k.sigma;
+    const G V0 = g.U0 * g.U0;
+    const G z2 = z * z;
+    const G x2 = G(1) + z;
+    const G cc = z2 * G(1.0 / 3.0) * k.d0102;
+    const G p = V0 + s * z2 * k.d0102;
+    const G iq = g.X02 * k.w0 * Fp<G>::rcp(p); // 1/q
+    const G tau = s * z2 * iq;
+    const G xy = g.X0 * k.y0;
+    G f2, f1;
+    sqrtQ<G, PAIR>(k, g, f2, f1);
     // (Q(x2) - Q(1))/dz as a divided difference (no cancellation at small z)
-    const T DQ = T(3) + z * (T(3) + z) + k.q2 * (T(2) + z) + k.q1;
-    const T rd = rd_last_x<T, PAIR>(V0, g.va, g.vb); // R_D(U_1^2, U_2^2, U_0^2)
-    if (cubic) {
-        // eq. B.3 with i = 0:  (2 dz/3) { [f]/dz + (3 r0^2 - d01 d02) R_F
-        //                     + 2 S3 [ (dz^2/3) d01 d02 R_D(U1^2, U2^2, U0^2) + X0 Y0 / U0 ] }
-        const T A1 = DQ * Fp<T>::rcp(f2 + f1);
-        const T rf = rf_s<T, PAIR>(V0, g.va, g.vb);
-        const T br = z2 * T(1.0 / 3.0) * k.d0102 * rd + g.X0 * k.y0 * Fp<T>::rcp(g.U0);
-        const T t2 = k.xc3 * rf, t3 = T(2) * k.xs3 * br;
-        const T sum = A1 + t2 + t3;
-        // the terms cancel at small z (by ~60 on the near-cubic workload): beyond a
-        // factor 4 in FP32 (64 in FP64) the quadrature route is taken
-        const T lim = fp32 ? T(4) : T(64);
-        if (!(Fp<T>::abs(A1) + Fp<T>::abs(t2) + Fp<T>::abs(t3) <= lim * Fp<T>::abs(sum))) {
-            used_gl = true;
-            T v, gd[3];
-            gl_integral<T, PAIR>(k, z, 2, false, v, gd);
-            return v;
+    const G DQ = G(3) + z * (G(3) + z) + k.q2 * (G(2) + z) + k.q1;
+    const G num = DQ - s * (x2 * (G(1) + x2) + k.q2 * x2 - k.q0);
+    const G fq2 = f2 * Fp<G>::rsqrt(g.Xt2), fq1 = f1 * Fp<G>::rsqrt(k.yt2);
+    const G A = num * Fp<G>::rcp(k.yt2 * g.Xt2 * (fq2 + fq1));
+    const bool regular = Fp<G>::abs(tau) <= G(XSeries<Q>::tau_max);
+    // the algebraic terms first (few values stay live across the Carlson sequence)
+    G alg, amag;
+    if (regular) {
+        const G rs = Fp<G>::rsqrt(p), su = p * rs;
+        const G D1 = z2 * k.d0102 * Fp<G>::rcp(su + g.U0);     // (sqrt(p) - U0)/s
+        const G xm = -x2 * Fp<G>::rcp(g.Xt + G(1));             // (Xt - 1)/s
+        const G D2 = s * xm * k.xym + xm + k.xym;               // (Xt Yt - 1)/s
+        const G b = k.xs3;
+        const G Np = D1 + k.xa * g.U0 + k.xa * s * D1 - D2 * g.U0 - b * g.U0 - b * s * D2 * g.U0;
+        const G tN = -xy * Np * Fp<G>::rcp(g.Xt * k.yt * g.U0 * su);
+        G S1 = G(rc_series_coef(XSeries<Q>::n));
+#pragma unroll
+        for (int n = XSeries<Q>::n - 1; n >= 1; --n) S1 = S1 * tau + G(rc_series_coef(n));
+        const G tS = k.op1s3 * xy * rs * z2 * iq * S1;
+        alg = A + tN + tS;
+        amag = Fp<G>::abs(A) + Fp<G>::abs(tN) + Fp<G>::abs(tS);
+    } else {
+        const G q = Fp<G>::rcp(iq);
+        const G L = -Fp<G>::rcp(s);
+        const G a1 = L * k.om1s12 * xy * Fp<G>::rcp(g.Xt * k.yt * g.U0);
+        const G a2 = -L * k.op1s3 * G(rc_r(Q(q - s * z2), Q(q)));
+        alg = A + a1 + a2;
+        amag = Fp<G>::abs(A) + Fp<G>::abs(a1) + Fp<G>::abs(a2);
+    }
+    Q rf, rj, jx;
+    rfjx_s<Q, PAIR>(Q(V0), Q(g.va), Q(g.vb), Q(p), rf, rj, jx);
+    const G t2 = k.xc2 * G(rf);
+    xr.V0 = V0; xr.va = g.va; xr.vb = g.vb; xr.t2 = t2;
+    G t3, t4;
+    if (regular) {
+        t3 = G(2) * cc * k.om1s12 * z2 * k.d0102 * G(jx);
+        t4 = -cc * k.xe1 * G(rj);
+    } else {
+        const G L = -Fp<G>::rcp(s);
+        const G rd = G(rj) - G(2) * s * z2 * k.d0102 * G(jx); // R_D(U1^2, U2^2, U0^2)
+        t3 = L * k.om1s12 * cc * rd;
+        t4 = -L * k.op1s3 * cc * k.om1s0 * G(rj);
+    }
+    mag = amag + Fp<G>::abs(t2) + Fp<G>::abs(t3) + Fp<G>::abs(t4);
+    return alg + t2 + t3 + t4;
+}
+
+// Rounding bounds on the cancellation M/|B| of x_terms.  FP32 lanes beyond kXCancel32
+// refine the R_F term in FP64 (the algebraic terms are FP64 already; the R_J terms are
+// small where the terms cancel, at small z), which leaves an FP64-sized error in every
+// large term.  Lanes beyond kXCancel64 (none on the workloads: the matter-poor open
+// cosmologies of the non-flat workload reach ~300 at z = 1e-3, where the real root of Q
+// is ~ -15 and the terms are ~r0^2) take the Gauss-Legendre quadrature of eq. 2.5.
+constexpr double kXCancel32 = 8.0;
+constexpr double kXCancel64 = 1024.0;
+enum { kXRouteCarlson = 0, kXRouteFp64 = 1, kXRouteQuad = 2 };
+
+// X / (c/H0) for one lane; route: one of kXRoute* (1: the FP32 lane's R_F term refined
+// in FP64).
+template <typename T, bool PAIR> __device__ T x_hat(const CosmoRec &r, T z, int &route) {
+    route = kXRouteCarlson;
+    const double zd = (double)z;
+    double mag, B;
+    XRf<double> xr;
+    if (sizeof(T) == 4) {
+        B = x_terms<float, double, PAIR>(r, zd, mag, xr);
+        if (!(mag <= kXCancel32 * __builtin_fabs(B))) {
+            route = kXRouteFp64;
+            B += r.d.xc2 * rf_s<double, PAIR>(xr.V0, xr.va, xr.vb) - xr.t2;
         }
-        return k.pre * T(2.0 / 3.0) * z * sum;
+    } else {
+        B = x_terms<double, double, PAIR>(r, zd, mag, xr);
     }
-    // eq. 3.9, normalised (i = 0 real root of Q, (j, k) = slots (1, 2), l = radiation root)
-    const T yt2x = k.yt2 * g.Xt2;
-    const T fq2 = f2 * Fp<T>::rsqrt(g.Xt2), fq1 = f1 * Fp<T>::rsqrt(k.yt2);
-    const T num = DQ - k.sigma * (x2 * (T(1) + x2) + k.q2 * x2 - k.q0);
-    const T A = num * Fp<T>::rcp(yt2x * (fq2 + fq1));
-    // U0tilde = U_2^2 + dz^2 d_02 (1 - s r0)  (real)
-    const T u0t = (PAIR ? g.va : g.vb) + z2 * k.om1s0 * k.d02re;
-    const T q0t = u0t * Fp<T>::rcp(g.X02 * k.w0);
-    T rf, rj;
-    rfj_s<T, PAIR>(V0, g.va, g.vb, u0t, rf, rj);
-    const T rc = rc_r(q0t - k.sigma * z2, q0t);
-    const T t2 = k.xc2 * rf;
-    const T B1 = k.om1s12 * (z2 * T(1.0 / 3.0) * k.d0102 * rd + g.X0 * k.y0 * Fp<T>::rcp(g.Xt * k.yt * g.U0));
-    const T B2 = k.op1s3 * (z2 * T(1.0 / 3.0) * k.d0102 * k.om1s0 * rj + rc);
-    const T L = -Fp<T>::rcp(k.sigma);
-    const T sum = A + t2 + L * (B1 - B2);
-    const T mag = Fp<T>::abs(A) + Fp<T>::abs(t2) + L * (Fp<T>::abs(B1) + Fp<T>::abs(B2));
-    if (!(mag <= T(64) * Fp<T>::abs(sum))) { // cancellation beyond ~64 eps: quadrature
-        used_gl = true;
-        T v, gd[3];
-        gl_integral<T, PAIR>(k, z, 2, false, v, gd);
-        return v;
-    }
-    return k.pre * z * sum;
+    if (mag <= kXCancel64 * __builtin_fabs(B)) return T(r.d.pre * zd * B);
+    route = kXRouteQuad;
+    T v, gd[3];
+    gl_integral<T, PAIR>(lane_of<T>(r), z, 2, false, v, gd);
+    return v;
 }
 
 // Curvature transform: S = sinn(chi) (sec. 2.1.1; sinh for Ok > 0, sin for Ok < 0),

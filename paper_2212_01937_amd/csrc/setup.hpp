@@ -62,6 +62,8 @@ template <typename T> struct LaneConst {
     T d0102;                // X: (r1 - r0)(r2 - r0)
     T om1s12, op1s3, om1s0; // X: (1-s r1)(1-s r2), 1 + s S3, 1 - s r0
     T d02re, d02im;         // X: r2 - r0
+    T xe1, xa, xym;         // X, regular form: -2(r1 + r2) + s (r1 r2 + S3 r0), -(r1 + r2) + s r1 r2,
+                            //   -1/(Yt + 1)
     T dpath;                // distance of the nearest singularity ln(rho_n) to the path u >= 0
     T iyt2, iw0, iw1re, iw1im, iw2; // 1/Yt^2, 1/w_0, 1/w_1 (complex for a pair), 1/w_2
     T hinv;                 // 1/H0 [s Mpc/km]
@@ -195,6 +197,7 @@ template <typename T> __device__ void fill_lane(LaneConst<T> &L, const LaneConst
     L.xc3 = T(D.xc3); L.xc2 = T(D.xc2); L.xs3 = T(D.xs3); L.d0102 = T(D.d0102);
     L.om1s12 = T(D.om1s12); L.op1s3 = T(D.op1s3); L.om1s0 = T(D.om1s0);
     L.d02re = T(D.d02re); L.d02im = T(D.d02im);
+    L.xe1 = T(D.xe1); L.xa = T(D.xa); L.xym = T(D.xym);
     L.dpath = T(D.dpath);
     L.iyt2 = T(D.iyt2); L.iw0 = T(D.iw0); L.iw1re = T(D.iw1re); L.iw1im = T(D.iw1im); L.iw2 = T(D.iw2);
     L.hinv = T(D.hinv);
@@ -352,6 +355,7 @@ __device__ void setup_cosmo(const double *prm, CosmoRec &rec) {
         }
     rec.minsep = minsep;
     if (minsep < 1e-4) info |= COSMO_INFO_NEAR_MULTIROOT;
+    if (minsep < 2e-2) info |= COSMO_INFO_NEAR_MULTIROOT_F32;
 
     // --- lane constants
     D.sigma = sigma;
@@ -404,6 +408,12 @@ __device__ void setup_cosmo(const double *prm, CosmoRec &rec) {
     D.op1s3 = 1.0 + sigma * D.xs3;
     D.om1s0 = 1.0 - sigma * s0;
     D.d02re = d02.re; D.d02im = d02.im;
+    {   // the coefficients of the regular form of eq. 3.9, as polynomials in sigma
+        const double sum12 = (rho[1] + rho[2]).re, prod12 = (rho[1] * rho[2]).re;
+        D.xa = -sum12 + sigma * prod12;
+        D.xe1 = -2.0 * sum12 + sigma * (prod12 + D.xs3 * s0);
+        D.xym = -1.0 / (D.yt + 1.0);
+    }
     // Quadrature routes integrate in u = ln x along the half-line u >= 0; the
     // integrand is singular at u = ln(rho_n) (complex log).  Distance of the nearest
     // singularity to that half-line sizes the quadrature panels.

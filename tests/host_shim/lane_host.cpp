@@ -3,9 +3,9 @@
 using namespace cosmo;
 template <typename T, bool PAIR> static double one(const CosmoRec &r, int kind, T z) {
     const LaneConst<T> &k = lane_of<T>(r);
-    bool ugl = false;
+    int route = 0;
     if (kind == COSMO_T) return k.th * t_hat<T, PAIR>(r, z);
-    if (kind == COSMO_X) return k.dh * x_hat<T, PAIR>(k, z, ugl);
+    if (kind == COSMO_X) return k.dh * x_hat<T, PAIR>(r, z, route);
     return k.dh * chi_hat<T, PAIR>(k, z);
 }
 // kind: COSMO_DC, COSMO_T or COSMO_X; dt: 0 FP32, 1 FP64.  NaN for invalid cosmologies.
@@ -80,6 +80,84 @@ extern "C" void host_time_between_grad(const double *prm, int dt, const double *
         } else {
             if (r.pair) tgb<double, true>(r, z1[i], z2[i], o);
             else tgb<double, false>(r, z1[i], z2[i], o);
+        }
+    }
+}
+
+// R_F, R_J(x, y, z, p) and dR_J/dx from one duplication sequence (rfjx_s): triple as
+// host_rfd.  out: rf, rj, jx.  dt: 0 FP32, 1 FP64.
+extern "C" void host_rfjx(int dt, int pair, double x, double a, double b, double p, double *out) {
+    if (dt == 0) {
+        float rf, rj, jx;
+        if (pair) rfjx_s<float, true>((float)x, (float)a, (float)b, (float)p, rf, rj, jx);
+        else rfjx_s<float, false>((float)x, (float)a, (float)b, (float)p, rf, rj, jx);
+        out[0] = rf; out[1] = rj; out[2] = jx;
+    } else {
+        double rf, rj, jx;
+        if (pair) rfjx_s<double, true>(x, a, b, p, rf, rj, jx);
+        else rfjx_s<double, false>(x, a, b, p, rf, rj, jx);
+        out[0] = rf; out[1] = rj; out[2] = jx;
+    }
+}
+
+// Route taken by x_hat per redshift (kXRoute*: 0 Carlson in the lane precision, 1 FP64
+// re-evaluation of an FP32 lane, 2 quadrature), for one cosmology.
+extern "C" void host_x_route(const double *prm, int dt, const double *z, long n, int *route) {
+    CosmoRec r;
+    setup_cosmo(prm, r);
+    for (long i = 0; i < n; ++i) {
+        route[i] = -1;
+        if (!r.valid) continue;
+        if (dt == 0) {
+            if (r.pair) x_hat<float, true>(r, (float)z[i], route[i]);
+            else x_hat<float, false>(r, (float)z[i], route[i]);
+        } else {
+            if (r.pair) x_hat<double, true>(r, z[i], route[i]);
+            else x_hat<double, false>(r, z[i], route[i]);
+        }
+    }
+}
+
+// Value and derivatives of one lane between z1 and z2 (lane_grad_between, finished with
+// the root-Jacobian contraction of app. A as k_finalize_params does): out[6 i ..] =
+// (value, d/dOm0, d/dOL0, d/dOr0, d/dz1, d/dz2).  kind: COSMO_DC, COSMO_DM, COSMO_DA or
+// COSMO_T; dt: 0 FP32, 1 FP64; z2 = inf allowed.
+template <typename T, int KIND, bool PAIR> static void bgr(const CosmoRec &r, T z1, T z2, double *o) {
+    LaneGrad2<T> g2;
+    lane_grad_between<T, KIND, PAIR>(r, z1, z2, g2);
+    const LaneGrad<T> &g = g2.g;
+    double p[5];
+    for (int i = 0; i < 5; ++i) p[i] = (double)g.p[i];
+    o[0] = g.val;
+    for (int th = 0; th < 3; ++th) {
+        const double base = g.quad ? g.q[th] : root_contract(r, p, th);
+        o[1 + th] = (double)g.s * base - (double)g.dok;
+    }
+    o[4] = g2.dz1;
+    o[5] = g.dz;
+}
+template <typename T, bool PAIR> static void bgk(const CosmoRec &r, int kind, T z1, T z2, double *o) {
+    switch (kind) {
+    case COSMO_DC: bgr<T, COSMO_DC, PAIR>(r, z1, z2, o); break;
+    case COSMO_DM: bgr<T, COSMO_DM, PAIR>(r, z1, z2, o); break;
+    case COSMO_DA: bgr<T, COSMO_DA, PAIR>(r, z1, z2, o); break;
+    default: bgr<T, COSMO_T, PAIR>(r, z1, z2, o); break;
+    }
+}
+extern "C" void host_between_grad(const double *prm, int kind, int dt, const double *z1, const double *z2, long n,
+                                  double *out) {
+    CosmoRec r;
+    setup_cosmo(prm, r);
+    for (long i = 0; i < n; ++i) {
+        double *o = out + 6 * i;
+        if (!r.valid) { for (int q = 0; q < 6; ++q) o[q] = __builtin_nan(""); continue; }
+        if (dt == 0) {
+            const float a = (float)z1[i], b = z2[i] == __builtin_inf() ? __builtin_inff() : (float)z2[i];
+            if (r.pair) bgk<float, true>(r, kind, a, b, o);
+            else bgk<float, false>(r, kind, a, b, o);
+        } else {
+            if (r.pair) bgk<double, true>(r, kind, z1[i], z2[i], o);
+            else bgk<double, false>(r, kind, z1[i], z2[i], o);
         }
     }
 }

@@ -279,3 +279,35 @@ def test_value_from_the_adjoint_pass(dev, dt):
         if kind == "X":
             _, finfo = cosmo.cosmo_distance("X", p, zt, info=True)
             assert torch.equal(info, finfo)
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_x_carlson_route_on_every_workload(dev, dt):
+    """The absorption distance takes the Carlson route (eq. 3.9 in its regular
+    arrangement, eq. B.3 without radiation) on workloads 1, 2, 4 and 5 at full size:
+    the X_QUADRATURE bit is clear for every cosmology.  The matter-poor open cosmologies
+    of workload 2 (Om0 < 0.06, OL0 < 0.15: a real root of Q near -15, terms cancelling by
+    ~300 at z = 1e-3) are checked against the oracle on every one of their redshifts."""
+    sets = []
+    p1, z1 = workloads.config1()
+    sets.append((p1, z1))
+    p2, z2 = workloads.config2()
+    sets.append((p2, z2))
+    p4, z4, _ = workloads.config4()
+    sets.append((p4, z4))
+    p5, z5 = workloads.config5(n_z=2 ** 18)
+    sets.append((p5, z5))
+    for params, z in sets:
+        p = torch.tensor(params, device=dev)
+        zt = torch.tensor(z, dtype=dt, device=dev)
+        _, info = cosmo.cosmo_distance("X", p, zt, info=True)
+        flagged = int(((info & cosmo.INFO["X_QUADRATURE"]) != 0).sum())
+        assert flagged == 0, (params.shape, z.shape, flagged)
+    poor = np.where((p2[:, 1] < 0.06) & (p2[:, 2] < 0.15))[0]
+    assert poor.size >= 4
+    p = torch.tensor(p2[poor], device=dev)
+    zt = torch.tensor(z2[poor], dtype=dt, device=dev)
+    zref = zt.double().cpu().numpy()
+    out = cosmo.cosmo_distance("X", p, zt).cpu().numpy()
+    ref = oracle.distance("X", p2[poor], zref, shared_z=False)
+    check("X", dt, out, ref, "config2-matter-poor")

@@ -219,3 +219,103 @@ def test_time_between_gradient_matches_oracle(libs):
             scale = np.abs(ref) + 1e-3 * np.abs(val[0] / th)[:, None]
             e = np.abs(got - ref)[fin] / scale[fin]
             assert e.size and e.max() <= tol, (dt, c, params[c], float(e.max()))
+
+
+def host_x_route(lib, p, dt, z):
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    out = np.zeros(z.size, dtype=np.int32)
+    lib.host_x_route(np.ascontiguousarray(p, dtype=np.float64).ctypes.data_as(ctypes.c_void_p), dt,
+                     z.ctypes.data_as(ctypes.c_void_p), ctypes.c_long(z.size), out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def test_x_takes_the_carlson_route_on_every_workload(libs):
+    """The absorption distance (eq. 3.9 in its regular arrangement, eq. B.3) needs no
+    quadrature on any workload: route 0 (Carlson in the lane precision) or, for FP32
+    lanes whose terms cancel by more than 8, route 1 (the same formulas in FP64); never
+    route 2 (Gauss-Legendre).  Workloads 1, 2, 4 (all families) and 5 at their full
+    redshift ranges."""
+    p1, z1 = workloads.config1()
+    p2, z2 = workloads.config2(n_cosmo=64, n_z=256, seed=31)
+    p4, z4, _ = workloads.config4(n_per_family=16, n_z=256, seed=31)
+    p5, z5 = workloads.config5(n_cosmo=32, n_z=256, seed=31)
+    sets = [(p1, np.broadcast_to(z1, (1, z1.size))), (p2, z2), (p4, np.broadcast_to(z4, (p4.shape[0], z4.size))),
+            (p5, np.broadcast_to(z5, (p5.shape[0], z5.size)))]
+    counts = np.zeros((2, 3), dtype=np.int64)
+    for p, z in sets:
+        for c in range(p.shape[0]):
+            for dt in (0, 1):
+                r = host_x_route(libs["exact"], p[c], dt, z[c])
+                assert (r >= 0).all() and (r <= 2).all()
+                counts[dt] += np.bincount(r, minlength=3)
+    print("FP32 routes (Carlson, FP64, quadrature)", counts[0], "FP64 routes", counts[1])
+    assert counts[0, 2] == 0 and counts[1, 2] == 0
+    assert counts[1, 1] == 0  # the FP64 path has no FP64 re-evaluation route
+
+
+@pytest.mark.parametrize("model", ["exact", "noisy"])
+def test_rfjx_derivative_matches_mpmath(libs, model):
+    """rfjx_s: R_F, R_J(x, y, z, p) and dR_J/dx (forward-mode through the duplication)
+    against mpmath's R_F, R_J and its numerical derivative of R_J at 30 digits, on
+    structured triples with p both close to x (relative 1e-9 .. 1, the regular form of
+    eq. 3.9) and unrelated to it: FP64 <= 2e-14, FP32 <= 4e-6 (arguments rounded)."""
+    import mpmath as mp
+    mp.mp.dps = 30
+    rng = np.random.default_rng(17)
+    for n, (pair, x, a, b) in enumerate(_triples(rng, 120)):
+        p = x * (1 + rng.choice([-1, 1]) * 10 ** rng.uniform(-9, 0)) if n % 2 else 10 ** rng.uniform(-2, 2)
+        for dt, tol in ((1, 2e-14), (0, 4e-6)):
+            if dt == 0:
+                x, a, b, p = (float(np.float32(v)) for v in (x, a, b, p))
+            y, zc = (mp.mpc(a, b), mp.mpc(a, -b)) if pair else (mp.mpf(a), mp.mpf(b))
+            ref = [mp.re(mp.elliprf(x, y, zc)), mp.re(mp.elliprj(x, y, zc, p)),
+                   mp.re(mp.diff(lambda t: mp.elliprj(t, y, zc, p), x))]
+            out = np.zeros(3)
+            libs[model].host_rfjx(dt, int(pair), ctypes.c_double(x), ctypes.c_double(a), ctypes.c_double(b),
+                                  ctypes.c_double(p), out.ctypes.data_as(ctypes.c_void_p))
+            errs = [abs(out[k] / float(ref[k]) - 1) for k in range(3)]
+            assert max(errs) <= tol, (dt, pair, x, a, b, p, errs)
+
+
+def host_between_grad(lib, p, kind, dt, z1, z2):
+    z1 = np.ascontiguousarray(z1, dtype=np.float64)
+    z2 = np.ascontiguousarray(z2, dtype=np.float64)
+    out = np.zeros((z1.size, 6))
+    lib.host_between_grad(np.ascontiguousarray(p, dtype=np.float64).ctypes.data_as(ctypes.c_void_p), KIND_BTW[kind],
+                          dt, z1.ctypes.data_as(ctypes.c_void_p), z2.ctypes.data_as(ctypes.c_void_p),
+                          ctypes.c_long(z1.size), out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def test_time_between_root_chain_gradient_matches_oracle(libs):
+    """t(z1, z2) differentiated through eq. 3.8 with both limits (t_grad_between: Carlson
+    derivatives, eqs. 2.10-2.11, and the root Jacobian of app. A), finished with the
+    root-Jacobian contraction, against the oracle's Leibniz derivatives in (Om0, OL0, Or0)
+    and its fundamental-theorem limit derivatives: FP64 <= 1e-11, FP32 <= 1e-4 (Or0: 5e-4,
+    the root-chain cancellation of that component), each relative to the largest
+    magnitude of that derivative over the lanes of the cosmology; lens-source pairs, close
+    limits and the age t(z, inf) on the headline and non-flat cosmologies."""
+    rng = np.random.default_rng(19)
+    p5, _ = workloads.config5(n_cosmo=6, n_z=4, seed=19)
+    p2, _ = workloads.config2(n_cosmo=6, n_z=4, seed=19)
+    for p in np.concatenate([p5, p2]):
+        z1 = rng.uniform(0.05, 1.5, 60)
+        z2 = z1 + rng.uniform(0.01, 2.0, 60)
+        z2[:10] = z1[:10] + 10.0 ** rng.uniform(-6, -2, 10)
+        z1[40:] = rng.uniform(0.0, 20.0, 20)
+        z2[40:] = np.inf
+        for dt, tol in ((1, (1e-11, 1e-11, 1e-11)), (0, (1e-4, 1e-4, 5e-4))):
+            a = z1.astype(np.float32).astype(np.float64) if dt == 0 else z1
+            b = z2.astype(np.float32).astype(np.float64) if dt == 0 else z2
+            val, g = oracle.between("T", p[None], a, b, grad=True)
+            got = host_between_grad(libs["exact"], p, "T", dt, a, b)
+            assert np.max(np.abs(got[:, 0] / val[0] - 1)) <= (1e-12 if dt == 1 else 1e-6)
+            for th in range(3):
+                ref = g[0, :, 1 + th]
+                e = np.abs(got[:, 1 + th] - ref) / np.abs(ref).max()
+                assert e.max() <= tol[th], (dt, th, p, float(e.max()))
+            fin = np.isfinite(b)
+            for q, col in ((4, 4), (5, 5)):
+                ref = g[0, fin, col]
+                e = np.abs(got[fin, q] - ref) / np.abs(ref).max()
+                assert e.max() <= (1e-12 if dt == 1 else 1e-6), (dt, q, float(e.max()))
