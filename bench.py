@@ -144,6 +144,14 @@ def cpu_baseline_widened(params, z1, z2, zv):
                                                  zv.size)}
 
 
+def route_fractions(counts):
+    """Fractions of the evaluated lanes per route (cosmo_route_counts): the value's FP64
+    R_F refinement (FP32 X lanes) and quadrature (X), and the adjoint's Leibniz quadrature."""
+    c = counts.sum(0).cpu().numpy().astype(np.float64)
+    n = max(c[0] + c[1] + c[2], 1.0)
+    return {"value_carlson_fp64_rf": c[1] / n, "value_quadrature": c[2] / n, "adjoint_quadrature": c[3] / n}
+
+
 def timed(fn, steps, stream, torch):
     """Event-timed repetitions of fn on `stream`; returns (per-call ms list, wall ms per call)."""
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
@@ -232,6 +240,8 @@ def main():
                          "two_call_fwd_plus_vjp_ms": float(np.median(fwd_ev) + np.median(vjp_ev)),
                          "jacobian_ms": float(np.median(jac_ev)),
                          "jacobian_evals_per_s": evals / (np.median(jac_ev) * 1e-3),
+                         "route_fractions": {k: route_fractions(cosmo.cosmo_route_counts(k, p, zt, workspace=ws))
+                                             for k in ("MU", "X")},
                          }
         del mu, gp, gz, w
         torch.cuda.empty_cache()
@@ -400,6 +410,8 @@ def main():
                     e2, _, _ = timed(f2, 10, stream, torch)
                     rec[f"{path}_{kind}_fwd_evals_per_s"] = rec["evals"] / (np.median(e1) * 1e-3)
                     rec[f"{path}_{kind}_fwd_grad_evals_per_s"] = rec["evals"] / (np.median(e2) * 1e-3)
+                    rec.setdefault("route_fractions", {})[f"{path}_{kind}"] = route_fractions(
+                        cosmo.cosmo_route_counts(kind, pt, zt_o, workspace=ws_o))
             others[name] = rec
         results["other_workloads"] = others
 

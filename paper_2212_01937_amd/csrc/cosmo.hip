@@ -322,12 +322,36 @@ __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T 
     const T *__restrict__ vr = LIKE ? ivar + c * zstride : nullptr;
     T *__restrict__ orow = out ? out + c * n_z : nullptr;
     T *__restrict__ grow = gz_out ? gz_out + c * n_z : nullptr;
+    // FP64: the next redshift's inputs are loaded before this one's outputs are stored
+    // (one in-order counter tracks vector loads and stores, so a wait for loads issued
+    // after a store would also wait for the store; 4% on the headline FP64 step).  The
+    // FP32 loop loads in place: the prefetch's registers cost it more at eight waves.
+    constexpr bool pre = sizeof(T) == 8;
     uint32_t deferred = 0;
+    T zn = T(0), cn = T(0), vn = T(0);
+    if (pre && i0 < nz) {
+        zn = zr[i0];
+        cn = LIKE ? cr[i0] : __builtin_nontemporal_load(cr + i0);
+        if (LIKE) vn = vr[i0];
+    }
 #pragma unroll 1
     for (int k = 0; k < ZPT; ++k) {
         const uint32_t i = i0 + (uint32_t)(k * kBlock);
         if (i >= nz) break;
-        const T zz = zr[i];
+        T zz, cin, vin;
+        if (pre) {
+            zz = zn; cin = cn; vin = vn;
+            const uint32_t i1 = i + kBlock;
+            if (k + 1 < ZPT && i1 < nz) {
+                zn = zr[i1];
+                cn = LIKE ? cr[i1] : __builtin_nontemporal_load(cr + i1);
+                if (LIKE) vn = vr[i1];
+            }
+        } else {
+            zz = zr[i];
+            cin = LIKE ? cr[i] : __builtin_nontemporal_load(cr + i);
+            vin = LIKE ? vr[i] : T(0);
+        }
         if (small_z_lane<T>(zz)) {
             deferred |= 1u << k;
             continue;
@@ -336,12 +360,12 @@ __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T 
         lane_grad_root<T, KIND, PAIR>(r, zz, o);
         T cv;
         if (LIKE) {
-            const T res = cr[i] - o.val;
-            const T rv = res * vr[i];
+            const T res = cin - o.val;
+            const T rv = res * vin;
             acc[kAccLoss] += T(-0.5) * res * rv;
             cv = wc * rv;
         } else {
-            cv = __builtin_nontemporal_load(cr + i);
+            cv = cin;
         }
         const T w = cv * o.s;
 #pragma unroll
@@ -376,11 +400,12 @@ __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T 
     }
 }
 
-// Occupancy: the FP32 comoving-distance-family adjoint fits 80 VGPRs, six waves per
-// SIMD (measured 6% faster than the five its unconstrained allocation gives); the
-// others (T, and X with its FP64 geometry) keep the compiler's allocation.
+// Occupancy: the FP32 comoving-distance-family adjoint is held to 64 VGPRs, eight waves
+// per SIMD (the root-chain loop fits; measured 3-6% faster on the headline workload than
+// six waves at 80 VGPRs); the others (T, and X with its FP64 geometry) keep the
+// compiler's allocation.
 template <typename T, int KIND> constexpr int adjoint_min_waves() {
-    return (sizeof(T) == 4 && KIND != COSMO_T && KIND != COSMO_X) ? 6 : 1;
+    return (sizeof(T) == 4 && KIND != COSMO_T && KIND != COSMO_X) ? 8 : 1;
 }
 
 template <typename T, int KIND, int ZPT, bool LIKE>
@@ -564,8 +589,45 @@ __global__ __launch_bounds__(kBlock) void k_between_vjp(const CosmoRec *__restri
 // Materialised Jacobian: per lane the observable and d out / d(H0, Om0, OL0, Or0, z),
 // written as five planes jac[q][c][i]; the root-space partials are contracted with the
 // root Jacobian per lane, in FP64.  Grid as k_forward.
+// Occupancy of the materialised Jacobian: the FP32 comoving-distance family at 80 VGPRs
+// (six waves); the others keep the compiler's allocation.
+template <typename T, int KIND> constexpr int jac_min_waves() {
+    return (sizeof(T) == 4 && KIND != COSMO_T && KIND != COSMO_X) ? 6 : 1;
+}
+
+// The lane's partials contracted with the root Jacobian (app. A) per parameter, with the
+// cancellation check of kJacCancel32: FP32 lanes contract in FP32 with the FP32 copies of
+// the coefficients (the check compares the size of the terms with their sum, which does
+// not depend on the precision of the contraction); FP64 lanes as root_contract.  Returns
+// false where the terms cancel by more than kJacCancel32 (FP32 only).
+template <typename T>
+__device__ __forceinline__ bool jac_contract(const CosmoRec &r, const T p[5], double d[3]) {
+    if (sizeof(T) == 4) {
+        bool ok = true;
+#pragma unroll
+        for (int th = 0; th < 3; ++th) {
+            float sum = 0.0f, mag = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const float t = (float)p[q] * r.jc32[q][th];
+                sum += t;
+                mag += __builtin_fabsf(t);
+            }
+            d[th] = sum;
+            ok = ok && (mag <= float(kJacCancel32) * __builtin_fabsf(sum));
+        }
+        return ok;
+    }
+    double pd[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) pd[q] = (double)p[q];
+#pragma unroll
+    for (int th = 0; th < 3; ++th) d[th] = root_contract(r, pd, th);
+    return true;
+}
+
 template <typename T, int KIND>
-__global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_jac(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
+__global__ __launch_bounds__(kBlock, (jac_min_waves<T, KIND>())) void k_jac(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
                                                  const T *__restrict__ z, int64_t n_z, int64_t zstride,
                                                  T *__restrict__ out, T *__restrict__ jac, int32_t *__restrict__ info,
                                                  int ct, int64_t nzb) {
@@ -573,20 +635,41 @@ __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_jac(
     const int64_t tile = b / nzb, zb = b - tile * nzb;
     const int64_t i = zb * kBlock + threadIdx.x;
     const bool active = i < n_z;
+    const uint32_t i32 = (uint32_t)i; // n_z < 2^31 (checked on the host)
     const int64_t c0 = tile * ct;
     const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
     const int64_t plane = n_cosmo * n_z;
     const T zshared = (zstride == 0 && active) ? z[i] : T(0);
+    constexpr bool fp32 = sizeof(T) == 4;
     for (int64_t c = c0; c < c1; ++c) {
         const CosmoRec &r = recs[c];
         if (!active) continue;
-        const T zz = zstride == 0 ? zshared : z[c * zstride + i];
+        const T zz = zstride == 0 ? zshared : (z + c * zstride)[i32];
         T v, J[5];
         bool used_gl = false;
         if (!r.valid) {
             v = Fp<T>::nan();
 #pragma unroll
             for (int q = 0; q < 5; ++q) J[q] = Fp<T>::nan();
+        } else if (KIND != COSMO_X && !adjoint_quadrature_lane<T>(KIND, r, zz)) {
+            // root-chain lane (the common case)
+            RootGrad<T> o;
+            if (r.pair) lane_grad_root<T, KIND, true>(r, zz, o);
+            else lane_grad_root<T, KIND, false>(r, zz, o);
+            v = o.val;
+            J[0] = o.dh;
+            J[4] = o.dz;
+            double d[3];
+            if (!jac_contract<T>(r, o.p, d)) {
+                // the contraction cancels (small beta, small z): Leibniz-rule quadrature
+                T bv, g[3];
+                if (r.pair) gl_integral<T, true>(lane_of<T>(r), zz, KIND == COSMO_T ? 1 : 0, true, bv, g, 1);
+                else gl_integral<T, false>(lane_of<T>(r), zz, KIND == COSMO_T ? 1 : 0, true, bv, g, 1);
+#pragma unroll
+                for (int th = 0; th < 3; ++th) d[th] = g[th];
+            }
+#pragma unroll
+            for (int th = 0; th < 3; ++th) J[1 + th] = fp32 ? T(o.s) * T(d[th]) - o.dok : T((double)o.s * d[th] - (double)o.dok);
         } else {
             LaneGrad<T> o;
             if (r.pair) lane_grad<T, KIND, true>(r, zz, o, used_gl);
@@ -598,32 +681,20 @@ __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_jac(
             if (o.quad) {
 #pragma unroll
                 for (int th = 0; th < 3; ++th) d[th] = o.q[th];
-            } else {
-                double pd[5];
+            } else if (!jac_contract<T>(r, o.p, d) && KIND != COSMO_X) {
+                T bv, g[3];
+                if (r.pair) gl_integral<T, true>(lane_of<T>(r), zz, KIND == COSMO_T ? 1 : 0, true, bv, g, 1);
+                else gl_integral<T, false>(lane_of<T>(r), zz, KIND == COSMO_T ? 1 : 0, true, bv, g, 1);
 #pragma unroll
-                for (int q = 0; q < 5; ++q) pd[q] = (double)o.p[q];
-                bool bad = false;
-#pragma unroll
-                for (int th = 0; th < 3; ++th) {
-                    double mag;
-                    d[th] = root_contract(r, pd, th, &mag);
-                    bad = bad || !(mag <= kJacCancel32 * __builtin_fabs(d[th]));
-                }
-                if (sizeof(T) == 4 && bad && KIND != COSMO_X) {
-                    T bv, g[3];
-                    if (r.pair) gl_integral<T, true>(lane_of<T>(r), zz, KIND == COSMO_T ? 1 : 0, true, bv, g, 1);
-                    else gl_integral<T, false>(lane_of<T>(r), zz, KIND == COSMO_T ? 1 : 0, true, bv, g, 1);
-#pragma unroll
-                    for (int th = 0; th < 3; ++th) d[th] = g[th];
-                }
+                for (int th = 0; th < 3; ++th) d[th] = g[th];
             }
 #pragma unroll
             for (int th = 0; th < 3; ++th) J[1 + th] = T((double)o.s * d[th] - (double)o.dok);
         }
-        const int64_t e = c * n_z + i;
-        if (out) out[e] = v;
+        T *__restrict__ row = jac + c * n_z;
+        if (out) __builtin_nontemporal_store(v, (out + c * n_z) + i32);
 #pragma unroll
-        for (int q = 0; q < 5; ++q) jac[q * plane + e] = J[q];
+        for (int q = 0; q < 5; ++q) __builtin_nontemporal_store(J[q], (row + q * plane) + i32);
         if (KIND == COSMO_X && info) {
             unsigned long long m = __ballot(used_gl);
             if (m && (int)__lane_id() == __ffsll((long long)m) - 1) atomicOr(info + c, COSMO_INFO_X_QUADRATURE);

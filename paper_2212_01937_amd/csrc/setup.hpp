@@ -79,6 +79,7 @@ struct CosmoRec {
     double dbeta[3], dsigma[3];       // d/d(Om, OL, Or)
     double drho_re[3][3], drho_im[3][3]; // [root slot][param]
     double rl;                         // radiation root in x (1/sigma), NaN if cubic
+    float jc32[5][3];                  // root-Jacobian contraction coefficients in FP32 (root_contract's)
     LaneConst<double> d;
     LaneConst<float> f;
 };
@@ -227,6 +228,7 @@ __device__ void setup_cosmo(const double *prm, CosmoRec &rec) {
     for (int a = 0; a < 3; ++a) {
         rec.dbeta[a] = rec.dsigma[a] = 0.0;
         for (int n = 0; n < 3; ++n) rec.drho_re[n][a] = rec.drho_im[n][a] = 0.0;
+        for (int q = 0; q < 5; ++q) rec.jc32[q][a] = 0.0f;
     }
     LaneConst<double> &D = rec.d;
     D = LaneConst<double>{};
@@ -456,6 +458,13 @@ __device__ void setup_cosmo(const double *prm, CosmoRec &rec) {
         }
     }
     rec.beta = beta;
+    for (int a = 0; a < 3; ++a) {
+        rec.jc32[0][a] = (float)(-rec.dbeta[a] / (2.0 * beta));
+        rec.jc32[1][a] = (float)rec.dsigma[a];
+        rec.jc32[2][a] = (float)rec.drho_re[0][a];
+        rec.jc32[3][a] = (float)(pair ? 2.0 * rec.drho_re[1][a] : rec.drho_re[1][a]);
+        rec.jc32[4][a] = (float)(pair ? -2.0 * rec.drho_im[1][a] : rec.drho_re[2][a]);
+    }
     rec.rl = Or > 0.0 ? 1.0 / sigma : __builtin_nan("");
     rec.fallback_grad = (minsep < 1e-4) ? 1 : 0;
     bool ok_all = !(info & (COSMO_INFO_RED | COSMO_INFO_DOMAIN));
