@@ -141,7 +141,8 @@ __device__ __forceinline__ void lane_grad(const CosmoRec &r, T z, LaneGrad<T> &o
         } else {
             ChiGrad<T, PAIR> cg;
             chi_grad<T, PAIR>(k, z, cg);
-            o.p[0] = cg.chi; o.p[1] = cg.dsig; o.p[2] = cg.dr0; o.p[3] = cg.dr1re; o.p[4] = PAIR ? cg.dr1im : cg.dr2;
+            o.p[0] = cg.chi; o.p[1] = cg.kr * cg.dsig; o.p[2] = cg.kr * cg.dr0; o.p[3] = cg.kr * cg.dr1re;
+            o.p[4] = cg.kr * (PAIR ? cg.dr1im : cg.dr2);
             ie = cg.iE;
         }
         o.val = observable<T>(KIND, k, o.p[0], z, H0inv, o.s, o.dok, dzz, o.dh);
@@ -156,7 +157,8 @@ __device__ __forceinline__ void lane_grad(const CosmoRec &r, T z, LaneGrad<T> &o
 // stay out of the main loop).
 template <typename T> struct RootGrad {
     T val, s, dok, dh, dz;
-    T p[5];
+    T p[5]; // p[1..4] divided by ps: the partials are (p[0], ps p[1], ..., ps p[4])
+    T ps;
 };
 
 template <typename T, int KIND, bool PAIR>
@@ -167,6 +169,7 @@ __device__ __forceinline__ void lane_grad_root(const CosmoRec &r, T z, RootGrad<
         TGrad<T, PAIR> tg;
         t_grad<T, PAIR>(r, z, tg);
         o.p[0] = tg.t; o.p[1] = tg.dsig; o.p[2] = tg.dr0; o.p[3] = tg.dr1re; o.p[4] = PAIR ? tg.dr1im : tg.dr2;
+        o.ps = T(1);
         o.s = k.th;
         o.val = k.th * o.p[0];
         o.dok = T(0);
@@ -177,6 +180,7 @@ __device__ __forceinline__ void lane_grad_root(const CosmoRec &r, T z, RootGrad<
     ChiGrad<T, PAIR> cg;
     chi_grad<T, PAIR>(k, z, cg);
     o.p[0] = cg.chi; o.p[1] = cg.dsig; o.p[2] = cg.dr0; o.p[3] = cg.dr1re; o.p[4] = PAIR ? cg.dr1im : cg.dr2;
+    o.ps = cg.kr;
     T dzz;
     o.val = observable<T>(KIND, k, o.p[0], z, H0inv, o.s, o.dok, dzz, o.dh);
     o.dz = dzz + o.s * cg.iE;

@@ -99,7 +99,7 @@ template <typename T, bool PAIR> __device__ __forceinline__ T chi_between(const 
     sides<T, PAIR>(k, z1, z2, a, b, dz);
     Args2<T, PAIR> u;
     args_between<T, PAIR>(a, b, u);
-    return k.pre * T(2) * dz * rf_s<T, PAIR>(u.V0, u.va, u.vb);
+    return k.pre2 * dz * rf_s<T, PAIR>(u.V0, u.va, u.vb);
 }
 
 // Arguments of t(z1, z2) (eq. 3.8 in the normalised form of t_args_in), in the
@@ -146,7 +146,7 @@ template <typename T, bool PAIR> __device__ __forceinline__ T t_between(const Co
     T rf, rj;
     rfj_s<T, PAIR>(V0, va, vb, W, rf, rj);
     const T rc = ad.rc_zero ? T(0) : rc_r(T(ad.S), T(ad.Qv));
-    return k.pre * T(2) * dz * (d2 * T(1.0 / 3.0) * k.pre3 * rj + rc + k.sigma * rf);
+    return k.pre2 * dz * (d2 * T(1.0 / 3.0) * k.pre3 * rj + rc + k.sigma * rf);
 }
 
 // Observable KIND (COSMO_DC, COSMO_DM, COSMO_DA or COSMO_T) between z1 and z2.
@@ -264,7 +264,7 @@ __device__ __forceinline__ void chi_grad_between(const LaneConst<T> &k, T z1, T 
     T rf, rdx, rdz;
     cx<T> rdy;
     rfd_s<T, PAIR>(U0 * U0, va, vb, rf, rdx, rdy, rdz);
-    const T scale = k.pre * T(2) * dz;
+    const T scale = k.pre2 * dz;
     o.chi = scale * rf;
     o.iE1 = k.pre * b.ie;
     o.iE2 = k.pre * a.ie;
@@ -418,7 +418,7 @@ __device__ void t_grad_between(const CosmoRec &r, T z1, T z2, TGrad2<T, PAIR> &o
         dr1.re += T(-0.5) * ((a1 + Bs - b1) * a.i1re + (b1 + As - a1) * b.i1re);
         dr2 += T(-0.5) * ((a2 + Bs - b2) * a.i2 + (b2 + As - a2) * b.i2);
     }
-    const T scale = k.pre * T(2) * dz;
+    const T scale = k.pre2 * dz;
     o.t = scale * (c3 * rj + rc + s * rf);
     o.dsig = scale * dsig;
     o.dr0 = scale * dr0;

@@ -290,10 +290,25 @@ __device__ __forceinline__ void yz_sym(T A0, T a, T b, T g, T &s, T &q) {
     }
 }
 
+// FP32 lanes rarely duplicate at all (the expansion is accurate to the FP32 rounding
+// level from the tau7 deviation down), and neighbouring redshifts agree on it: a wave
+// none of whose lanes needs a step evaluates the tail at m = 0 directly, without the
+// sequence's bookkeeping (f = 1, the mean A = A0, no accumulated terms).
+template <typename T, bool PAIR> __device__ __forceinline__ bool wave_no_dup(T Q, T A0) {
+    return sizeof(T) == 4 && __ballot(spread_above<T, PAIR>(Q, T(1), Fp<T>::tau7, A0)) == 0;
+}
+
 template <typename T, bool PAIR> __device__ T rf_s(T x, T a, T b) {
     const T A0 = mean3<T, PAIR>(x, a, b);
     const T x0 = x, a0 = a, b0 = b;
     const T Q = spread3<T, PAIR>(A0, x, a, b);
+    if (wave_no_dup<T, PAIR>(Q, A0)) {
+        const T ra = Fp<T>::rsqrt(A0), g = ra * ra;
+        T s, q;
+        const T X = (A0 - x0) * g;
+        yz_sym<T, PAIR>(A0, a0, b0, g, s, q);
+        return rf_tail(q - X * X, X * q) * ra;
+    }
     T A = A0, f = T(1);
     for (int m = 0; m < kMaxDup && spread_above<T, PAIR>(Q, f, Fp<T>::tau7, A); ++m) {
         T sx, syr, sya, sz;
@@ -441,6 +456,15 @@ __device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
     const T AF0 = mean3<T, PAIR>(x, a, b);
     const T x0 = x, a0 = a, b0 = b;
     const T QF = spread3<T, PAIR>(AF0, x, a, b);
+    if (wave_no_dup<T, PAIR>(QF, AF0)) {
+        T tx, tz;
+        cx<T> ty;
+        rfd_tails<T, PAIR>(AF0, x0, a0, b0, AF0, T(1), rf, tx, ty, tz);
+        rdx = tx;
+        rdy = ty;
+        rdz = tz;
+        return;
+    }
     // One duplication sequence, stopped on R_F's criterion; each R_D(., ., x_k) is
     // 3 sum_m 4^-m / (sqrt(x_k,m) (x_k,m + lambda_m)) plus the tail of rfd_tails.
     T AF = AF0, f = T(1), accx = T(0), accz = T(0);

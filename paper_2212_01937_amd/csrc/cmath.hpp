@@ -135,6 +135,22 @@ template <typename T> __device__ __forceinline__ cx<T> csqrt_inv(cx<T> w, T &abs
     res.im = pos ? (w.im >= T(0) ? small : -small) : (w.im >= T(0) ? big : -big);
     return res;
 }
+// As csqrt_inv for w = wre + i wim with a non-zero imaginary part that is the same
+// on every lane: wim^2, |wim|/2 and sign(wim) come precomputed.  With wim != 0,
+// |w| > |wre| and the half-sum t below is positive.
+template <typename T>
+__device__ __forceinline__ cx<T> csqrt_uim_inv(T wre, T wim2, T hwim, T swim, T &absw, T &iabsw) {
+    const T n = wre * wre + wim2;
+    const T ir = Fp<T>::rsqrt(n);
+    const T r = n * ir;
+    absw = r;
+    iabsw = ir;
+    const T t = T(0.5) * (r + Fp<T>::abs(wre));
+    const T q = Fp<T>::rsqrt(t);
+    const T big = t * q, small = hwim * q;
+    const bool pos = wre >= T(0);
+    return mkc(pos ? big : small, swim * (pos ? small : big));
+}
 template <typename T> __device__ __forceinline__ cx<T> csqrt(cx<T> w) {
     T r;
     return csqrt(w, r);

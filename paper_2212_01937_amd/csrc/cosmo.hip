@@ -258,6 +258,74 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
     return lane63(v);
 }
 
+// Cross-lane moves for wave_sum8: lane ^ X within 32 lanes (swizzle in bit mode:
+// and-mask 0x1F, xor-mask X) and any lane (permute by byte address).
+template <int X> __device__ __forceinline__ float swap_x(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), (X << 10) | 0x1F));
+}
+template <int X> __device__ __forceinline__ double swap_x(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)b, (X << 10) | 0x1F);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)(b >> 32), (X << 10) | 0x1F);
+    return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+__device__ __forceinline__ float permute(float v, int addr) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double permute(double v, int addr) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)b);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+
+// Wave sums of eight slots at once (all lanes active): a transposed butterfly.  Each
+// exchange step pairs the lanes that differ in one bit of the lane index (bit 0, 1, then
+// 3: quad permutes and a row rotation by 8, i.e. lane ^ 8 within a 16-lane row); a lane
+// keeps the half of its slots that this bit selects and adds the partner's copy of the
+// same half.  After three steps a lane holds one slot, j = 4 b0 + 2 b1 + b3, summed over
+// eight lanes; the rest is a plain sum over lane bits 2, 4 and 5.  Returns the wave total
+// of slot j(lane) on every lane: about a third of the lane operations of eight wave_sum
+// calls.
+template <typename T> __device__ __forceinline__ T wave_sum8(const T v[8], int lane) {
+    const bool h0 = lane & 1, h1 = lane & 2, h3 = lane & 8;
+    T a[4], b[2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const T keep = h0 ? v[j + 4] : v[j], send = h0 ? v[j] : v[j + 4];
+        a[j] = keep + dpp_move<0xB1, 0xF>(send);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const T keep = h1 ? a[j + 2] : a[j], send = h1 ? a[j] : a[j + 2];
+        b[j] = keep + dpp_move<0x4E, 0xF>(send);
+    }
+    const T keep = h3 ? b[1] : b[0], send = h3 ? b[0] : b[1];
+    T c = keep + dpp_move<0x128, 0xF>(send);
+    c += swap_x<4>(c);
+    c += swap_x<16>(c);
+    c += permute(c, (lane ^ 32) << 2);
+    return c;
+}
+
+// The wave's partial sums of one cosmology's accumulators into its row of kAcc slots:
+// slots 0-6 and the loss by wave_sum8 (its lanes 0-3 and 8-11 store them), the three
+// quadrature slots one by one, skipped when no lane of the wave touched them.
+template <typename T> __device__ __forceinline__ void store_partials(const T acc[kAcc], T *__restrict__ row, int lane) {
+    const T v8[8] = {acc[0], acc[1], acc[2], acc[3], acc[4], acc[5], acc[6], acc[kAccLoss]};
+    const T tot = wave_sum8(v8, lane);
+    if ((lane & 0x34) == 0) {
+        const int j = 4 * (lane & 1) + (lane & 2) + ((lane >> 3) & 1);
+        row[j == 7 ? kAccLoss : j] = tot;
+    }
+#pragma unroll
+    for (int s = 7; s < 10; ++s) {
+        T v = T(0);
+        if (__ballot(acc[s] != T(0))) v = wave_sum(acc[s]);
+        if (lane == 0) row[s] = v;
+    }
+}
+
 // Redshifts per lane of the adjoint: lane t of z-block zb handles
 // i = zb * kBlock * ZPT + t + k * kBlock, k < ZPT (coalesced for every k).  The
 // parameter partials of a cosmology are summed over the lane's ZPT redshifts in
@@ -367,9 +435,10 @@ __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T 
         } else {
             cv = cin;
         }
-        const T w = cv * o.s;
+        const T w = cv * o.s, wp = w * o.ps;
+        acc[0] += w * o.p[0];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) acc[q] += w * o.p[q];
+        for (int q = 1; q < 5; ++q) acc[q] += wp * o.p[q];
         acc[5] += cv * o.dok;
         acc[6] += cv * o.dh;
         const T gz = cv * o.dz;
@@ -447,16 +516,7 @@ __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_vjp(
                 }
             }
         }
-        if (pacc) {
-#pragma unroll
-            for (int s = 0; s < kAcc; ++s) {
-                // slots no lane of the wave touched (the loss outside likelihood mode,
-                // the quadrature slots away from small z) skip the reduction
-                T v = T(0);
-                if (__ballot(acc[s] != T(0))) v = wave_sum(acc[s]);
-                if (lane == 0) pacc[(c * nwz + gw) * kAcc + s] = v;
-            }
-        }
+        if (pacc) store_partials(acc, pacc + (c * nwz + gw) * kAcc, lane);
     }
     if (zstride == 0 && gz_out) {
         for (int k = 0; k < ZPT; ++k) {
@@ -560,14 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_between_vjp(const CosmoRec *__restri
                 }
             }
         }
-        if (pacc) {
-#pragma unroll
-            for (int s = 0; s < kAcc; ++s) {
-                T v = T(0);
-                if (__ballot(acc[s] != T(0))) v = wave_sum(acc[s]);
-                if (lane == 0) pacc[(c * nwz + gw) * kAcc + s] = v;
-            }
-        }
+        if (pacc) store_partials(acc, pacc + (c * nwz + gw) * kAcc, lane);
     }
     if (zstride == 0) {
         for (int k = 0; k < ZPT; ++k) {
@@ -659,6 +712,8 @@ __global__ __launch_bounds__(kBlock, (jac_min_waves<T, KIND>())) void k_jac(cons
             v = o.val;
             J[0] = o.dh;
             J[4] = o.dz;
+#pragma unroll
+            for (int q = 1; q < 5; ++q) o.p[q] *= o.ps;
             double d[3];
             if (!jac_contract<T>(r, o.p, d)) {
                 // the contraction cancels (small beta, small z): Leibniz-rule quadrature

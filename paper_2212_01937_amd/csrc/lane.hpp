@@ -64,21 +64,21 @@ __device__ __forceinline__ void build_u(const LaneConst<T> &k, T z, Geo<T, PAIR>
     }
     if (PAIR) {
         T ab;
-        const cx<T> w1 = mkc(z + k.w1re, k.w1im);
+        const T w1re = z + k.w1re;
         cx<T> X1;
         if (INV) {
             T iab;
-            X1 = csqrt_inv(w1, ab, iab);
+            X1 = csqrt_uim_inv(w1re, k.w1im2, k.hw1im, k.sw1im, ab, iab);
             const T i2 = iab * iab;
-            g.iX1re = w1.re * i2; g.iX1im = -w1.im * i2;
+            g.iX1re = w1re * i2; g.iX1im = -k.w1im * i2;
             g.iXprod *= iab;
         } else {
-            X1 = csqrt(w1, ab);
+            X1 = csqrt(mkc(w1re, k.w1im), ab);
         }
         g.X1re = X1.re; g.X1im = X1.im; g.X1abs = ab;
         // U_0 = Xt X_0 |Y_1|^2 + Yt Y_0 |X_1|^2
         g.T1_0 = g.Xt * g.X0 * k.y1abs2;
-        g.T2_0 = k.yt * k.y0 * ab;
+        g.T2_0 = k.yty0 * ab;
         g.U0 = g.T1_0 + g.T2_0;
         // U_1 = Xt Y_0 w + Yt X_0 conj(w),  w = X_1 conj(Y_1)
         cx<T> w = X1 * mkc(k.y1re, -k.y1im);
@@ -101,12 +101,12 @@ __device__ __forceinline__ void build_u(const LaneConst<T> &k, T z, Geo<T, PAIR>
             g.X2 = Fp<T>::sqrt(v2);
         }
         g.X1im = T(0); g.X1abs = T(0);
-        g.T1_0 = g.Xt * g.X0 * k.y1re * k.y2;
-        g.T2_0 = k.yt * k.y0 * g.X1re * g.X2;
-        g.T1_1re = g.Xt * g.X1re * k.y0 * k.y2;
-        g.T2_1re = k.yt * k.y1re * g.X0 * g.X2;
-        g.T1_2 = g.Xt * g.X2 * k.y0 * k.y1re;
-        g.T2_2 = k.yt * k.y2 * g.X0 * g.X1re;
+        g.T1_0 = g.Xt * g.X0 * k.y1y2;
+        g.T2_0 = k.yty0 * (g.X1re * g.X2);
+        g.T1_1re = g.Xt * g.X1re * k.y0y2;
+        g.T2_1re = k.yty1 * (g.X0 * g.X2);
+        g.T1_2 = g.Xt * g.X2 * k.y0y1;
+        g.T2_2 = k.yty2 * (g.X0 * g.X1re);
         g.T1_1im = g.T2_1im = T(0);
         g.U0 = g.T1_0 + g.T2_0;
         g.U1re = g.T1_1re + g.T2_1re;
@@ -121,7 +121,7 @@ __device__ __forceinline__ void build_u(const LaneConst<T> &k, T z, Geo<T, PAIR>
 template <typename T, bool PAIR> __device__ __forceinline__ T chi_hat(const LaneConst<T> &k, T z) {
     Geo<T, PAIR> g;
     build_u<T, PAIR>(k, z, g);
-    return k.pre * T(2) * z * rf_s<T, PAIR>(g.U0 * g.U0, g.va, g.vb);
+    return k.pre2 * z * rf_s<T, PAIR>(g.U0 * g.U0, g.va, g.vb);
 }
 
 // Arguments of the time coordinate's integrals (eqs. 3.8 / B.2): the U_m of build_u,
@@ -195,7 +195,7 @@ template <typename T, bool PAIR> __device__ __forceinline__ T t_hat(const CosmoR
     T rf, rj;
     rfj_s<T, PAIR>(a.V0, a.g.va, a.g.vb, a.W, rf, rj);
     T rc = rc_r(a.S, a.Q);
-    return k.pre * T(2) * z * (z2 * T(1.0 / 3.0) * k.pre3 * rj + rc + k.sigma * rf);
+    return k.pre2 * z * (z2 * T(1.0 / 3.0) * k.pre3 * rj + rc + k.sigma * rf);
 }
 
 // sqrt(Q(x)) at x2 = 1 + z and at x1 = 1 (products of the X_n / Y_n)
@@ -584,8 +584,8 @@ __device__ __forceinline__ T observable(int kind, const LaneConst<T> &k, T chi, 
     }
     // COSMO_MU: 5 log10(D_L / Mpc) + 25 (fn. 22)
     const T k5 = T(2.1714724095162591); // 5 / ln 10
-    T iS = Fp<T>::rcp(S);
-    d_chi = k5 * C * iS; d_ok = k5 * dS * iS; d_z = k5 * Fp<T>::rcp(x); d_h = -k5 * H0inv;
+    const T u = k5 * Fp<T>::rcp(S);
+    d_chi = C * u; d_ok = dS * u; d_z = k5 * Fp<T>::rcp(x); d_h = -k.k5hinv;
     return T(5) * Fp<T>::log10_fast(DL) + T(25);
 }
 
@@ -603,7 +603,9 @@ template <typename T> __device__ __forceinline__ T iEz(const LaneConst<T> &k, T 
 // (sigma, rho_0, rho_1[, rho_2]), by the chain rule through the Carlson
 // arguments: dR_F/d(U_m^2) = -R_D(., ., U_m^2)/6 (eq. 2.10).
 template <typename T, bool PAIR> struct ChiGrad {
-    T chi, dsig, dr0, dr1re, dr1im, dr2;
+    T chi;
+    T dsig, dr0, dr1re, dr1im, dr2; // the partials divided by kr (one factor shared by all four)
+    T kr;
     T iE; // 1/E(z), from the lane's geometry (E^2 = beta Xt^2 X_0^2 |X_1^2|^2)
 };
 
@@ -614,9 +616,10 @@ __device__ __forceinline__ void chi_grad(const LaneConst<T> &k, T z, ChiGrad<T, 
     T rf, rdx, rdz;
     cx<T> rdy;
     rfd_s<T, PAIR>(g.U0 * g.U0, g.va, g.vb, rf, rdx, rdy, rdz);
-    const T scale = k.pre * T(2) * z;
+    const T scale = k.pre2 * z;
     o.chi = scale * rf;
     o.iE = k.pre * g.iXprod;
+    o.kr = scale * T(-0.5);
     // G_m = dR_F/dU_m = -U_m R_D(., ., U_m^2)/3 ; a_m = G_m T1_m, b_m = G_m T2_m
     const T G0 = -g.U0 * rdx * T(1.0 / 3.0);
     const T a0 = G0 * g.T1_0, b0 = G0 * g.T2_0;
@@ -625,23 +628,23 @@ __device__ __forceinline__ void chi_grad(const LaneConst<T> &k, T z, ChiGrad<T, 
         cx<T> G1 = mkc(g.U1re, g.U1im) * rdy * T(-1.0 / 3.0);
         cx<T> a1 = G1 * mkc(g.T1_1re, g.T1_1im), b1 = G1 * mkc(g.T2_1re, g.T2_1im);
         const T A = a0 + T(2) * a1.re, B = b0 + T(2) * b1.re;
-        o.dsig = scale * T(-0.5) * ((T(1) + z) * A * g.iXt2 + B * k.iyt2);
-        o.dr0 = scale * T(-0.5) * ((a0 + B - b0) * g.iX02 + (b0 + A - a0) * k.iw0);
+        o.dsig = ((T(1) + z) * A * g.iXt2 + B * k.iyt2);
+        o.dr0 = ((a0 + B - b0) * g.iX02 + (b0 + A - a0) * k.iw0);
         const cx<T> iX1sq = mkc(g.iX1re, g.iX1im);
         const cx<T> iW1 = mkc(k.iw1re, k.iw1im);
         // (a1 + B - b1)/X1^2 + (b1 + A - a1)/W1
         cx<T> d1 = (a1 + B - b1) * iX1sq + (b1 + A - a1) * iW1;
-        o.dr1re = scale * T(-0.5) * d1.re;
-        o.dr1im = scale * T(-0.5) * d1.im;
+        o.dr1re = d1.re;
+        o.dr1im = d1.im;
         o.dr2 = T(0);
     } else {
         const T G1 = -g.U1re * rdy.re * T(1.0 / 3.0), G2 = -g.U2 * rdz * T(1.0 / 3.0);
         const T a1 = G1 * g.T1_1re, b1 = G1 * g.T2_1re, a2 = G2 * g.T1_2, b2 = G2 * g.T2_2;
         const T A = a0 + a1 + a2, B = b0 + b1 + b2;
-        o.dsig = scale * T(-0.5) * ((T(1) + z) * A * g.iXt2 + B * k.iyt2);
-        o.dr0 = scale * T(-0.5) * ((a0 + B - b0) * g.iX02 + (b0 + A - a0) * k.iw0);
-        o.dr1re = scale * T(-0.5) * ((a1 + B - b1) * g.iX1re + (b1 + A - a1) * k.iw1re);
-        o.dr2 = scale * T(-0.5) * ((a2 + B - b2) * g.iX2 + (b2 + A - a2) * k.iw2);
+        o.dsig = ((T(1) + z) * A * g.iXt2 + B * k.iyt2);
+        o.dr0 = ((a0 + B - b0) * g.iX02 + (b0 + A - a0) * k.iw0);
+        o.dr1re = ((a1 + B - b1) * g.iX1re + (b1 + A - a1) * k.iw1re);
+        o.dr2 = ((a2 + B - b2) * g.iX2 + (b2 + A - a2) * k.iw2);
         o.dr1im = T(0);
     }
 }
@@ -747,7 +750,7 @@ __device__ void t_grad(const CosmoRec &r, T z, TGrad<T, PAIR> &o) {
                     dRC_S * (-z2 * k.r0 * k.r1re));
     // through the Carlson arguments V_m(U_m)
     u_chain<T, PAIR>(k, g, z, dB_dV0, dB_dV1, dB_dV2, dsig, dr0, dr1, dr2);
-    const T scale = k.pre * T(2) * z;
+    const T scale = k.pre2 * z;
     const T Bv = c3 * rj + rc + s * rf;
     o.t = scale * Bv;
     o.dsig = scale * dsig;

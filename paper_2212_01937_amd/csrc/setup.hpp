@@ -68,6 +68,13 @@ template <typename T> struct LaneConst {
     T iyt2, iw0, iw1re, iw1im, iw2; // 1/Yt^2, 1/w_0, 1/w_1 (complex for a pair), 1/w_2
     T hinv;                 // 1/H0 [s Mpc/km]
     T beta;                 // E^2 = beta (1 - sigma x) Q(x)
+    // per-cosmology products the lanes would otherwise form on every evaluation
+    T pre2;                 // 2 beta^(-1/2)
+    T yty0;                 // Yt Y0
+    T y1y2, y0y2, y0y1;     // three real roots: Y1 Y2, Y0 Y2, Y0 Y1
+    T yty1, yty2;           //   Yt Y1, Yt Y2
+    T w1im2, hw1im, sw1im;  // pair: Im(w_1)^2, |Im(w_1)|/2, sign of Im(w_1) (+-1)
+    T k5hinv;               // (5 / ln 10) / H0: minus dmu/dH0
 };
 
 struct CosmoRec {
@@ -203,6 +210,10 @@ template <typename T> __device__ void fill_lane(LaneConst<T> &L, const LaneConst
     L.iyt2 = T(D.iyt2); L.iw0 = T(D.iw0); L.iw1re = T(D.iw1re); L.iw1im = T(D.iw1im); L.iw2 = T(D.iw2);
     L.hinv = T(D.hinv);
     L.beta = T(D.beta);
+    L.pre2 = T(D.pre2); L.yty0 = T(D.yty0);
+    L.y1y2 = T(D.y1y2); L.y0y2 = T(D.y0y2); L.y0y1 = T(D.y0y1); L.yty1 = T(D.yty1); L.yty2 = T(D.yty2);
+    L.w1im2 = T(D.w1im2); L.hw1im = T(D.hw1im); L.sw1im = T(D.sw1im);
+    L.k5hinv = T(D.k5hinv);
 }
 
 // dP/dtheta at x for theta = Om, OL, Or (Ok eliminated)
@@ -384,6 +395,12 @@ __device__ void setup_cosmo(const double *prm, CosmoRec &rec) {
     D.hinv = 1.0 / H0;
     D.beta = beta;
     D.pre = 1.0 / __builtin_sqrt(beta);
+    D.pre2 = 2.0 * D.pre;
+    D.yty0 = D.yt * D.y0;
+    D.y1y2 = D.y1re * D.y2; D.y0y2 = D.y0 * D.y2; D.y0y1 = D.y0 * D.y1re;
+    D.yty1 = D.yt * D.y1re; D.yty2 = D.yt * D.y2;
+    D.w1im2 = D.w1im * D.w1im; D.hw1im = 0.5 * __builtin_fabs(D.w1im); D.sw1im = D.w1im >= 0.0 ? 1.0 : -1.0;
+    D.k5hinv = 2.1714724095162591 * D.hinv;
     D.ok = Ok;
     D.sk = __builtin_sqrt(__builtin_fabs(Ok));
     D.dh = kC / H0;

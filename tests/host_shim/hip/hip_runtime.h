@@ -34,3 +34,5 @@ static inline float __builtin_amdgcn_logf(float x) { return host_prim(std::log2(
 static inline float __builtin_amdgcn_exp2f(float x) { return host_prim(std::exp2(x)); }
 static inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
 static inline double __builtin_amdgcn_rsq(double x) { return 1.0 / std::sqrt(x); }
+// A host thread is a wave of one lane.
+static inline unsigned long long __ballot(int p) { return p ? 1ull : 0ull; }
