@@ -32,9 +32,13 @@ template <> struct Fp<float> {
         return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
     }
     static __device__ __forceinline__ float atan(float x) { return atanf(x); }
-    static __device__ __forceinline__ float sin(float x) { return sinf(x); }
-    static __device__ __forceinline__ float cos(float x) { return cosf(x); }
     static __device__ __forceinline__ float nan() { return __builtin_nanf(""); }
+    static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    static __device__ __forceinline__ float rint(float x) { return __builtin_rintf(x); }
+    // pi/2 in three parts (P1 + P2 + P3 = pi/2 to about 1e-23) and 2/pi, for sincos
+    static constexpr float hp1 = 1.5707963705062866f, hp2 = -4.371138828673793e-08f, hp3 = -1.7151245100058819e-15f;
+    static constexpr float two_over_pi = 0.6366197723675814f;
+    static constexpr int sin_terms = 4, cos_terms = 5; // sin to r^9, cos to r^10
     static __device__ __forceinline__ float inf() { return __builtin_inff(); }
     // Duplication stopping thresholds: iterate while max|A0 - x_i| 4^-m > tau |A_m|.
     // 7th-order tails (R_F, R_C): remainder ~ tau^8 / 4; 5th-order (R_D, R_J): ~ tau^6.
@@ -69,9 +73,12 @@ template <> struct Fp<double> {
     static __device__ __forceinline__ double log10_fast(double x) { return ::log10(x); }
     static __device__ __forceinline__ double exp_fast(double x) { return ::exp(x); }
     static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
-    static __device__ __forceinline__ double sin(double x) { return ::sin(x); }
-    static __device__ __forceinline__ double cos(double x) { return ::cos(x); }
     static __device__ __forceinline__ double nan() { return __builtin_nan(""); }
+    static __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+    static __device__ __forceinline__ double rint(double x) { return __builtin_rint(x); }
+    static constexpr double hp1 = 1.5707963267948966, hp2 = 6.123233995736766e-17, hp3 = -1.4973849048591698e-33;
+    static constexpr double two_over_pi = 0.6366197723675814;
+    static constexpr int sin_terms = 8, cos_terms = 8; // sin to r^17, cos to r^16
     static __device__ __forceinline__ double inf() { return __builtin_inf(); }
     static constexpr double tau7 = 0.0121;
     static constexpr double tau5 = 0.0028;
@@ -79,6 +86,39 @@ template <> struct Fp<double> {
     static constexpr double rc_series_max = 0.01;
     static constexpr int rc_series_terms = 9;
 };
+
+// sin x and cos x together, for |x| < 2^16 (NaN beyond; the curvature transform's
+// arguments sqrt|Ok| chi stay within a few pi).  Cody-Waite reduction: k = rint(2x/pi),
+// r = x - k pi/2 with pi/2 in three parts (each step one FMA), so |r| <= pi/4 up to the
+// rounding of k; then the Taylor polynomials of sin r and cos r, truncated where the
+// first omitted term at |r| = pi/4 is below the type's rounding (FP32: 2e-9 for sin to
+// r^9, 1e-10 for cos to r^10; FP64: 1e-19, 2e-18), and the quadrant k mod 4.  No
+// large-argument reduction (its tables would sit in registers across the lane loops).
+template <typename T> __device__ __forceinline__ void sincos_red(T x, T &s, T &c) {
+    const T k = Fp<T>::rint(x * Fp<T>::two_over_pi);
+    T r = Fp<T>::fma(-k, Fp<T>::hp1, x);
+    r = Fp<T>::fma(-k, Fp<T>::hp2, r);
+    r = Fp<T>::fma(-k, Fp<T>::hp3, r);
+    const T r2 = r * r;
+    // Horner from the top: sin r = r (1 - r^2/3! + r^4/5! - ...), cos r = 1 - r^2/2! + ...
+    double fs[Fp<T>::sin_terms + 1], fc[Fp<T>::cos_terms + 1];
+    fs[0] = 1.0; fc[0] = 1.0;
+#pragma unroll
+    for (int n = 1; n <= Fp<T>::sin_terms; ++n) fs[n] = -fs[n - 1] / double((2 * n) * (2 * n + 1));
+#pragma unroll
+    for (int n = 1; n <= Fp<T>::cos_terms; ++n) fc[n] = -fc[n - 1] / double((2 * n - 1) * (2 * n));
+    T ps = T(fs[Fp<T>::sin_terms]), pc = T(fc[Fp<T>::cos_terms]);
+#pragma unroll
+    for (int n = Fp<T>::sin_terms - 1; n >= 0; --n) ps = ps * r2 + T(fs[n]);
+#pragma unroll
+    for (int n = Fp<T>::cos_terms - 1; n >= 0; --n) pc = pc * r2 + T(fc[n]);
+    const T sr = r * ps, cr = pc;
+    const int q = (int)k & 3;
+    const T sa = (q & 1) ? cr : sr, ca = (q & 1) ? sr : cr;
+    s = (q & 2) ? -sa : sa;
+    c = ((q + 1) & 2) ? -ca : ca;
+    if (!(Fp<T>::abs(x) < T(65536))) s = c = Fp<T>::nan();
+}
 
 template <typename T> struct cx {
     T re, im;

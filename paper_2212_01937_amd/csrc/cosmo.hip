@@ -70,22 +70,29 @@ __device__ __forceinline__ T eval_kind(const CosmoRec &r, T z, bool &used_gl) {
     return observable<T>(KIND, k, chi, z, T(0), a, b, c, d);
 }
 
+// Block index -> (cosmology tile, z block).
+__device__ __forceinline__ void block_tile(int64_t nzb, int64_t &tile, int64_t &zb) {
+    const int64_t b = blockIdx.x;
+    tile = b / nzb;
+    zb = b - tile * nzb;
+}
+
 template <typename T, int KIND>
 __global__ __launch_bounds__(kBlock) void k_forward(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
                                                      const T *__restrict__ z, int64_t n_z, int64_t zstride,
                                                      T *__restrict__ out, int32_t *__restrict__ info,
                                                      int ct, int64_t nzb) {
-    const int64_t b = blockIdx.x;
-    const int64_t tile = b / nzb, zb = b - tile * nzb;
+    // grid: x = z block, y = cosmology tile (fewer than 65536 tiles, see tiling)
+    const int64_t tile = blockIdx.y, zb = blockIdx.x;
     const int64_t i = zb * kBlock + threadIdx.x;
     const bool active = i < n_z;
     const int64_t c0 = tile * ct;
     const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
-    const T zshared = (zstride == 0 && active) ? z[i] : T(0);
+    if (!active) return; // no cross-lane work below
+    const T zshared = zstride == 0 ? z[i] : T(0);
     const uint32_t i32 = (uint32_t)i; // n_z < 2^31 (checked on the host)
     for (int64_t c = c0; c < c1; ++c) {
         const CosmoRec &r = recs[c];
-        if (!active) continue;
         const T zz = zstride == 0 ? zshared : (z + c * zstride)[i32];
         T v;
         bool used_gl = false;
@@ -124,8 +131,8 @@ template <typename T, int KIND>
 __global__ __launch_bounds__(kBlock) void k_routes(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
                                                     const T *__restrict__ z, int64_t n_z, int64_t zstride,
                                                     unsigned long long *__restrict__ counts, int ct, int64_t nzb) {
-    const int64_t b = blockIdx.x;
-    const int64_t tile = b / nzb, zb = b - tile * nzb;
+    int64_t tile, zb;
+    block_tile(nzb, tile, zb);
     const int64_t i = zb * kBlock + threadIdx.x;
     const bool act = i < n_z;
     const int64_t c0 = tile * ct;
@@ -145,14 +152,14 @@ template <typename T> __global__ void k_fill_zero_u64(T *__restrict__ p, int64_t
 }
 
 // Observables between two redshifts (between.hpp): lane i of a cosmology evaluates the
-// pair (z1[i], z2[i]); grid and tiling as k_forward.
+// pair (z1[i], z2[i]); tiling as k_forward (a one-dimensional grid of tile-major blocks).
 template <typename T, int KIND>
 __global__ __launch_bounds__(kBlock) void k_between(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
                                                      const T *__restrict__ z1, const T *__restrict__ z2,
                                                      int64_t n_z, int64_t zstride, T *__restrict__ out,
                                                      int ct, int64_t nzb) {
-    const int64_t b = blockIdx.x;
-    const int64_t tile = b / nzb, zb = b - tile * nzb;
+    int64_t tile, zb;
+    block_tile(nzb, tile, zb);
     const int64_t i = zb * kBlock + threadIdx.x;
     if (i >= n_z) return;
     const int64_t c0 = tile * ct;
@@ -486,8 +493,8 @@ __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_vjp(
                                                  T *__restrict__ out, int32_t *__restrict__ info,
                                                  int ct, int64_t nzb) {
     __shared__ T gzl[ZPT * kBlock];
-    const int64_t b = blockIdx.x;
-    const int64_t tile = b / nzb, zb = b - tile * nzb;
+    int64_t tile, zb;
+    block_tile(nzb, tile, zb);
     const int64_t base = zb * (int64_t)(kBlock * ZPT) + threadIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t nwz = nzb * (kBlock / 64);           // wave partials per cosmology
@@ -589,8 +596,8 @@ __global__ __launch_bounds__(kBlock) void k_between_vjp(const CosmoRec *__restri
                                                         T *__restrict__ g2_part, T *__restrict__ out, int ct,
                                                         int64_t nzb) {
     __shared__ T gl1[ZPT * kBlock], gl2[ZPT * kBlock];
-    const int64_t b = blockIdx.x;
-    const int64_t tile = b / nzb, zb = b - tile * nzb;
+    int64_t tile, zb;
+    block_tile(nzb, tile, zb);
     const int64_t base = zb * (int64_t)(kBlock * ZPT) + threadIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t nwz = nzb * (kBlock / 64);
@@ -653,8 +660,8 @@ template <typename T, int KIND> constexpr int jac_min_waves() {
 // the coefficients (the check compares the size of the terms with their sum, which does
 // not depend on the precision of the contraction); FP64 lanes as root_contract.  Returns
 // false where the terms cancel by more than kJacCancel32 (FP32 only).
-template <typename T>
-__device__ __forceinline__ bool jac_contract(const CosmoRec &r, const T p[5], double d[3]) {
+template <typename T, typename D>
+__device__ __forceinline__ bool jac_contract(const CosmoRec &r, const T p[5], D d[3]) {
     if (sizeof(T) == 4) {
         bool ok = true;
 #pragma unroll
@@ -666,7 +673,7 @@ __device__ __forceinline__ bool jac_contract(const CosmoRec &r, const T p[5], do
                 sum += t;
                 mag += __builtin_fabsf(t);
             }
-            d[th] = sum;
+            d[th] = D(sum);
             ok = ok && (mag <= float(kJacCancel32) * __builtin_fabsf(sum));
         }
         return ok;
@@ -675,7 +682,7 @@ __device__ __forceinline__ bool jac_contract(const CosmoRec &r, const T p[5], do
 #pragma unroll
     for (int q = 0; q < 5; ++q) pd[q] = (double)p[q];
 #pragma unroll
-    for (int th = 0; th < 3; ++th) d[th] = root_contract(r, pd, th);
+    for (int th = 0; th < 3; ++th) d[th] = D(root_contract(r, pd, th));
     return true;
 }
 
@@ -684,19 +691,20 @@ __global__ __launch_bounds__(kBlock, (jac_min_waves<T, KIND>())) void k_jac(cons
                                                  const T *__restrict__ z, int64_t n_z, int64_t zstride,
                                                  T *__restrict__ out, T *__restrict__ jac, int32_t *__restrict__ info,
                                                  int ct, int64_t nzb) {
-    const int64_t b = blockIdx.x;
-    const int64_t tile = b / nzb, zb = b - tile * nzb;
+    // grid as k_forward
+    const int64_t tile = blockIdx.y, zb = blockIdx.x;
     const int64_t i = zb * kBlock + threadIdx.x;
     const bool active = i < n_z;
     const uint32_t i32 = (uint32_t)i; // n_z < 2^31 (checked on the host)
     const int64_t c0 = tile * ct;
     const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
     const int64_t plane = n_cosmo * n_z;
-    const T zshared = (zstride == 0 && active) ? z[i] : T(0);
-    constexpr bool fp32 = sizeof(T) == 4;
+    // no cross-lane work below: lanes past the end leave at once (which keeps the
+    // cosmology loop uniform)
+    if (!active) return;
+    const T zshared = zstride == 0 ? z[i] : T(0);
     for (int64_t c = c0; c < c1; ++c) {
         const CosmoRec &r = recs[c];
-        if (!active) continue;
         const T zz = zstride == 0 ? zshared : (z + c * zstride)[i32];
         T v, J[5];
         bool used_gl = false;
@@ -714,8 +722,8 @@ __global__ __launch_bounds__(kBlock, (jac_min_waves<T, KIND>())) void k_jac(cons
             J[4] = o.dz;
 #pragma unroll
             for (int q = 1; q < 5; ++q) o.p[q] *= o.ps;
-            double d[3];
-            if (!jac_contract<T>(r, o.p, d)) {
+            T d[3];
+            if (!jac_contract(r, o.p, d)) {
                 // the contraction cancels (small beta, small z): Leibniz-rule quadrature
                 T bv, g[3];
                 if (r.pair) gl_integral<T, true>(lane_of<T>(r), zz, KIND == COSMO_T ? 1 : 0, true, bv, g, 1);
@@ -724,7 +732,7 @@ __global__ __launch_bounds__(kBlock, (jac_min_waves<T, KIND>())) void k_jac(cons
                 for (int th = 0; th < 3; ++th) d[th] = g[th];
             }
 #pragma unroll
-            for (int th = 0; th < 3; ++th) J[1 + th] = fp32 ? T(o.s) * T(d[th]) - o.dok : T((double)o.s * d[th] - (double)o.dok);
+            for (int th = 0; th < 3; ++th) J[1 + th] = o.s * d[th] - o.dok;
         } else {
             LaneGrad<T> o;
             if (r.pair) lane_grad<T, KIND, true>(r, zz, o, used_gl);
@@ -736,7 +744,7 @@ __global__ __launch_bounds__(kBlock, (jac_min_waves<T, KIND>())) void k_jac(cons
             if (o.quad) {
 #pragma unroll
                 for (int th = 0; th < 3; ++th) d[th] = o.q[th];
-            } else if (!jac_contract<T>(r, o.p, d) && KIND != COSMO_X) {
+            } else if (!jac_contract(r, o.p, d) && KIND != COSMO_X) {
                 T bv, g[3];
                 if (r.pair) gl_integral<T, true>(lane_of<T>(r), zz, KIND == COSMO_T ? 1 : 0, true, bv, g, 1);
                 else gl_integral<T, false>(lane_of<T>(r), zz, KIND == COSMO_T ? 1 : 0, true, bv, g, 1);
@@ -961,6 +969,9 @@ Tiling tiling(int64_t n_cosmo, int64_t n_z, int zpt = 1) {
     if (t.nzb < 1) t.nzb = 1;
     int64_t want = (n_cosmo * t.nzb * zpt) / 8192;
     t.ct = (int)(want < 1 ? 1 : (want > 16 ? 16 : want));
+    // at most 65535 tiles (the forward and Jacobian grids put them on the y axis)
+    const int64_t ct_min = (n_cosmo + 65534) / 65535;
+    if (t.ct < ct_min) t.ct = (int)ct_min;
     t.ntile = (n_cosmo + t.ct - 1) / t.ct;
     t.nblocks = t.ntile * t.nzb;
     return t;
@@ -1055,7 +1066,7 @@ template <typename T>
 int launch_forward(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int64_t n_z, int64_t zstride,
                    T *out, int32_t *info, hipStream_t s) {
     Tiling t = tiling(n_cosmo, n_z);
-    dim3 grid((unsigned)t.nblocks), block(kBlock);
+    dim3 grid((unsigned)t.nzb, (unsigned)t.ntile), block(kBlock);
 #define COSMO_FWD(K) hipLaunchKernelGGL((k_forward<T, K>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, out, info, t.ct, t.nzb)
     switch (kind) {
     case COSMO_DC: COSMO_FWD(COSMO_DC); break;
@@ -1115,7 +1126,7 @@ template <typename T>
 int launch_jac(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int64_t n_z, int64_t zstride, T *out,
                T *jac, int32_t *info, hipStream_t s) {
     Tiling t = tiling(n_cosmo, n_z);
-    dim3 grid((unsigned)t.nblocks), block(kBlock);
+    dim3 grid((unsigned)t.nzb, (unsigned)t.ntile), block(kBlock);
 #define COSMO_JAC(K) \
     hipLaunchKernelGGL((k_jac<T, K>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, out, jac, info, t.ct, t.nzb)
     switch (kind) {

@@ -486,8 +486,9 @@ __device__ __forceinline__ void sinn(T chi, T ok, T sk, T &S, T &C, T &dS) {
         S = T(0.5) * (e - ie) * Fp<T>::rcp(sk);
         C = T(0.5) * (e + ie);
     } else {
-        S = Fp<T>::sin(sk * chi) * Fp<T>::rcp(sk);
-        C = Fp<T>::cos(sk * chi);
+        T sn;
+        sincos_red(sk * chi, sn, C);
+        S = sn * Fp<T>::rcp(sk);
     }
     dS = (chi * C - S) * Fp<T>::rcp(T(2) * ok);
 }
@@ -533,8 +534,7 @@ __device__ __forceinline__ void vol_g(T chi, T ok, T sk, T &G, T &dG) {
         s2 = T(0.5) * (e - ie);
         c2 = T(0.5) * (e + ie);
     } else {
-        s2 = Fp<T>::sin(x2);
-        c2 = Fp<T>::cos(x2);
+        sincos_red(x2, s2, c2);
     }
     const T ia = Fp<T>::rcp(a), aok = Fp<T>::abs(ok);
     const T h = T(0.5) * s2 * ia;
