@@ -161,3 +161,16 @@ extern "C" void host_between_grad(const double *prm, int kind, int dt, const dou
         }
     }
 }
+
+// sincos_red (the curvature transform's sin and cos) for n arguments; dt: 0 FP32, 1 FP64.
+extern "C" void host_sincos(int dt, const double *x, long n, double *s, double *c) {
+    for (long i = 0; i < n; ++i) {
+        if (dt == 0) {
+            float sf, cf;
+            sincos_red<float>((float)x[i], sf, cf);
+            s[i] = sf; c[i] = cf;
+        } else {
+            sincos_red<double>(x[i], s[i], c[i]);
+        }
+    }
+}
