@@ -27,8 +27,8 @@ namespace cosmo {
 // ---------------------------------------------------------------- tails
 template <typename T> __device__ __forceinline__ T rf_tail(T E2, T E3) {
     // 1 - E2/10 + E3/14 + E2^2/24 - 3E2E3/44 - 5E2^3/208 + 3E3^2/104 + E2^2E3/16
-    return T(1) + E2 * (T(-0.1) + E2 * (T(1.0 / 24.0) - T(5.0 / 208.0) * E2)) +
-           E3 * (T(1.0 / 14.0) + T(3.0 / 104.0) * E3 - T(3.0 / 44.0) * E2 + T(1.0 / 16.0) * E2 * E2);
+    return T(1) + E2 * (kc<T>(-0.1) + E2 * (kc<T>(1.0 / 24.0) - kc<T>(5.0 / 208.0) * E2)) +
+           E3 * (kc<T>(1.0 / 14.0) + kc<T>(3.0 / 104.0) * E3 - kc<T>(3.0 / 44.0) * E2 + kc<T>(1.0 / 16.0) * E2 * E2);
 }
 template <typename T> __device__ __forceinline__ cx<T> rf_tail(cx<T> E2, cx<T> E3) {
     cx<T> a = (E2 * T(-5.0 / 208.0)) + T(1.0 / 24.0);
@@ -38,8 +38,8 @@ template <typename T> __device__ __forceinline__ cx<T> rf_tail(cx<T> E2, cx<T> E
 }
 // Partial derivatives of rf_tail in E2 and E3.
 template <typename T> __device__ __forceinline__ void rf_tail_grad(T E2, T E3, T &t2, T &t3) {
-    t2 = T(-0.1) + E2 * (T(1.0 / 12.0) - T(15.0 / 208.0) * E2) + E3 * (T(-3.0 / 44.0) + T(0.125) * E2);
-    t3 = T(1.0 / 14.0) + T(3.0 / 52.0) * E3 + E2 * (T(-3.0 / 44.0) + T(1.0 / 16.0) * E2);
+    t2 = kc<T>(-0.1) + E2 * (kc<T>(1.0 / 12.0) - kc<T>(15.0 / 208.0) * E2) + E3 * (kc<T>(-3.0 / 44.0) + kc<T>(0.125) * E2);
+    t3 = kc<T>(1.0 / 14.0) + kc<T>(3.0 / 52.0) * E3 + E2 * (kc<T>(-3.0 / 44.0) + kc<T>(1.0 / 16.0) * E2);
 }
 // 1 - 3E2/14 + E3/6 + 9E2^2/88 - 3E4/22 - 9E2E3/52 + 3E5/26
 template <typename T> __device__ __forceinline__ T rj_tail(T E2, T E3, T E4, T E5) {
@@ -436,8 +436,8 @@ __device__ __forceinline__ void rfd_tails(T AF0, T x0, T a0, T b0, T AF, T f, T 
     T t2, t3;
     rf_tail_grad(E2, E3, t2, t3);
     const T sc = g * ra; // 4^-m A^(-3/2)
-    const T c0 = tF + E2 * (T(4) * t2 - T(2) * t3) + T(6) * t3 * E3;
-    const T m2 = T(-6) * t2, m3 = T(6) * t3;
+    const T c0 = tF + E2 * (T(4) * t2 - T(2) * t3) + kc<T>(6.0) * t3 * E3;
+    const T m2 = kc<T>(-6.0) * t2, m3 = kc<T>(6.0) * t3;
     tx = sc * (c0 + m2 * X + m3 * q); // P_x = Y Z = q
     if (PAIR) {
         // Y = u - i v, Z = conj(Y); P_y = X Z

@@ -10,6 +10,25 @@
 
 namespace cosmo {
 
+// A coefficient of the lane loops' polynomials.  FP32: the literal itself (an inline
+// operand).  FP64: a 64-bit literal is never an inline operand, so the compiler would
+// keep every coefficient of a loop body in a pair of vector registers across the loop
+// (some seventy of them in the adjoint); the empty asm statement makes the value opaque
+// at its use, so it is materialised there into scalar registers (two scalar moves), the
+// operand kind an FP64 vector instruction takes directly.
+#ifndef COSMO_KC_OPAQUE // (the host build of the tests defines it away)
+#define COSMO_KC_OPAQUE(c) asm volatile("" : "+s"(c))
+#endif
+template <typename T> __device__ __forceinline__ T kc(double v) {
+    if constexpr (sizeof(T) == 8) {
+        double c = v;
+        COSMO_KC_OPAQUE(c);
+        return c;
+    } else {
+        return T(v);
+    }
+}
+
 template <typename T> struct Fp;
 
 template <> struct Fp<float> {
@@ -70,8 +89,45 @@ template <> struct Fp<double> {
     static __device__ __forceinline__ double log(double x) { return ::log(x); }
     static __device__ __forceinline__ double log1p(double x) { return ::log1p(x); }
     static __device__ __forceinline__ double log10(double x) { return ::log10(x); }
-    static __device__ __forceinline__ double log10_fast(double x) { return ::log10(x); }
-    static __device__ __forceinline__ double exp_fast(double x) { return ::exp(x); }
+    // log10 and exp of the lane loops (mu; the closed forms of the curvature transform)
+    // with their coefficients through kc (see there): log x = e ln 2 + log m for
+    // x = m 2^e, m in [sqrt(1/2), sqrt(2)), with log m = 2 atanh(s), s = (m - 1)/(m + 1),
+    // |s| <= 0.172, by its series to s^21 (first omitted term below 1e-18 relative);
+    // exp x = 2^k e^r with r = x - k ln 2 (ln 2 in two parts), |r| <= 0.347, by the
+    // Taylor series to r^13 (first omitted term below 5e-18).  x = 0 gives -inf, x < 0
+    // NaN, as the library functions.
+    static __device__ __forceinline__ double log10_fast(double x) {
+        double m = __builtin_amdgcn_frexp_mant(x);
+        int e = __builtin_amdgcn_frexp_exp(x);
+        if (m < 0.70710678118654752) {
+            m *= 2.0;
+            e -= 1;
+        }
+        const double s = (m - 1.0) * rcp(m + 1.0), s2 = s * s;
+        double p = kc<double>(1.0 / 21.0);
+#pragma unroll
+        for (int n = 9; n >= 1; --n) p = p * s2 + kc<double>(1.0 / (2 * n + 1));
+        const double lm = 2.0 * s * (p * s2 + 1.0);
+        const double ln = __builtin_fma((double)e, kc<double>(0.69314718055994529), __builtin_fma((double)e, kc<double>(2.3190468138462996e-17), lm));
+        double r = ln * kc<double>(0.43429448190325182);
+        if (!(x > 0.0)) r = x == 0.0 ? -__builtin_inf() : __builtin_nan("");
+        if (x == __builtin_inf()) r = x;
+        return r;
+    }
+    static __device__ __forceinline__ double exp_fast(double x) {
+        const double k = __builtin_rint(x * kc<double>(1.4426950408889634));
+        const double r = __builtin_fma(-k, kc<double>(2.3190468138462996e-17), __builtin_fma(-k, kc<double>(0.69314718055994529), x));
+        double c[14];
+        c[0] = 1.0;
+#pragma unroll
+        for (int n = 1; n <= 13; ++n) c[n] = c[n - 1] / n;
+        double p = kc<double>(c[13]);
+#pragma unroll
+        for (int n = 12; n >= 2; --n) p = p * r + kc<double>(c[n]);
+        p = p * r + 1.0;
+        p = p * r + 1.0;
+        return __builtin_amdgcn_ldexp(p, (int)k);
+    }
     static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
     static __device__ __forceinline__ double nan() { return __builtin_nan(""); }
     static __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -107,11 +163,11 @@ template <typename T> __device__ __forceinline__ void sincos_red(T x, T &s, T &c
     for (int n = 1; n <= Fp<T>::sin_terms; ++n) fs[n] = -fs[n - 1] / double((2 * n) * (2 * n + 1));
 #pragma unroll
     for (int n = 1; n <= Fp<T>::cos_terms; ++n) fc[n] = -fc[n - 1] / double((2 * n - 1) * (2 * n));
-    T ps = T(fs[Fp<T>::sin_terms]), pc = T(fc[Fp<T>::cos_terms]);
+    T ps = kc<T>(fs[Fp<T>::sin_terms]), pc = kc<T>(fc[Fp<T>::cos_terms]);
 #pragma unroll
-    for (int n = Fp<T>::sin_terms - 1; n >= 0; --n) ps = ps * r2 + T(fs[n]);
+    for (int n = Fp<T>::sin_terms - 1; n >= 0; --n) ps = ps * r2 + (n == 0 ? T(1) : kc<T>(fs[n]));
 #pragma unroll
-    for (int n = Fp<T>::cos_terms - 1; n >= 0; --n) pc = pc * r2 + T(fc[n]);
+    for (int n = Fp<T>::cos_terms - 1; n >= 0; --n) pc = pc * r2 + (n == 0 ? T(1) : kc<T>(fc[n]));
     const T sr = r * ps, cr = pc;
     const int q = (int)k & 3;
     const T sa = (q & 1) ? cr : sr, ca = (q & 1) ? sr : cr;

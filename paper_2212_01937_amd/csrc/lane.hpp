@@ -460,25 +460,22 @@ __device__ __forceinline__ void sinn(T chi, T ok, T sk, T &S, T &C, T &dS) {
         // 2.5e-8 in S/chi, 2.8e-7 in C and 7.5e-7 relative in dS (C and dS enter only
         // derivatives)
         constexpr int N = sizeof(T) == 4 ? 4 : 10;
-        T s = T(0), c = T(0), d = T(0);
-        // Horner in t from the top: S/chi = sum t^n/(2n+1)!, C = sum t^n/(2n)!,
-        // dS/(chi^3) = sum_{n>=1} n t^(n-1)/(2n+1)!
-        T fs[N + 1], fc[N + 1];
-        fs[0] = T(1); fc[0] = T(1);
+        // u(t) = S/chi = sum a_n t^n with a_n = 1/(2n+1)!, and u'(t) from the same
+        // Horner pass (one set of coefficients): C = dS/dchi = u + 2 t u' and
+        // dS/dOk = chi^3 u'
+        T a[N + 1];
+        a[0] = T(1);
 #pragma unroll
-        for (int n = 1; n <= N; ++n) {
-            fs[n] = fs[n - 1] / T((2 * n) * (2 * n + 1));
-            fc[n] = fc[n - 1] / T((2 * n - 1) * (2 * n));
-        }
+        for (int n = 1; n <= N; ++n) a[n] = a[n - 1] / T((2 * n) * (2 * n + 1));
+        T u = kc<T>(a[N]), du = T(0);
 #pragma unroll
-        for (int n = N; n >= 0; --n) {
-            s = s * t + fs[n];
-            c = c * t + fc[n];
-            if (n >= 1) d = d * t + T(n) * fs[n];
+        for (int n = N - 1; n >= 0; --n) {
+            du = du * t + u;
+            u = u * t + (n == 0 ? T(1) : kc<T>(a[n]));
         }
-        S = chi * s;
-        C = c;
-        dS = chi * chi * chi * d;
+        S = chi * u;
+        C = u + T(2) * t * du;
+        dS = chi * chi * chi * du;
         return;
     }
     if (ok > T(0)) {

@@ -36,3 +36,8 @@ static inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
 static inline double __builtin_amdgcn_rsq(double x) { return 1.0 / std::sqrt(x); }
 // A host thread is a wave of one lane.
 static inline unsigned long long __ballot(int p) { return p ? 1ull : 0ull; }
+static inline double __builtin_amdgcn_frexp_mant(double x) { int e; return std::frexp(x, &e); }
+static inline int __builtin_amdgcn_frexp_exp(double x) { int e; std::frexp(x, &e); return e; }
+static inline double __builtin_amdgcn_ldexp(double x, int e) { return std::ldexp(x, e); }
+// the opaque-constant hint of the device build (cmath.hpp: kc) has no host meaning
+#define COSMO_KC_OPAQUE(c) ((void)0)

@@ -174,3 +174,11 @@ extern "C" void host_sincos(int dt, const double *x, long n, double *s, double *
         }
     }
 }
+
+// The FP64 lane path's log10 and exp (mu and the curvature transform's closed forms).
+extern "C" void host_log10_exp(const double *x, long n, double *lg, double *ex) {
+    for (long i = 0; i < n; ++i) {
+        lg[i] = Fp<double>::log10_fast(x[i]);
+        ex[i] = Fp<double>::exp_fast(x[i]);
+    }
+}

@@ -349,3 +349,34 @@ def test_sincos_reduction_matches_library(libs):
     libs["exact"].host_sincos(1, big.ctypes.data_as(ctypes.c_void_p), ctypes.c_long(3),
                               s.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p))
     assert np.all(np.isnan(s)) and np.all(np.isnan(c))
+
+
+def test_fp64_log10_and_exp_match_library(libs):
+    """The FP64 lanes' log10 (mu = 5 log10(D_L/Mpc) + 25, fn. 22) and exp (sinh of the
+    curvature transform for Ok0 > 0, sec. 2.1.1), written as polynomials (atanh series of
+    the reduced mantissa; Taylor series after reduction by ln 2): against numpy within
+    4 ulp relative (exp: on the curvature transform's range; log10: on distances from
+    1e-3 to 1e6 Mpc and beyond, subnormal included), the special values as the library."""
+    rng = np.random.default_rng(29)
+    x = np.concatenate([10.0 ** rng.uniform(-3, 6, 5000), 10.0 ** rng.uniform(-300, 300, 500),
+                        [1.0, 2.0, 0.5, np.sqrt(0.5), np.sqrt(2.0), 10.0, 1e-310]])
+    lg = np.zeros(x.size)
+    ex = np.zeros(x.size)
+    libs["exact"].host_log10_exp(x.ctypes.data_as(ctypes.c_void_p), ctypes.c_long(x.size),
+                                 lg.ctypes.data_as(ctypes.c_void_p), ex.ctypes.data_as(ctypes.c_void_p))
+    ref = np.log10(x)
+    err = np.abs(lg - ref) / np.maximum(np.abs(ref), 1.0)
+    assert err.max() <= 4 * np.finfo(float).eps, float(err.max())
+    xe = np.concatenate([rng.uniform(-30.0, 30.0, 5000), [0.0, 1.0, -1.0, 700.0]])
+    lg = np.zeros(xe.size)
+    ex = np.zeros(xe.size)
+    libs["exact"].host_log10_exp(xe.ctypes.data_as(ctypes.c_void_p), ctypes.c_long(xe.size),
+                                 lg.ctypes.data_as(ctypes.c_void_p), ex.ctypes.data_as(ctypes.c_void_p))
+    e = np.abs(ex / np.exp(xe) - 1)
+    assert e.max() <= 4 * np.finfo(float).eps, float(e.max())
+    sp = np.array([0.0, -1.0, np.inf, np.nan])
+    lg = np.zeros(4)
+    ex = np.zeros(4)
+    libs["exact"].host_log10_exp(sp.ctypes.data_as(ctypes.c_void_p), ctypes.c_long(4),
+                                 lg.ctypes.data_as(ctypes.c_void_p), ex.ctypes.data_as(ctypes.c_void_p))
+    assert lg[0] == -np.inf and np.isnan(lg[1]) and lg[2] == np.inf and np.isnan(lg[3])
