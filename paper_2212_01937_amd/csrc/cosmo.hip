@@ -476,12 +476,13 @@ __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T 
     }
 }
 
-// Occupancy: the FP32 comoving-distance-family adjoint is held to 64 VGPRs, eight waves
-// per SIMD (the root-chain loop fits; measured 3-6% faster on the headline workload than
-// six waves at 80 VGPRs); the others (T, and X with its FP64 geometry) keep the
-// compiler's allocation.
+// Occupancy: the comoving-distance-family adjoint is held to 64 VGPRs, eight waves per
+// SIMD, on the FP32 path (the root-chain loop fits; measured 3-6% faster on the headline
+// workload than six waves at 80 VGPRs) and to 128, four waves, on the FP64 path (its
+// coefficients in scalar registers, see kc); T, X and the volume keep the compiler's
+// allocation.
 template <typename T, int KIND> constexpr int adjoint_min_waves() {
-    return (sizeof(T) == 4 && KIND != COSMO_T && KIND != COSMO_X) ? 8 : 1;
+    return (KIND == COSMO_T || KIND == COSMO_X || KIND == COSMO_VC) ? 1 : (sizeof(T) == 4 ? 8 : 4);
 }
 
 template <typename T, int KIND, int ZPT, bool LIKE>
