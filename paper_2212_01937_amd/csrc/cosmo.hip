@@ -650,10 +650,11 @@ __global__ __launch_bounds__(kBlock) void k_between_vjp(const CosmoRec *__restri
 // Materialised Jacobian: per lane the observable and d out / d(H0, Om0, OL0, Or0, z),
 // written as five planes jac[q][c][i]; the root-space partials are contracted with the
 // root Jacobian per lane, in FP64.  Grid as k_forward.
-// Occupancy of the materialised Jacobian: the FP32 comoving-distance family at 80 VGPRs
-// (six waves); the others keep the compiler's allocation.
+// Occupancy of the materialised Jacobian: the FP32 comoving-distance family at 64 VGPRs
+// (eight waves; the lane fits without spilling); the others keep the compiler's
+// allocation.
 template <typename T, int KIND> constexpr int jac_min_waves() {
-    return (sizeof(T) == 4 && KIND != COSMO_T && KIND != COSMO_X) ? 6 : 1;
+    return (sizeof(T) == 4 && KIND != COSMO_T && KIND != COSMO_X) ? 8 : 1;
 }
 
 // The lane's partials contracted with the root Jacobian (app. A) per parameter, with the
@@ -667,12 +668,13 @@ __device__ __forceinline__ bool jac_contract(const CosmoRec &r, const T p[5], D 
         bool ok = true;
 #pragma unroll
         for (int th = 0; th < 3; ++th) {
+            // sum of the terms and of their magnitudes, one FMA each (|p c| = |p| |c|)
             float sum = 0.0f, mag = 0.0f;
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
-                const float t = (float)p[q] * r.jc32[q][th];
-                sum += t;
-                mag += __builtin_fabsf(t);
+                const float c = r.jc32[q][th];
+                sum = __builtin_fmaf((float)p[q], c, sum);
+                mag = __builtin_fmaf(__builtin_fabsf((float)p[q]), __builtin_fabsf(c), mag);
             }
             d[th] = D(sum);
             ok = ok && (mag <= float(kJacCancel32) * __builtin_fabsf(sum));
