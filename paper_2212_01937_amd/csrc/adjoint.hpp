@@ -17,7 +17,9 @@ namespace cosmo {
 // COSMO_INFO_NEAR_MULTIROOT bits).
 __device__ __forceinline__ bool direct_mode(int kind, const CosmoRec &r, bool fp32) {
     if (kind == COSMO_X) return true;
-    return r.minsep < (fp32 ? 2e-2 : 1e-4);
+    // minsep below 2e-2 (FP32) / 1e-4 (FP64), as the set-up recorded it in the info bits
+    // (an integer test on the record instead of an FP64 compare against a literal)
+    return (r.info & (fp32 ? COSMO_INFO_NEAR_MULTIROOT_F32 : COSMO_INFO_NEAR_MULTIROOT)) != 0;
 }
 
 // Near-multiple roots (direct mode): chi and its parameter gradient by quadrature in

@@ -319,6 +319,10 @@ template <typename T> __device__ __forceinline__ T wave_sum8(const T v[8], int l
 // slots 0-6 and the loss by wave_sum8 (its lanes 0-3 and 8-11 store them), the three
 // quadrature slots one by one, skipped when no lane of the wave touched them.
 template <typename T> __device__ __forceinline__ void store_partials(const T acc[kAcc], T *__restrict__ row, int lane) {
+    // the lane masks and offsets below are derived here, once per call (an opaque copy of
+    // the lane index keeps the compiler from hoisting them out of the cosmology loop,
+    // where they would occupy registers across the lane loops and spill)
+    asm volatile("" : "+v"(lane));
     const T v8[8] = {acc[0], acc[1], acc[2], acc[3], acc[4], acc[5], acc[6], acc[kAccLoss]};
     const T tot = wave_sum8(v8, lane);
     if ((lane & 0x34) == 0) {
