@@ -23,6 +23,8 @@
  *    E^2(z) = Or0 (1+z)^4 + Om0 (1+z)^3 + Ok0 (1+z)^2 + OL0 (eq. 2.2).
  *  - Redshifts z (> -1; all outputs are for the interval from 0 to z) and the
  *    outputs use the dtype argument: COSMO_F32 (float) or COSMO_F64 (double).
+ *    Rows hold fewer than 2^29 - 2048 redshifts (n_z; the kernels address a row by
+ *    32-bit byte offsets): COSMO_E_ARG beyond.
  *    Whatever the dtype, the per-cosmology root finding and the root Jacobian run
  *    in FP64.  Parameter-gradient reductions: each wave sums its lanes' terms (at
  *    most 512: 64 lanes x 8 redshifts) in the dtype; the sums over waves and the

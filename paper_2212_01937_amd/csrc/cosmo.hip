@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(const CosmoRec *__restrict__
     const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
     if (!active) return; // no cross-lane work below
     const T zshared = zstride == 0 ? z[i] : T(0);
-    const uint32_t i32 = (uint32_t)i; // n_z < 2^31 (checked on the host)
+    const uint32_t i32 = (uint32_t)i; // n_z < 2^29 (checked on the host)
     for (int64_t c = c0; c < c1; ++c) {
         const CosmoRec &r = recs[c];
         const T zz = zstride == 0 ? zshared : (z + c * zstride)[i32];
@@ -377,6 +377,16 @@ __device__ __forceinline__ void vjp_cosmo_general(const CosmoRec &r, int64_t c, 
     }
 }
 
+// Element i of a row through a 32-bit byte offset (a row holds fewer than 2^32 bytes:
+// n_z < 2^29, checked on the host), so that an address is the row's scalar base plus one
+// vector offset, with no 64-bit address arithmetic per lane.
+template <typename T> __device__ __forceinline__ T *row_at(T *row, uint32_t i) {
+    return (T *)((char *)row + i * (uint32_t)sizeof(T));
+}
+template <typename T> __device__ __forceinline__ const T *row_at(const T *row, uint32_t i) {
+    return (const T *)((const char *)row + i * (uint32_t)sizeof(T));
+}
+
 // The root-chain lanes (lane_grad_root) run in a loop of their own, which touches only
 // the slots that route writes (0..6, and the loss); FP32 lanes below kSmallZ32 are
 // marked and run afterwards in a second pass that only waves holding such lanes enter
@@ -393,7 +403,7 @@ __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T 
                                                    info);
         return;
     }
-    // row pointers of this cosmology (uniform) and 32-bit lane offsets (n_z < 2^31 is
+    // row pointers of this cosmology (uniform) and 32-bit lane offsets (n_z < 2^29 is
     // checked on the host): the loads and stores take a scalar base and a vector offset
     const uint32_t i0 = (uint32_t)base, nz = (uint32_t)n_z;
     const T *__restrict__ zr = z + c * zstride;
@@ -409,9 +419,9 @@ __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T 
     uint32_t deferred = 0;
     T zn = T(0), cn = T(0), vn = T(0);
     if (pre && i0 < nz) {
-        zn = zr[i0];
-        cn = LIKE ? cr[i0] : __builtin_nontemporal_load(cr + i0);
-        if (LIKE) vn = vr[i0];
+        zn = *row_at(zr, i0);
+        cn = LIKE ? *row_at(cr, i0) : __builtin_nontemporal_load(row_at(cr, i0));
+        if (LIKE) vn = *row_at(vr, i0);
     }
 #pragma unroll 1
     for (int k = 0; k < ZPT; ++k) {
@@ -422,14 +432,14 @@ __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T 
             zz = zn; cin = cn; vin = vn;
             const uint32_t i1 = i + kBlock;
             if (k + 1 < ZPT && i1 < nz) {
-                zn = zr[i1];
-                cn = LIKE ? cr[i1] : __builtin_nontemporal_load(cr + i1);
-                if (LIKE) vn = vr[i1];
+                zn = *row_at(zr, i1);
+                cn = LIKE ? *row_at(cr, i1) : __builtin_nontemporal_load(row_at(cr, i1));
+                if (LIKE) vn = *row_at(vr, i1);
             }
         } else {
-            zz = zr[i];
-            cin = LIKE ? cr[i] : __builtin_nontemporal_load(cr + i);
-            vin = LIKE ? vr[i] : T(0);
+            zz = *row_at(zr, i);
+            cin = LIKE ? *row_at(cr, i) : __builtin_nontemporal_load(row_at(cr, i));
+            vin = LIKE ? *row_at(vr, i) : T(0);
         }
         if (small_z_lane<T>(zz)) {
             deferred |= 1u << k;
@@ -453,9 +463,9 @@ __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T 
         acc[5] += cv * o.dok;
         acc[6] += cv * o.dh;
         const T gz = cv * o.dz;
-        if (orow) __builtin_nontemporal_store(o.val, orow + i);
+        if (orow) __builtin_nontemporal_store(o.val, row_at(orow, i));
         if (zstride != 0) {
-            if (grow) grow[i] = gz;
+            if (grow) *row_at(grow, i) = gz;
         } else {
             gzl[k * kBlock + threadIdx.x] += gz;
         }
@@ -702,7 +712,7 @@ __global__ __launch_bounds__(kBlock, (jac_min_waves<T, KIND>())) void k_jac(cons
     const int64_t tile = blockIdx.y, zb = blockIdx.x;
     const int64_t i = zb * kBlock + threadIdx.x;
     const bool active = i < n_z;
-    const uint32_t i32 = (uint32_t)i; // n_z < 2^31 (checked on the host)
+    const uint32_t i32 = (uint32_t)i; // n_z < 2^29 (checked on the host)
     const int64_t c0 = tile * ct;
     const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
     const int64_t plane = n_cosmo * n_z;
@@ -1275,7 +1285,7 @@ int check_grid(int64_t n_cosmo, int64_t n_z) {
     Tiling t = tiling(n_cosmo, n_z);  // the forward grid is the larger one
     if (t.nblocks > 0x7FFFFFFFll) return COSMO_E_ARG;
     if (n_cosmo > 0x7FFFFFFFll) return COSMO_E_ARG;
-    if (n_z > 0x7FFFFFFFll - 8 * kBlock) return COSMO_E_ARG; // 32-bit redshift offsets in the kernels
+    if (n_z > (1ll << 29) - 8 * kBlock) return COSMO_E_ARG; // 32-bit byte offsets within a row in the kernels
     return COSMO_OK;
 }
 

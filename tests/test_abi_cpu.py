@@ -53,6 +53,12 @@ def test_argument_errors_are_synchronous(lib):
     assert lib.carlson_rf(0, 4, dummy, dummy, null, dummy, null) == E_ARG
     assert lib.carlson_rj(1, 4, dummy, dummy, dummy, null, dummy, null) == E_ARG
     assert lib.carlson_rc(5, 4, dummy, dummy, dummy, null) == E_DTYPE
+    # rows of 2^29 redshifts or more (32-bit byte offsets within a row in the kernels)
+    big = 1 << 29
+    assert lib.cosmo_distance(0, 1, dummy, 1, dummy, big, 0, dummy, null, null, 0, null) == E_ARG
+    assert lib.cosmo_distance_vjp(3, 0, dummy, 1, dummy, big, 0, dummy, null, dummy, null, null, null, 0,
+                                  null) == E_ARG
+    assert lib.cosmo_distance_jac(3, 0, dummy, 1, dummy, big, 0, null, dummy, null, null, 0, null) == E_ARG
     # empty problems are valid no-ops
     assert lib.cosmo_roots(null, 0, null, null, null) == 0
     assert lib.carlson_rd(0, 0, null, null, null, null, null) == 0
