@@ -263,16 +263,16 @@ __device__ __forceinline__ void chi_grad_between(const LaneConst<T> &k, T z1, T 
     U0 = T1_0 + T2_0;
     T rf, rdx, rdz;
     cx<T> rdy;
-    rfd_s<T, PAIR>(U0 * U0, va, vb, rf, rdx, rdy, rdz);
+    rfd_s<T, PAIR>(U0 * U0, va, vb, rf, rdx, rdy, rdz, T(-1.0 / 3.0)); // -R_D/3
     const T scale = k.pre2 * dz;
     o.chi = scale * rf;
     o.iE1 = k.pre * b.ie;
     o.iE2 = k.pre * a.ie;
     const T h = scale * T(-0.5);
-    const T G0 = -U0 * rdx * T(1.0 / 3.0);
+    const T G0 = U0 * rdx;
     const T a0 = G0 * T1_0, b0 = G0 * T2_0;
     if (PAIR) {
-        const cx<T> G1 = U1 * rdy * T(-1.0 / 3.0);
+        const cx<T> G1 = U1 * rdy;
         const cx<T> a1 = G1 * T1_1, b1 = G1 * T2_1;
         const T Asum = a0 + T(2) * a1.re, Bsum = b0 + T(2) * b1.re;
         o.dsig = h * (A_.x * Asum * a.it2 + B_.x * Bsum * b.it2);
@@ -282,7 +282,7 @@ __device__ __forceinline__ void chi_grad_between(const LaneConst<T> &k, T z1, T 
         o.dr1im = h * d1.im;
         o.dr2 = T(0);
     } else {
-        const T G1 = -U1.re * rdy.re * T(1.0 / 3.0), G2 = -U2 * rdz * T(1.0 / 3.0);
+        const T G1 = U1.re * rdy.re, G2 = U2 * rdz;
         const T a1 = G1 * T1_1r, b1 = G1 * T2_1r, a2 = G2 * T1_2, b2 = G2 * T2_2;
         const T Asum = a0 + a1 + a2, Bsum = b0 + b1 + b2;
         o.dsig = h * (A_.x * Asum * a.it2 + B_.x * Bsum * b.it2);

@@ -424,7 +424,8 @@ template <typename T, bool PAIR> __device__ T rd_last_x(T x, T a, T b) {
 // this derivative is below 4e-7 (FP32) / 2e-14 (FP64) relative.
 // Outputs: rf; tx, ty (PAIR: complex, last argument y = a + i b), tz (not PAIR).
 template <typename T, bool PAIR>
-__device__ __forceinline__ void rfd_tails(T AF0, T x0, T a0, T b0, T AF, T f, T &rf, T &tx, cx<T> &ty, T &tz) {
+__device__ __forceinline__ void rfd_tails(T AF0, T x0, T a0, T b0, T AF, T f, T &rf, T &tx, cx<T> &ty, T &tz,
+                                          T rs = T(1)) {
     const T ra = Fp<T>::rsqrt(AF);
     const T g = f * (ra * ra);
     const T X = (AF0 - x0) * g;
@@ -435,7 +436,7 @@ __device__ __forceinline__ void rfd_tails(T AF0, T x0, T a0, T b0, T AF, T f, T 
     rf = tF * ra;
     T t2, t3;
     rf_tail_grad(E2, E3, t2, t3);
-    const T sc = g * ra; // 4^-m A^(-3/2)
+    const T sc = g * ra * rs; // 4^-m A^(-3/2), times the caller's scale of the R_D outputs
     const T c0 = tF + E2 * (T(4) * t2 - T(2) * t3) + kc<T>(6.0) * t3 * E3;
     const T m2 = kc<T>(-6.0) * t2, m3 = kc<T>(6.0) * t3;
     tx = sc * (c0 + m2 * X + m3 * q); // P_x = Y Z = q
@@ -451,15 +452,17 @@ __device__ __forceinline__ void rfd_tails(T AF0, T x0, T a0, T b0, T AF, T f, T 
     }
 }
 
+// The R_D outputs come multiplied by rs (a constant the caller would otherwise apply to
+// each of them).
 template <typename T, bool PAIR>
-__device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
+__device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz, T rs = T(1)) {
     const T AF0 = mean3<T, PAIR>(x, a, b);
     const T x0 = x, a0 = a, b0 = b;
     const T QF = spread3<T, PAIR>(AF0, x, a, b);
     if (wave_no_dup<T, PAIR>(QF, AF0)) {
         T tx, tz;
         cx<T> ty;
-        rfd_tails<T, PAIR>(AF0, x0, a0, b0, AF0, T(1), rf, tx, ty, tz);
+        rfd_tails<T, PAIR>(AF0, x0, a0, b0, AF0, T(1), rf, tx, ty, tz, rs);
         rdx = tx;
         rdy = ty;
         rdz = tz;
@@ -492,10 +495,11 @@ __device__ void rfd_s(T x, T a, T b, T &rf, T &rdx, cx<T> &rdy, T &rdz) {
     }
     T tx, tz;
     cx<T> ty;
-    rfd_tails<T, PAIR>(AF0, x0, a0, b0, AF, f, rf, tx, ty, tz);
-    rdx = T(3) * accx + tx;
-    rdy = accy * T(3) + ty;
-    rdz = T(3) * accz + tz;
+    rfd_tails<T, PAIR>(AF0, x0, a0, b0, AF, f, rf, tx, ty, tz, rs);
+    const T r3 = T(3) * rs;
+    rdx = r3 * accx + tx;
+    rdy = accy * r3 + ty;
+    rdz = r3 * accz + tz;
 }
 
 // R_F(x, y, z), R_J(x, y, z, p) and jx = dR_J/dx from one duplication sequence (p real

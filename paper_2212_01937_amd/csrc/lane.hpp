@@ -612,17 +612,18 @@ __device__ __forceinline__ void chi_grad(const LaneConst<T> &k, T z, ChiGrad<T, 
     build_u<T, PAIR, true>(k, z, g);
     T rf, rdx, rdz;
     cx<T> rdy;
-    rfd_s<T, PAIR>(g.U0 * g.U0, g.va, g.vb, rf, rdx, rdy, rdz);
+    // the R_D outputs as -R_D/3 (rs), the factor of G_m below
+    rfd_s<T, PAIR>(g.U0 * g.U0, g.va, g.vb, rf, rdx, rdy, rdz, T(-1.0 / 3.0));
     const T scale = k.pre2 * z;
     o.chi = scale * rf;
     o.iE = k.pre * g.iXprod;
     o.kr = scale * T(-0.5);
     // G_m = dR_F/dU_m = -U_m R_D(., ., U_m^2)/3 ; a_m = G_m T1_m, b_m = G_m T2_m
-    const T G0 = -g.U0 * rdx * T(1.0 / 3.0);
+    const T G0 = g.U0 * rdx;
     const T a0 = G0 * g.T1_0, b0 = G0 * g.T2_0;
     // derivative of X_n, Y_n in rho_n: -1/(2 X_n), -1/(2 Y_n); of Xt, Yt in sigma: -x/(2 Xt)
     if (PAIR) {
-        cx<T> G1 = mkc(g.U1re, g.U1im) * rdy * T(-1.0 / 3.0);
+        cx<T> G1 = mkc(g.U1re, g.U1im) * rdy;
         cx<T> a1 = G1 * mkc(g.T1_1re, g.T1_1im), b1 = G1 * mkc(g.T2_1re, g.T2_1im);
         const T A = a0 + T(2) * a1.re, B = b0 + T(2) * b1.re;
         o.dsig = ((T(1) + z) * A * g.iXt2 + B * k.iyt2);
@@ -635,7 +636,7 @@ __device__ __forceinline__ void chi_grad(const LaneConst<T> &k, T z, ChiGrad<T, 
         o.dr1im = d1.im;
         o.dr2 = T(0);
     } else {
-        const T G1 = -g.U1re * rdy.re * T(1.0 / 3.0), G2 = -g.U2 * rdz * T(1.0 / 3.0);
+        const T G1 = g.U1re * rdy.re, G2 = g.U2 * rdz;
         const T a1 = G1 * g.T1_1re, b1 = G1 * g.T2_1re, a2 = G2 * g.T1_2, b2 = G2 * g.T2_2;
         const T A = a0 + a1 + a2, B = b0 + b1 + b2;
         o.dsig = ((T(1) + z) * A * g.iXt2 + B * k.iyt2);
