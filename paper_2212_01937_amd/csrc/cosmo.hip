@@ -89,11 +89,9 @@ __global__ __launch_bounds__(kBlock) void k_forward(const CosmoRec *__restrict__
     const int64_t c0 = tile * ct;
     const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
     if (!active) return; // no cross-lane work below
-    const T zshared = zstride == 0 ? z[i] : T(0);
     const uint32_t i32 = (uint32_t)i; // n_z < 2^29 (checked on the host)
-    for (int64_t c = c0; c < c1; ++c) {
+    auto lane = [&](int64_t c, T zz) __attribute__((always_inline)) {
         const CosmoRec &r = recs[c];
-        const T zz = zstride == 0 ? zshared : (z + c * zstride)[i32];
         T v;
         bool used_gl = false;
         if (!r.valid) v = Fp<T>::nan();
@@ -104,6 +102,16 @@ __global__ __launch_bounds__(kBlock) void k_forward(const CosmoRec *__restrict__
             unsigned long long m = __ballot(used_gl);
             if (m && (int)__lane_id() == __ffsll((long long)m) - 1) atomicOr(info + c, COSMO_INFO_X_QUADRATURE);
         }
+    };
+    if (zstride == 0) {
+        const T zz = z[i];
+        // the shared redshift has arrived before the loop starts, so the loop holds no
+        // load and no wait for one (a wait on the in-order vector-memory counter would
+        // also wait for the previous cosmology's stores)
+        __builtin_amdgcn_s_waitcnt(0);
+        for (int64_t c = c0; c < c1; ++c) lane(c, zz);
+    } else {
+        for (int64_t c = c0; c < c1; ++c) lane(c, (z + c * zstride)[i32]);
     }
 }
 
@@ -719,10 +727,8 @@ __global__ __launch_bounds__(kBlock, (jac_min_waves<T, KIND>())) void k_jac(cons
     // no cross-lane work below: lanes past the end leave at once (which keeps the
     // cosmology loop uniform)
     if (!active) return;
-    const T zshared = zstride == 0 ? z[i] : T(0);
-    for (int64_t c = c0; c < c1; ++c) {
+    auto lane = [&](int64_t c, T zz) __attribute__((always_inline)) {
         const CosmoRec &r = recs[c];
-        const T zz = zstride == 0 ? zshared : (z + c * zstride)[i32];
         T v, J[5];
         bool used_gl = false;
         if (!r.valid) {
@@ -779,6 +785,14 @@ __global__ __launch_bounds__(kBlock, (jac_min_waves<T, KIND>())) void k_jac(cons
             unsigned long long m = __ballot(used_gl);
             if (m && (int)__lane_id() == __ffsll((long long)m) - 1) atomicOr(info + c, COSMO_INFO_X_QUADRATURE);
         }
+    };
+    if (zstride == 0) {
+        const T zz = z[i];
+        // as in k_forward: no load, and no wait on the vector-memory counter, in the loop
+        __builtin_amdgcn_s_waitcnt(0);
+        for (int64_t c = c0; c < c1; ++c) lane(c, zz);
+    } else {
+        for (int64_t c = c0; c < c1; ++c) lane(c, (z + c * zstride)[i32]);
     }
 }
 

@@ -2,7 +2,10 @@
 // distance kernels (packed-FP32 instruction selection disabled) can reach on
 // this GPU: independent FMA chains per lane at full occupancy (FP32, FP64),
 // the same with one reciprocal square root per eight FMAs, and the FP32 chains
-// at 1, 2 and 4 waves per SIMD.  Prints one JSON object.
+// at 1, 2 and 4 waves per SIMD.  Also the HBM write rate of the materialised
+// Jacobian's store pattern without its arithmetic (five planes of 256 x 1e6 FP32,
+// one redshift per lane and 16 cosmologies per lane, non-temporal stores) and of a
+// plain streaming write of the same bytes.  Prints one JSON object.
 //
 // Every launch writes exactly one element per lane of a buffer sized for the
 // largest grid; the kernels have no data-dependent control flow.
@@ -58,6 +61,24 @@ __global__ __launch_bounds__(kThreads) void fma_rsq_chains(float *out, int iters
 #pragma unroll
     for (int c = 0; c < 8; ++c) s += v[c];
     out[gid] = s;
+}
+
+// The Jacobian kernel's stores alone: lane i of a 256-lane block (grid x) writes
+// element i of five planes for each of the ct cosmologies of its tile (grid y).
+__global__ __launch_bounds__(kThreads) void jac_store_pattern(float *jac, long n_c, long n_z, int ct) {
+    const long tile = blockIdx.y, i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n_z) return;
+    const long plane = n_c * n_z;
+    const long c0 = tile * ct, c1 = c0 + ct < n_c ? c0 + ct : n_c;
+    for (long c = c0; c < c1; ++c) {
+        float *row = jac + c * n_z;
+        for (int q = 0; q < 5; ++q) __builtin_nontemporal_store(float(q + c) * 1e-3f + float(i), row + q * plane + i);
+    }
+}
+// A plain streaming write: 16 bytes per lane, n a multiple of 4 * kThreads.
+__global__ __launch_bounds__(kThreads) void stream_write(float *p, long n) {
+    const long i = ((long)blockIdx.x * kThreads + threadIdx.x) * 4;
+    if (i + 3 < n) *(float4 *)(p + i) = float4{1.f, 2.f, 3.f, 4.f};
 }
 
 template <typename L> float time_ms(L launch, int reps) {
@@ -119,6 +140,17 @@ int main() {
         float ms = time_ms([&] { fma_chains<float, 8><<<blocks, kThreads>>>(of, 4 * iters, 0.999f, 1e-3f); }, 3);
         double fma = 8.0 * 4 * iters * double(blocks) * kThreads;
         std::printf(", \"fp32_fma_tflops_%d_waves_per_simd\": %.2f", waves, 2 * fma / ms * 1e-9);
+    }
+    {
+        const long n_c = 256, n_z = 1000000, n = 5 * n_c * n_z; // 5.12 GB
+        float *jac = nullptr;
+        CHECK(hipMalloc(&jac, n * sizeof(float)));
+        const dim3 grid((unsigned)((n_z + kThreads - 1) / kThreads), 16);
+        float ms = time_ms([&] { jac_store_pattern<<<grid, kThreads>>>(jac, n_c, n_z, 16); }, 10);
+        std::printf(", \"hbm_write_jacobian_pattern_tbs\": %.2f, \"hbm_write_jacobian_pattern_ms\": %.3f", n * 4.0 / (ms * 1e-3) / 1e12, ms);
+        ms = time_ms([&] { stream_write<<<(unsigned)(n / 4 / kThreads), kThreads>>>(jac, n); }, 10);
+        std::printf(", \"hbm_write_stream_tbs\": %.2f", n * 4.0 / (ms * 1e-3) / 1e12);
+        CHECK(hipFree(jac));
     }
     std::printf("}\n");
     CHECK(hipFree(of));
