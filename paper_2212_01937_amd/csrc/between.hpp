@@ -43,7 +43,7 @@ template <typename T, bool PAIR> __device__ __forceinline__ void side_at(const L
 template <typename T, bool PAIR> __device__ __forceinline__ void side_inf(const LaneConst<T> &k, Side<T, PAIR> &s) {
     s.x = T(1);
     s.t2 = -k.sigma; // sigma <= 0 (sigma < 0 with radiation, 0 without)
-    s.t = Fp<T>::sqrt(s.t2);
+    s.t = k.tinf;
     s.n0 = T(1);
     s.n1re = T(1); s.n1im = T(0); s.n1abs = T(1);
     s.n2 = T(1);
@@ -80,10 +80,11 @@ __device__ __forceinline__ void args_between(const Side<T, PAIR> &a, const Side<
     o.V0 = o.U0 * o.U0;
 }
 
-template <typename T, bool PAIR>
+// ZINF: the upper limit is known to be infinite on every lane (otherwise tested per lane).
+template <typename T, bool PAIR, bool ZINF = false>
 __device__ __forceinline__ void sides(const LaneConst<T> &k, T z1, T z2, Side<T, PAIR> &a, Side<T, PAIR> &b, T &dz) {
     side_at<T, PAIR>(k, z1, b);
-    if (z2 == Fp<T>::inf()) {
+    if (ZINF || z2 == Fp<T>::inf()) {
         side_inf<T, PAIR>(k, a);
         dz = T(1);
     } else {
@@ -115,9 +116,9 @@ template <typename Q, bool PAIR> struct TArgs2 {
 };
 
 template <typename Q, bool PAIR>
-__device__ __forceinline__ void t_args_between(const LaneConst<Q> &k, Q z1, Q z2, TArgs2<Q, PAIR> &o) {
-    Side<Q, PAIR> a, b;
-    sides<Q, PAIR>(k, z1, z2, a, b, o.dz);
+__device__ __forceinline__ void t_args_sides(const LaneConst<Q> &k, const Side<Q, PAIR> &a, const Side<Q, PAIR> &b,
+                                             Q dz, TArgs2<Q, PAIR> &o) {
+    o.dz = dz;
     args_between<Q, PAIR>(a, b, o.u);
     const Q d2 = o.dz * o.dz;
     Q W = o.u.V0 + d2 * k.c5;
@@ -135,31 +136,12 @@ __device__ __forceinline__ void t_args_between(const LaneConst<Q> &k, Q z1, Q z2
     o.S = o.Qv - d2 * k.rprod;
 }
 
-// t(z1, z2) / (1/H0), eq. 3.8 (z2 = inf: the age t(z1, inf)).  The FP32 path forms
-// the arguments in FP64 and rounds once (as t_hat does).
-template <typename T, bool PAIR> __device__ __forceinline__ T t_between(const CosmoRec &r, T z1, T z2) {
-    const LaneConst<T> &k = lane_of<T>(r);
-    TArgs2<double, PAIR> ad;
-    t_args_between<double, PAIR>(r.d, (double)z1, z2 == Fp<T>::inf() ? Fp<double>::inf() : (double)z2, ad);
-    const T V0 = T(ad.u.V0), va = T(ad.u.va), vb = T(ad.u.vb), W = T(ad.W);
-    const T dz = T(ad.dz), d2 = dz * dz;
-    T rf, rj;
-    rfj_s<T, PAIR>(V0, va, vb, W, rf, rj);
-    const T rc = ad.rc_zero ? T(0) : rc_r(T(ad.S), T(ad.Qv));
-    return k.pre2 * dz * (d2 * T(1.0 / 3.0) * k.pre3 * rj + rc + k.sigma * rf);
-}
-
-// Observable KIND (COSMO_DC, COSMO_DM, COSMO_DA or COSMO_T) between z1 and z2.
-template <typename T, int KIND, bool PAIR>
-__device__ __forceinline__ T eval_between(const CosmoRec &r, T z1, T z2) {
-    const LaneConst<T> &k = lane_of<T>(r);
-    if (KIND == COSMO_T) return k.th * t_between<T, PAIR>(r, z1, z2);
-    const T chi = chi_between<T, PAIR>(k, z1, z2);
-    if (KIND == COSMO_DC) return k.dh * chi;
-    T S, C, dS;
-    sinn(chi, k.ok, k.sk, S, C, dS);
-    if (KIND == COSMO_DM) return k.dh * S;
-    return z2 == Fp<T>::inf() ? T(0) : k.dh * S * Fp<T>::rcp(T(1) + z2); // COSMO_DA
+template <typename Q, bool PAIR, bool ZINF = false>
+__device__ __forceinline__ void t_args_between(const LaneConst<Q> &k, Q z1, Q z2, TArgs2<Q, PAIR> &o) {
+    Side<Q, PAIR> a, b;
+    Q dz;
+    sides<Q, PAIR, ZINF>(k, z1, z2, a, b, dz);
+    t_args_sides<Q, PAIR>(k, a, b, dz, o);
 }
 
 // ---------------------------------------------------------------- adjoint (D_C family)
@@ -203,10 +185,129 @@ template <typename T, bool PAIR> __device__ __forceinline__ void side_at_g(const
 
 template <typename T, bool PAIR> __device__ __forceinline__ void side_inf_g(const LaneConst<T> &k, SideG<T, PAIR> &o) {
     side_inf<T, PAIR>(k, o.s);
-    o.it2 = Fp<T>::rcp(o.s.t2); // 1/(-sigma): infinite without radiation (see chi_grad_between)
+    o.it2 = k.itinf2; // 1/(-sigma): infinite without radiation (see chi_grad_between)
     o.i0 = T(0); o.i1re = T(0); o.i1im = T(0); o.i2 = T(0);
     o.ie = T(0);
 }
+
+// FP64 square root of x to about 1e-14 relative from the FP32 root s = xf rt (rt the FP32
+// reciprocal square root of xf = (float)x) and one Newton step whose correction
+// (x - s^2)/(2 s) is formed in FP32: the FP32 root is within ~1e-7, so the step leaves
+// ~1e-14.
+__device__ __forceinline__ double sqrt_nr(double x, float s, float rt) {
+    const double sd = (double)s;
+    return sd + (double)((float)__builtin_fma(-sd, sd, x) * (0.5f * rt));
+}
+
+// One finite limit of an FP32 lane of the time coordinate: the square roots as FP32 values
+// with the reciprocals of the chain (side_at_g's, in o) and, refined by sqrt_nr, in FP64
+// (d) for the FP64 arguments of eq. 3.8 -- one reciprocal square root per factor.
+template <bool PAIR>
+__device__ __forceinline__ void side_at_mixed(const LaneConst<double> &kd, const LaneConst<float> &kf, float z,
+                                              Side<double, PAIR> &d, SideG<float, PAIR> &o) {
+    Side<float, PAIR> &s = o.s;
+    const double zd = (double)z;
+    d.x = 1.0 + zd;
+    s.x = 1.0f + z;
+    d.t2 = kd.yt2 - kd.sigma * zd;
+    s.t2 = (float)d.t2;
+    const float rt = Fp<float>::rsqrt(s.t2);
+    s.t = s.t2 * rt;
+    o.it2 = rt * rt;
+    d.t = sqrt_nr(d.t2, s.t, rt);
+    const double v0 = zd + kd.w0;
+    const float v0f = (float)v0, r0 = Fp<float>::rsqrt(v0f);
+    s.n0 = v0f * r0;
+    o.i0 = r0 * r0;
+    d.n0 = sqrt_nr(v0, s.n0, r0);
+    if (PAIR) {
+        const double wre = zd + kd.w1re;
+        const float wref = (float)wre;
+        float ab, iab;
+        const cx<float> n1 = csqrt_uim_inv(wref, kf.w1im2, kf.hw1im, kf.sw1im, ab, iab);
+        s.n1re = n1.re; s.n1im = n1.im; s.n1abs = ab;
+        const float i2v = iab * iab;
+        o.i1re = wref * i2v; o.i1im = -kf.w1im * i2v;
+        s.n2 = 0.0f; o.i2 = 0.0f;
+        o.ie = rt * r0 * iab;
+        // Newton step for the complex root: n1 + (w - n1^2) / (2 n1), with
+        // 1/(2 n1) = conj(n1) / (2 |w|) and the residual in FP64
+        const double nre = (double)n1.re, nim = (double)n1.im;
+        const float rr = (float)__builtin_fma(-nre, nre, __builtin_fma(nim, nim, wre));
+        const float ri = (float)__builtin_fma(-2.0 * nre, nim, kd.w1im);
+        const float h = 0.5f * iab;
+        d.n1re = nre + (double)((rr * n1.re + ri * n1.im) * h);
+        d.n1im = nim + (double)((ri * n1.re - rr * n1.im) * h);
+        d.n1abs = d.n1re * d.n1re + d.n1im * d.n1im;
+        d.n2 = 0.0;
+    } else {
+        const double v1 = zd + kd.w1re, v2 = zd + kd.w2;
+        const float v1f = (float)v1, v2f = (float)v2;
+        const float r1 = Fp<float>::rsqrt(v1f), r2 = Fp<float>::rsqrt(v2f);
+        s.n1re = v1f * r1; s.n1im = 0.0f; s.n1abs = 0.0f;
+        s.n2 = v2f * r2;
+        o.i1re = r1 * r1; o.i1im = 0.0f; o.i2 = r2 * r2;
+        o.ie = rt * r0 * r1 * r2;
+        d.n1re = sqrt_nr(v1, s.n1re, r1); d.n1im = 0.0; d.n1abs = 0.0;
+        d.n2 = sqrt_nr(v2, s.n2, r2);
+    }
+}
+
+// The FP64 arguments of eq. 3.8 for an FP32 lane (z2 = inf: the scaled side), with the
+// FP32 sides of the chain in a (upper) and b (lower).
+template <bool PAIR, bool ZINF>
+__device__ __forceinline__ void t_args_mixed(const CosmoRec &r, float z1, float z2, TArgs2<double, PAIR> &o,
+                                             SideG<float, PAIR> &a, SideG<float, PAIR> &b) {
+    Side<double, PAIR> ad, bd;
+    side_at_mixed<PAIR>(r.d, r.f, z1, bd, b);
+    double dz;
+    if (ZINF || z2 == Fp<float>::inf()) {
+        side_inf<double, PAIR>(r.d, ad);
+        side_inf_g<float, PAIR>(r.f, a);
+        dz = 1.0;
+    } else {
+        side_at_mixed<PAIR>(r.d, r.f, z2, ad, a);
+        dz = (double)z2 - (double)z1;
+    }
+    t_args_sides<double, PAIR>(r.d, ad, bd, dz, o);
+}
+
+// t(z1, z2) / (1/H0), eq. 3.8 (z2 = inf: the age t(z1, inf)).  The FP32 path forms
+// the arguments in FP64 (square roots by sqrt_nr) and rounds them once.
+template <typename T, bool PAIR, bool ZINF = false> __device__ __forceinline__ T t_between(const CosmoRec &r, T z1, T z2) {
+    const LaneConst<T> &k = lane_of<T>(r);
+    TArgs2<double, PAIR> ad;
+    if constexpr (sizeof(T) == 4) {
+        SideG<float, PAIR> a, b;
+        t_args_mixed<PAIR, ZINF>(r, z1, z2, ad, a, b);
+    } else {
+        t_args_between<double, PAIR, ZINF>(r.d, z1, z2, ad);
+    }
+    const T V0 = T(ad.u.V0), va = T(ad.u.va), vb = T(ad.u.vb), W = T(ad.W);
+    const T dz = T(ad.dz), d2 = dz * dz;
+    T rf, rj;
+    rfj_s<T, PAIR>(V0, va, vb, W, rf, rj);
+    const T rc = ad.rc_zero ? T(0) : rc_r(T(ad.S), T(ad.Qv));
+    return k.pre2 * dz * (d2 * T(1.0 / 3.0) * k.pre3 * rj + rc + k.sigma * rf);
+}
+
+// Observable KIND (COSMO_DC, COSMO_DM, COSMO_DA or COSMO_T) between z1 and z2.
+template <typename T, int KIND, bool PAIR>
+__device__ __forceinline__ T eval_between(const CosmoRec &r, T z1, T z2) {
+    const LaneConst<T> &k = lane_of<T>(r);
+    if (KIND == COSMO_T) {
+        // the age t(z1, inf) on every lane of the wave: the upper side's constants fold
+        if (__ballot(!(z2 == Fp<T>::inf())) == 0) return k.th * t_between<T, PAIR, true>(r, z1, z2);
+        return k.th * t_between<T, PAIR>(r, z1, z2);
+    }
+    const T chi = chi_between<T, PAIR>(k, z1, z2);
+    if (KIND == COSMO_DC) return k.dh * chi;
+    T S, C, dS;
+    sinn(chi, k.ok, k.sk, S, C, dS);
+    if (KIND == COSMO_DM) return k.dh * S;
+    return z2 == Fp<T>::inf() ? T(0) : k.dh * S * Fp<T>::rcp(T(1) + z2); // COSMO_DA
+}
+
 
 // chi(z1, z2)/D_H and its partials in the root parameters (sigma, rho_0, rho_1 [re, im]
 // or rho_1, rho_2) at fixed beta, through dR_F/d(U_m^2) = -R_D(., ., U_m^2)/6 (eq. 2.10)
@@ -317,18 +418,23 @@ template <typename T, bool PAIR> struct TGrad2 {
     T t, dsig, dr0, dr1re, dr1im, dr2, iE1, iE2;
 };
 
-template <typename T, bool PAIR>
-__device__ void t_grad_between(const CosmoRec &r, T z1, T z2, TGrad2<T, PAIR> &o) {
+template <typename T, bool PAIR, bool ZINF = false>
+__device__ __forceinline__ void t_grad_between(const CosmoRec &r, T z1, T z2, TGrad2<T, PAIR> &o) {
     const LaneConst<T> &k = lane_of<T>(r);
-    const bool zinf = z2 == Fp<T>::inf();
+    const bool zinf = ZINF || z2 == Fp<T>::inf();
     TArgs2<double, PAIR> ad;
-    t_args_between<double, PAIR>(r.d, (double)z1, zinf ? Fp<double>::inf() : (double)z2, ad);
+    SideG<T, PAIR> a, b;
+    if constexpr (sizeof(T) == 4) {
+        t_args_mixed<PAIR, ZINF>(r, z1, z2, ad, a, b);
+    } else {
+        // the sides of the chain give the arguments' square roots (2 ulp)
+        side_at_g<T, PAIR>(k, z1, b);
+        if (zinf) side_inf_g<T, PAIR>(k, a);
+        else side_at_g<T, PAIR>(k, z2, a);
+        t_args_sides<double, PAIR>(r.d, a.s, b.s, zinf ? 1.0 : z2 - z1, ad);
+    }
     const T V0 = T(ad.u.V0), va = T(ad.u.va), vb = T(ad.u.vb), W = T(ad.W), Qv = T(ad.Qv), S = T(ad.S);
     const T dz = T(ad.dz), d2 = dz * dz;
-    SideG<T, PAIR> a, b;
-    side_at_g<T, PAIR>(k, z1, b);
-    if (zinf) side_inf_g<T, PAIR>(k, a);
-    else side_at_g<T, PAIR>(k, z2, a);
     o.iE1 = k.pre * b.ie;
     o.iE2 = k.pre * a.ie;
     const Side<T, PAIR> &A_ = a.s, &B_ = b.s;
@@ -357,8 +463,9 @@ __device__ void t_grad_between(const CosmoRec &r, T z1, T z2, TGrad2<T, PAIR> &o
     rfjd_s<T, PAIR>(V0, va, vb, W, rf, rj, rdx, rdy, rdz);
     T rc = T(0), dRC_S = T(0), dRC_Q = T(0);
     if (!ad.rc_zero) {
-        rc = rc_r(S, Qv);
-        dRC_S = rd_last_x<T, false>(S, Qv, Qv) * T(-1.0 / 6.0); // -R_D(Q, Q, S)/6
+        T rdq;
+        rc_rd_r(S, Qv, rc, rdq);
+        dRC_S = rdq * T(-1.0 / 6.0); // -R_D(Q, Q, S)/6
         dRC_Q = (T(-0.5) * rc - S * dRC_S) * Fp<T>::rcp(Qv);
     }
     const T c3 = d2 * T(1.0 / 3.0) * k.pre3;
@@ -533,11 +640,15 @@ __device__ __forceinline__ void lane_grad_between(const CosmoRec &r, T z1, T z2,
     const LaneConst<T> &k = lane_of<T>(r);
     const bool fp32 = sizeof(T) == 4;
     const bool zinf = z2 == Fp<T>::inf();
-    if (KIND == COSMO_T && !(direct_mode(KIND, r, fp32) || (zinf && !(-k.sigma >= T(fp32 ? kAgeSigma32 : kAgeSigma64))))) {
-        // time coordinate: eq. 3.8 with both limits through the Carlson derivatives
+    const bool t_direct = KIND == COSMO_T && direct_mode(KIND, r, fp32);
+    const bool t_sig = -k.sigma >= T(fp32 ? kAgeSigma32 : kAgeSigma64);
+    if (KIND == COSMO_T && !(t_direct || (zinf && !t_sig))) {
+        // time coordinate: eq. 3.8 with both limits through the Carlson derivatives (the
+        // age t(z1, inf) on every lane of the wave: the upper side's constants fold)
         LaneGrad<T> &g = o.g;
         TGrad2<T, PAIR> tg;
-        t_grad_between<T, PAIR>(r, z1, z2, tg);
+        if (__ballot(!zinf) == 0) t_grad_between<T, PAIR, true>(r, z1, z2, tg);
+        else t_grad_between<T, PAIR>(r, z1, z2, tg);
         g.quad = false;
         g.p[0] = tg.t; g.p[1] = tg.dsig; g.p[2] = tg.dr0; g.p[3] = tg.dr1re; g.p[4] = PAIR ? tg.dr1im : tg.dr2;
         g.val = k.th * tg.t;

@@ -55,6 +55,11 @@ template <typename T> __device__ __forceinline__ T rc_tail(T s) {
     return T(1) + s * s * (T(0.3) + s * (T(1.0 / 7.0) + s * (T(0.375) + s * (T(9.0 / 22.0) +
                           s * (T(159.0 / 208.0) + s * T(1.125))))));
 }
+// d rc_tail / ds
+template <typename T> __device__ __forceinline__ T rc_tail_d(T s) {
+    return s * (T(0.6) + s * (T(3.0 / 7.0) + s * (T(1.5) + s * (T(45.0 / 22.0) +
+                s * (T(954.0 / 208.0) + s * T(63.0 / 8.0))))));
+}
 template <typename T> __device__ __forceinline__ cx<T> rc_tail(cx<T> s) {
     cx<T> p = (s * T(1.125)) + T(159.0 / 208.0);
     p = (s * p) + T(9.0 / 22.0);
@@ -403,6 +408,26 @@ template <typename T, bool PAIR> __device__ T rd_last_x(T x, T a, T b) {
     T E2 = q - T(6) * Z2, E3 = (T(3) * q - T(8) * Z2) * Z;
     T E4 = T(3) * (q - Z2) * Z2, E5 = q * Z2 * Z;
     return rj_tail(E2, E3, E4, E5) * g * ra + T(3) * acc;
+}
+
+// R_C(x, y) and R_D(y, y, x) = -6 dR_C/dx (x >= 0, y > 0: R_C = R_F(x, y, y), eq. 2.10).
+// An FP32 wave none of whose lanes needs a duplication step (rc_r's test at m = 0) takes
+// both from the m = 0 tail: with A = (x + 2y)/3, s = y/A - 1 and P the series of
+// rc_tail, R_C = A^(-1/2) P(s), and since dA/dx = 1/3, ds/dx = -(1 + s)/(3A),
+// R_D(y, y, x) = A^(-3/2) [P(s) + 2 (1 + s) P'(s)] (truncation of P' at |s| <= tau7/2:
+// below 2e-7 relative).  Otherwise rc_r and rd_last_x.
+template <typename T> __device__ __forceinline__ void rc_rd_r(T x, T y, T &rc, T &rd) {
+    const T A0 = (x + T(2) * y) * T(1.0 / 3.0);
+    if (sizeof(T) == 4 && __ballot(!(y > T(0)) || Fp<T>::abs(A0 - x) > Fp<T>::tau7 * Fp<T>::abs(A0)) == 0) {
+        const T ra = Fp<T>::rsqrt(A0), ia = ra * ra;
+        const T s = (y - A0) * ia;
+        const T P = rc_tail(s);
+        rc = P * ra;
+        rd = (P + T(2) * (T(1) + s) * rc_tail_d(s)) * ia * ra;
+        return;
+    }
+    rc = rc_r(x, y);
+    rd = rd_last_x<T, false>(x, y, y);
 }
 
 // R_F together with the three R_D(., ., x_k) that give its partial derivatives,

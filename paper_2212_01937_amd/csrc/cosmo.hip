@@ -610,8 +610,10 @@ __device__ __forceinline__ void between_vjp_cosmo(const CosmoRec &r, int64_t c, 
     }
 }
 
+template <typename T, int KIND> constexpr int between_min_waves() { return 1; }
+
 template <typename T, int KIND, int ZPT>
-__global__ __launch_bounds__(kBlock) void k_between_vjp(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
+__global__ __launch_bounds__(kBlock, (between_min_waves<T, KIND>())) void k_between_vjp(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
                                                         const T *__restrict__ z1, const T *__restrict__ z2,
                                                         int64_t n_z, int64_t zstride, const T *__restrict__ cot,
                                                         T *__restrict__ pacc, T *__restrict__ g1_out,

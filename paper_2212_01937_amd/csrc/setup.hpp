@@ -75,6 +75,7 @@ template <typename T> struct LaneConst {
     T yty1, yty2;           //   Yt Y1, Yt Y2
     T w1im2, hw1im, sw1im;  // pair: Im(w_1)^2, |Im(w_1)|/2, sign of Im(w_1) (+-1)
     T k5hinv;               // (5 / ln 10) / H0: minus dmu/dH0
+    T tinf, itinf2;         // sqrt(-sigma) and 1/(-sigma): an infinite limit's scaled sqrt(1 - sigma x)
 };
 
 struct CosmoRec {
@@ -214,6 +215,7 @@ template <typename T> __device__ void fill_lane(LaneConst<T> &L, const LaneConst
     L.y1y2 = T(D.y1y2); L.y0y2 = T(D.y0y2); L.y0y1 = T(D.y0y1); L.yty1 = T(D.yty1); L.yty2 = T(D.yty2);
     L.w1im2 = T(D.w1im2); L.hw1im = T(D.hw1im); L.sw1im = T(D.sw1im);
     L.k5hinv = T(D.k5hinv);
+    L.tinf = T(D.tinf); L.itinf2 = T(D.itinf2);
 }
 
 // dP/dtheta at x for theta = Om, OL, Or (Ok eliminated)
@@ -401,6 +403,8 @@ __device__ void setup_cosmo(const double *prm, CosmoRec &rec) {
     D.yty1 = D.yt * D.y1re; D.yty2 = D.yt * D.y2;
     D.w1im2 = D.w1im * D.w1im; D.hw1im = 0.5 * __builtin_fabs(D.w1im); D.sw1im = D.w1im >= 0.0 ? 1.0 : -1.0;
     D.k5hinv = 2.1714724095162591 * D.hinv;
+    D.tinf = __builtin_sqrt(-sigma);
+    D.itinf2 = 1.0 / -sigma; // infinite without radiation (sigma = 0)
     D.ok = Ok;
     D.sk = __builtin_sqrt(__builtin_fabs(Ok));
     D.dh = kC / H0;

@@ -19,6 +19,20 @@ extern "C" void host_eval(const double *prm, int kind, int dt, const double *z, 
     }
 }
 
+// R_C(x, y) and R_D(y, y, x) (rc_rd_r) for n pairs; out[2 i ..] = (rc, rd).  dt: 0 FP32
+// (the host stand-in for the wave vote is the lane's own test), 1 FP64.
+extern "C" void host_rc_rd(int dt, const double *x, const double *y, long n, double *out) {
+    for (long i = 0; i < n; ++i) {
+        if (dt == 0) {
+            float rc, rd;
+            rc_rd_r((float)x[i], (float)y[i], rc, rd);
+            out[2 * i] = rc; out[2 * i + 1] = rd;
+        } else {
+            rc_rd_r(x[i], y[i], out[2 * i], out[2 * i + 1]);
+        }
+    }
+}
+
 // Structured R_F and R_D(., ., x_k) from one duplication sequence (rfd_s), for a
 // triple (x, a, b): pair != 0 -> (x, a + i b, a - i b), else (x, a, b).
 // out: rf, rdx, rdy.re, rdy.im, rdz.  dt: 0 FP32, 1 FP64.

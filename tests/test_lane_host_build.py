@@ -124,6 +124,28 @@ def test_structured_rf_rd_match_oracle(libs, model):
     print("max relative error", worst)
 
 
+@pytest.mark.parametrize("model", ["exact", "noisy"])
+def test_rc_with_x_derivative_matches_oracle(libs, model):
+    """rc_rd_r: R_C(x, y) and R_D(y, y, x) = -6 dR_C/dx (eq. 2.10 with R_C = R_F(x, y, y))
+    against the oracle's R_C and R_D, on pairs within the m = 0 tail's range (the FP32
+    fast path: |x/y - 1| up to 0.3) and far outside it (duplication), FP64 and FP32 (the
+    oracle at the FP32-rounded arguments)."""
+    rng = np.random.default_rng(11)
+    y = 10.0 ** rng.uniform(-3, 3, 400)
+    near = y * (1.0 + rng.uniform(-0.3, 0.3, 400))
+    far = y * 10.0 ** rng.uniform(-4, 4, 400)
+    for x in (near, far):
+        for dt, tol in ((1, 1e-13), (0, 2e-6 if model == "exact" else 4e-6)):
+            xa, ya = (x, y) if dt == 1 else (x.astype(np.float32).astype(np.float64), y.astype(np.float32).astype(np.float64))
+            out = np.zeros(2 * x.size)
+            libs[model].host_rc_rd(dt, xa.ctypes.data_as(ctypes.c_void_p), ya.ctypes.data_as(ctypes.c_void_p),
+                                   ctypes.c_long(x.size), out.ctypes.data_as(ctypes.c_void_p))
+            rc = np.real(oracle.carlson("RC", xa, ya))
+            rd = np.real(oracle.carlson("RD", ya, ya, xa))
+            assert np.max(np.abs(out[0::2] - rc) / rc) <= tol, (dt, model)
+            assert np.max(np.abs(out[1::2] - rd) / rd) <= tol, (dt, model)
+
+
 KIND_BTW = {"DC": 0, "DM": 1, "T": 4, "DA": 6}
 
 
