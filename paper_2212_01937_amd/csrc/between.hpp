@@ -514,16 +514,27 @@ __device__ __forceinline__ void t_grad_between(const CosmoRec &r, T z1, T z2, TG
         const cx<T> a1 = G1 * T1_1, b1 = G1 * T2_1;
         const T As = a0 + T(2) * a1.re, Bs = b0 + T(2) * b1.re;
         dsig += T(-0.5) * (A_.x * As * a.it2 + B_.x * Bs * b.it2);
-        dr0 += T(-0.5) * ((a0 + Bs - b0) * a.i0 + (b0 + As - a0) * b.i0);
-        dr1 = dr1 + ((a1 + Bs - b1) * mkc(a.i1re, a.i1im) + (b1 + As - a1) * mkc(b.i1re, b.i1im)) * T(-0.5);
+        if (ZINF) { // the scaled side at infinity has zero reciprocal squares
+            dr0 += T(-0.5) * ((b0 + As - a0) * b.i0);
+            dr1 = dr1 + ((b1 + As - a1) * mkc(b.i1re, b.i1im)) * T(-0.5);
+        } else {
+            dr0 += T(-0.5) * ((a0 + Bs - b0) * a.i0 + (b0 + As - a0) * b.i0);
+            dr1 = dr1 + ((a1 + Bs - b1) * mkc(a.i1re, a.i1im) + (b1 + As - a1) * mkc(b.i1re, b.i1im)) * T(-0.5);
+        }
     } else {
         const T G1 = dB_dV1.re * T(2) * U1.re, G2 = dB_dV2 * T(2) * U2;
         const T a1 = G1 * T1_1.re, b1 = G1 * T2_1.re, a2 = G2 * T1_2, b2 = G2 * T2_2;
         const T As = a0 + a1 + a2, Bs = b0 + b1 + b2;
         dsig += T(-0.5) * (A_.x * As * a.it2 + B_.x * Bs * b.it2);
-        dr0 += T(-0.5) * ((a0 + Bs - b0) * a.i0 + (b0 + As - a0) * b.i0);
-        dr1.re += T(-0.5) * ((a1 + Bs - b1) * a.i1re + (b1 + As - a1) * b.i1re);
-        dr2 += T(-0.5) * ((a2 + Bs - b2) * a.i2 + (b2 + As - a2) * b.i2);
+        if (ZINF) {
+            dr0 += T(-0.5) * ((b0 + As - a0) * b.i0);
+            dr1.re += T(-0.5) * ((b1 + As - a1) * b.i1re);
+            dr2 += T(-0.5) * ((b2 + As - a2) * b.i2);
+        } else {
+            dr0 += T(-0.5) * ((a0 + Bs - b0) * a.i0 + (b0 + As - a0) * b.i0);
+            dr1.re += T(-0.5) * ((a1 + Bs - b1) * a.i1re + (b1 + As - a1) * b.i1re);
+            dr2 += T(-0.5) * ((a2 + Bs - b2) * a.i2 + (b2 + As - a2) * b.i2);
+        }
     }
     const T scale = k.pre2 * dz;
     o.t = scale * (c3 * rj + rc + s * rf);
@@ -635,14 +646,23 @@ template <typename T> struct LaneGrad2 {
     T dz1;
 };
 
-template <typename T, int KIND, bool PAIR>
+// Every lane of cosmology r takes the root chain (no quadrature route): not near-multiple
+// roots, and for the time coordinate a radiation root large enough for an infinite limit.
+template <typename T, int KIND> __device__ __forceinline__ bool between_chain_only(const CosmoRec &r) {
+    const bool fp32 = sizeof(T) == 4;
+    if (direct_mode(KIND, r, fp32)) return false;
+    return KIND != COSMO_T || -lane_of<T>(r).sigma >= T(fp32 ? kAgeSigma32 : kAgeSigma64);
+}
+
+// CO: the cosmology is known to satisfy between_chain_only (quadrature routes compiled out).
+template <typename T, int KIND, bool PAIR, bool CO = false>
 __device__ __forceinline__ void lane_grad_between(const CosmoRec &r, T z1, T z2, LaneGrad2<T> &o) {
     const LaneConst<T> &k = lane_of<T>(r);
     const bool fp32 = sizeof(T) == 4;
     const bool zinf = z2 == Fp<T>::inf();
     const bool t_direct = KIND == COSMO_T && direct_mode(KIND, r, fp32);
     const bool t_sig = -k.sigma >= T(fp32 ? kAgeSigma32 : kAgeSigma64);
-    if (KIND == COSMO_T && !(t_direct || (zinf && !t_sig))) {
+    if (KIND == COSMO_T && (CO || !(t_direct || (zinf && !t_sig)))) {
         // time coordinate: eq. 3.8 with both limits through the Carlson derivatives (the
         // age t(z1, inf) on every lane of the wave: the upper side's constants fold)
         LaneGrad<T> &g = o.g;
@@ -681,7 +701,7 @@ __device__ __forceinline__ void lane_grad_between(const CosmoRec &r, T z1, T z2,
     ChiGrad2<T, PAIR> cg;
     chi_grad_between<T, PAIR>(k, z1, z2, cg);
     LaneGrad<T> &g = o.g;
-    g.quad = direct_mode(KIND, r, fp32);
+    g.quad = !CO && direct_mode(KIND, r, fp32);
     g.p[0] = cg.chi; g.p[1] = cg.dsig; g.p[2] = cg.dr0; g.p[3] = cg.dr1re; g.p[4] = PAIR ? cg.dr1im : cg.dr2;
     if (g.quad) {
         // near-multiple roots: the root chain is ill conditioned; Leibniz quadrature from

@@ -562,8 +562,9 @@ __global__ __launch_bounds__(kBlock, (adjoint_min_waves<T, KIND>())) void k_vjp(
 // Adjoint of the observables between two redshifts (D_C family and T): the structure of k_vjp
 // (ZPT pairs per lane, per-wave partial sums of the same accumulator slots, finalised by
 // k_finalize_params) with two redshift gradients; for limits shared by all cosmologies
-// the z1- and z2-gradients are summed over the tile in thread-private LDS slots.
-template <typename T, int KIND, bool PAIR, int ZPT>
+// the z1- and z2-gradients are summed over the tile in thread-private LDS slots.  CO: the
+// cosmology satisfies between_chain_only (no quadrature route on any lane).
+template <typename T, int KIND, bool PAIR, int ZPT, bool CO>
 __device__ __forceinline__ void between_vjp_cosmo(const CosmoRec &r, int64_t c, const T *__restrict__ z1,
                                                   const T *__restrict__ z2, int64_t n_z, int64_t zstride,
                                                   const T *__restrict__ cot, int64_t base, T acc[kAcc], T *gl1,
@@ -576,10 +577,10 @@ __device__ __forceinline__ void between_vjp_cosmo(const CosmoRec &r, int64_t c, 
         const T a = z1[c * zstride + i], b = z2[c * zstride + i];
         const T w = cot[c * n_z + i];
         LaneGrad2<T> o;
-        lane_grad_between<T, KIND, PAIR>(r, a, b, o);
+        lane_grad_between<T, KIND, PAIR, CO>(r, a, b, o);
         const LaneGrad<T> &g = o.g;
         T d[5], e[3];
-        if (g.quad) {
+        if (!CO && g.quad) {
             const double ws = (double)w * (double)g.s;
 #pragma unroll
             for (int q = 0; q < 5; ++q) d[q] = T(0);
@@ -594,10 +595,12 @@ __device__ __forceinline__ void between_vjp_cosmo(const CosmoRec &r, int64_t c, 
         }
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[q] += d[q];
-        acc[5] += w * g.dok;
+        if (KIND != COSMO_T) acc[5] += w * g.dok; // the time coordinate has no curvature transform
         acc[6] += w * g.dh;
+        if (!CO) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) acc[7 + q] += e[q];
+            for (int q = 0; q < 3; ++q) acc[7 + q] += e[q];
+        }
         if (out) out[c * n_z + i] = g.val;
         const T gz1 = w * o.dz1, gz2 = w * g.dz;
         if (zstride != 0) {
@@ -612,7 +615,13 @@ __device__ __forceinline__ void between_vjp_cosmo(const CosmoRec &r, int64_t c, 
 
 template <typename T, int KIND> constexpr int between_min_waves() { return 1; }
 
-template <typename T, int KIND, int ZPT>
+// Two passes over the same grid: PASS 0 takes the cosmologies whose lanes all follow the
+// root chain (between_chain_only: a loop without the quadrature routes, so the register
+// allocation is that loop's), PASS 1 the others, invalid ones included.  For limits
+// shared by all cosmologies, pass 0 writes the tile sums of the z1- and z2-gradients and
+// pass 1 adds its own where its block had a cosmology (launched after pass 0 on the same
+// stream).
+template <typename T, int KIND, int ZPT, int PASS>
 __global__ __launch_bounds__(kBlock, (between_min_waves<T, KIND>())) void k_between_vjp(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
                                                         const T *__restrict__ z1, const T *__restrict__ z2,
                                                         int64_t n_z, int64_t zstride, const T *__restrict__ cot,
@@ -630,14 +639,21 @@ __global__ __launch_bounds__(kBlock, (between_min_waves<T, KIND>())) void k_betw
     const int64_t c0 = tile * ct;
     const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
     for (int k = 0; k < ZPT; ++k) gl1[k * kBlock + threadIdx.x] = gl2[k * kBlock + threadIdx.x] = T(0);
+    bool any = false; // the same on every thread of the block
     for (int64_t c = c0; c < c1; ++c) {
         const CosmoRec &r = recs[c];
+        const bool chain = r.valid && between_chain_only<T, KIND>(r);
+        if (chain != (PASS == 0)) continue;
+        any = true;
         T acc[kAcc];
 #pragma unroll
         for (int s = 0; s < kAcc; ++s) acc[s] = T(0);
-        if (r.valid) {
-            if (r.pair) between_vjp_cosmo<T, KIND, true, ZPT>(r, c, z1, z2, n_z, zstride, cot, base, acc, gl1, gl2, g1_out, g2_out, out);
-            else between_vjp_cosmo<T, KIND, false, ZPT>(r, c, z1, z2, n_z, zstride, cot, base, acc, gl1, gl2, g1_out, g2_out, out);
+        if (PASS == 0) {
+            if (r.pair) between_vjp_cosmo<T, KIND, true, ZPT, true>(r, c, z1, z2, n_z, zstride, cot, base, acc, gl1, gl2, g1_out, g2_out, out);
+            else between_vjp_cosmo<T, KIND, false, ZPT, true>(r, c, z1, z2, n_z, zstride, cot, base, acc, gl1, gl2, g1_out, g2_out, out);
+        } else if (r.valid) {
+            if (r.pair) between_vjp_cosmo<T, KIND, true, ZPT, false>(r, c, z1, z2, n_z, zstride, cot, base, acc, gl1, gl2, g1_out, g2_out, out);
+            else between_vjp_cosmo<T, KIND, false, ZPT, false>(r, c, z1, z2, n_z, zstride, cot, base, acc, gl1, gl2, g1_out, g2_out, out);
         } else {
             for (int k = 0; k < ZPT; ++k) {
                 const int64_t i = base + (int64_t)k * kBlock;
@@ -654,18 +670,18 @@ __global__ __launch_bounds__(kBlock, (between_min_waves<T, KIND>())) void k_betw
         }
         if (pacc) store_partials(acc, pacc + (c * nwz + gw) * kAcc, lane);
     }
-    if (zstride == 0) {
+    if (zstride == 0 && (PASS == 0 || any)) {
         for (int k = 0; k < ZPT; ++k) {
             const int64_t i = base + (int64_t)k * kBlock;
             if (i >= n_z) break;
             const T v1 = gl1[k * kBlock + threadIdx.x], v2 = gl2[k * kBlock + threadIdx.x];
             if (g1_out) {
-                if (g1_part) g1_part[tile * n_z + i] = v1;
-                else g1_out[i] = v1;
+                T *d = g1_part ? g1_part + tile * n_z + i : g1_out + i;
+                *d = PASS == 0 ? v1 : *d + v1;
             }
             if (g2_out) {
-                if (g2_part) g2_part[tile * n_z + i] = v2;
-                else g2_out[i] = v2;
+                T *d = g2_part ? g2_part + tile * n_z + i : g2_out + i;
+                *d = PASS == 0 ? v2 : *d + v2;
             }
         }
     }
@@ -1238,8 +1254,12 @@ int launch_between_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T 
     T *p2 = (part && g2) ? (T *)(ws + L.gzp) + (size_t)t.ntile * (size_t)n_z : nullptr;
     dim3 grid((unsigned)t.nblocks), block(kBlock);
 #define COSMO_BVJP_Z(K, Z)                                                                                      \
-    hipLaunchKernelGGL((k_between_vjp<T, K, Z>), grid, block, 0, s, recs, n_cosmo, z1, z2, n_z, zstride, cot,   \
-                       pacc, g1, g2, p1, p2, out, t.ct, t.nzb)
+    do {                                                                                                        \
+        hipLaunchKernelGGL((k_between_vjp<T, K, Z, 0>), grid, block, 0, s, recs, n_cosmo, z1, z2, n_z, zstride, \
+                           cot, pacc, g1, g2, p1, p2, out, t.ct, t.nzb);                                        \
+        hipLaunchKernelGGL((k_between_vjp<T, K, Z, 1>), grid, block, 0, s, recs, n_cosmo, z1, z2, n_z, zstride, \
+                           cot, pacc, g1, g2, p1, p2, out, t.ct, t.nzb);                                        \
+    } while (0)
 #define COSMO_BVJP(K)                                                                                           \
     if (zpt == 8) COSMO_BVJP_Z(K, 8);                                                                           \
     else COSMO_BVJP_Z(K, 1)
