@@ -488,24 +488,16 @@ __device__ __forceinline__ void t_grad_between(const CosmoRec &r, T z1, T z2, TG
     const T dB_dV0 = c3 * dJ0 - k.sigma * rdx * T(1.0 / 6.0) + dB_dW;
     const cx<T> dB_dV1 = dJ1 * c3 - rdy * (k.sigma * T(1.0 / 6.0));
     const T dB_dV2 = PAIR ? T(0) : c3 * dJ2 - k.sigma * rdz * T(1.0 / 6.0);
-    // explicit dependence of P3, C5, Rp and Q on sigma and the roots
-    const T s = k.sigma;
-    const cx<T> om1 = mkc(T(1) - s * k.r1re, -s * k.r1im);
-    const cx<T> om2 = PAIR ? conj(om1) : mkc(T(1) - s * k.r2, T(0));
-    const T om0 = T(1) - s * k.r0;
-    const cx<T> r1 = mkc(k.r1re, k.r1im);
-    const cx<T> r2 = PAIR ? conj(r1) : mkc(k.r2, T(0));
-    const T om12 = (om1 * om2).re;
-    const T r1o2_r2o1 = (r1 * om2).re + (r2 * om1).re;
-    const T dP3_ds = -(k.r0 * om12 + om0 * r1o2_r2o1);
-    const T dC5_ds = -k.r0 * r1o2_r2o1;
+    // explicit dependence of P3, C5, Rp and Q on sigma and the roots (the coefficients
+    // are per-cosmology constants of the set-up: tdp3 = dP3/dsigma, tdc5 = dC5/dsigma,
+    // om1s12 = o1 o2, tso12 = -sigma o1 o2, tr12 = r1 r2, tq1..3 and, for three real roots,
+    // tq4..6, with o_n = 1 - sigma r_n)
     const T dQ_ds = ad.rc_zero ? T(0) : Qv * (B_.x * b.it2 + A_.x * a.it2);
-    const T d23 = d2 * T(1.0 / 3.0);
-    T dsig = d23 * rj * dP3_ds + dB_dW * d2 * dC5_ds + dRC_sum * dQ_ds + rf;
-    T dr0 = d23 * rj * (-s * om12) + dB_dW * d2 * om12 + dRC_S * (-d2 * (r1 * r2).re);
-    cx<T> dr1 = (om0 * om2 * (-s)) * (d23 * rj) + om2 * (-s * k.r0) * (dB_dW * d2) + (r2 * k.r0) * (-d2 * dRC_S);
-    T dr2 = PAIR ? T(0)
-                 : d23 * rj * (-s * om0 * om1.re) + dB_dW * d2 * (-s * om1.re * k.r0) + dRC_S * (-d2 * k.r0 * k.r1re);
+    const T jr = d2 * T(1.0 / 3.0) * rj, bw = dB_dW * d2, rs = -d2 * dRC_S;
+    T dsig = jr * k.tdp3 + bw * k.tdc5 + dRC_sum * dQ_ds + rf;
+    T dr0 = jr * k.tso12 + bw * k.om1s12 + rs * k.tr12;
+    cx<T> dr1 = mkc(jr * k.tq1re + bw * k.tq2re + rs * k.tq3re, jr * k.tq1im + bw * k.tq2im + rs * k.tq3im);
+    T dr2 = PAIR ? T(0) : jr * k.tq4 + bw * k.tq5 + rs * k.tq6;
     // through the Carlson arguments V_m = U_m^2, with both limits' square roots
     const T G0 = dB_dV0 * T(2) * U0;
     const T a0 = G0 * T1_0, b0 = G0 * T2_0;
@@ -537,7 +529,7 @@ __device__ __forceinline__ void t_grad_between(const CosmoRec &r, T z1, T z2, TG
         }
     }
     const T scale = k.pre2 * dz;
-    o.t = scale * (c3 * rj + rc + s * rf);
+    o.t = scale * (c3 * rj + rc + k.sigma * rf);
     o.dsig = scale * dsig;
     o.dr0 = scale * dr0;
     o.dr1re = scale * dr1.re;

@@ -434,9 +434,9 @@ template <typename T> __device__ __forceinline__ void rc_rd_r(T x, T y, T &rc, T
 // dR_F/dx_k = -R_D(., ., x_k)/6 (eq. 2.10), from one duplication sequence.
 // Outputs: rf; rdx = R_D(y, z, x); rdy = R_D(x, z, y) (complex for PAIR; for a
 // PAIR triple R_D(x, y, z) = conj(rdy)); rdz = R_D(x, y, z) for real triples.
-// rdx is not accumulated: it follows from the cyclic identity
-// R_D(x,y,z) + R_D(y,z,x) + R_D(z,x,y) = 3/sqrt(xyz) (DLMF 19.21.7), whose terms are
-// of one size on these argument triples (cancellation below a factor 5).
+// Each R_D(., ., x_k) is accumulated along the sequence (the tests check the three
+// against the cyclic identity R_D(x,y,z) + R_D(y,z,x) + R_D(z,x,y) = 3/sqrt(xyz),
+// DLMF 19.21.7).
 // End of a structured duplication sequence for R_F and the three R_D(., ., x_k):
 // R_F from its seventh-order expansion about the final mean A, and the R_D tails
 // 4^-m R_D(x_m, y_m, z_m; last x_k) from the derivative of that same expansion

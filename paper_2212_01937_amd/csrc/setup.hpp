@@ -76,6 +76,15 @@ template <typename T> struct LaneConst {
     T w1im2, hw1im, sw1im;  // pair: Im(w_1)^2, |Im(w_1)|/2, sign of Im(w_1) (+-1)
     T k5hinv;               // (5 / ln 10) / H0: minus dmu/dH0
     T tinf, itinf2;         // sqrt(-sigma) and 1/(-sigma): an infinite limit's scaled sqrt(1 - sigma x)
+    // T between two limits: the explicit sigma- and root-dependence of eq. 3.8's
+    // coefficients (o_n = 1 - sigma r_n; slot 1 with its partner slot 2, and for three
+    // real roots slot 2 with partner 1)
+    T tdp3, tdc5;           // dP3/dsigma = -(r0 o1 o2 + o0 (r1 o2 + r2 o1)), dC5/dsigma = -r0 (r1 o2 + r2 o1)
+    T tso12, tr12;          // -sigma o1 o2, r1 r2 (real parts)
+    T tq1re, tq1im;         // -sigma o0 o2
+    T tq2re, tq2im;         // -sigma r0 o2
+    T tq3re, tq3im;         // r0 r2
+    T tq4, tq5, tq6;        // three real roots: -sigma o0 o1, -sigma r0 o1, r0 r1
 };
 
 struct CosmoRec {
@@ -216,6 +225,9 @@ template <typename T> __device__ void fill_lane(LaneConst<T> &L, const LaneConst
     L.w1im2 = T(D.w1im2); L.hw1im = T(D.hw1im); L.sw1im = T(D.sw1im);
     L.k5hinv = T(D.k5hinv);
     L.tinf = T(D.tinf); L.itinf2 = T(D.itinf2);
+    L.tdp3 = T(D.tdp3); L.tdc5 = T(D.tdc5); L.tso12 = T(D.tso12); L.tr12 = T(D.tr12);
+    L.tq1re = T(D.tq1re); L.tq1im = T(D.tq1im); L.tq2re = T(D.tq2re); L.tq2im = T(D.tq2im);
+    L.tq3re = T(D.tq3re); L.tq3im = T(D.tq3im); L.tq4 = T(D.tq4); L.tq5 = T(D.tq5); L.tq6 = T(D.tq6);
 }
 
 // dP/dtheta at x for theta = Om, OL, Or (Ok eliminated)
@@ -420,6 +432,17 @@ __device__ void setup_cosmo(const double *prm, CosmoRec &rec) {
         D.c5c = (o0 * o1 * rho[2]).re;
     }
     D.pre3 = o12 * (1.0 - sigma * s0);
+    {   // explicit dependence of the time coordinate's coefficients (t_grad_between)
+        const double o0 = 1.0 - sigma * s0;
+        const double ro = (rho[1] * o2).re + (rho[2] * o1).re;
+        D.tdp3 = -(s0 * o12 + o0 * ro);
+        D.tdc5 = -s0 * ro;
+        D.tso12 = -sigma * o12;
+        D.tr12 = (rho[1] * rho[2]).re;
+        const cx<double> q1 = o2 * (-sigma * o0), q2 = o2 * (-sigma * s0), q3 = rho[2] * s0;
+        D.tq1re = q1.re; D.tq1im = q1.im; D.tq2re = q2.re; D.tq2im = q2.im; D.tq3re = q3.re; D.tq3im = q3.im;
+        D.tq4 = -sigma * o0 * o1.re; D.tq5 = -sigma * s0 * o1.re; D.tq6 = s0 * rho[1].re;
+    }
     D.rprod = (rho[0] * rho[1] * rho[2]).re;
     cx<double> d01 = rho[1] - rho[0], d02 = rho[2] - rho[0];
     double d0102 = (d01 * d02).re;
