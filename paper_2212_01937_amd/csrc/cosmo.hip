@@ -615,29 +615,33 @@ __device__ __forceinline__ void between_vjp_cosmo(const CosmoRec &r, int64_t c, 
 
 template <typename T, int KIND> constexpr int between_min_waves() { return 1; }
 
-// Two passes over the same grid: PASS 0 takes the cosmologies whose lanes all follow the
-// root chain (between_chain_only: a loop without the quadrature routes, so the register
-// allocation is that loop's), PASS 1 the others, invalid ones included.  For limits
-// shared by all cosmologies, pass 0 writes the tile sums of the z1- and z2-gradients and
-// pass 1 adds its own where its block had a cosmology (launched after pass 0 on the same
-// stream).
+// Two passes over the (cosmology tile, z block) pairs: PASS 0 takes the cosmologies whose
+// lanes all follow the root chain (between_chain_only: a loop without the quadrature
+// routes, so the register allocation is that loop's), PASS 1 the others, invalid ones
+// included.  For limits shared by all cosmologies, pass 0 writes the tile sums of the z1-
+// and z2-gradients and pass 1 adds its own where its block had a cosmology (launched
+// after pass 0 on the same stream).  Pass 0 has one block per pair; pass 1, which usually
+// finds nothing to do, strides over the pairs with a smaller grid and leaves a tile
+// after reading its records.
 template <typename T, int KIND, int ZPT, int PASS>
-__global__ __launch_bounds__(kBlock, (between_min_waves<T, KIND>())) void k_between_vjp(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
-                                                        const T *__restrict__ z1, const T *__restrict__ z2,
-                                                        int64_t n_z, int64_t zstride, const T *__restrict__ cot,
-                                                        T *__restrict__ pacc, T *__restrict__ g1_out,
-                                                        T *__restrict__ g2_out, T *__restrict__ g1_part,
-                                                        T *__restrict__ g2_part, T *__restrict__ out, int ct,
-                                                        int64_t nzb) {
-    __shared__ T gl1[ZPT * kBlock], gl2[ZPT * kBlock];
-    int64_t tile, zb;
-    block_tile(nzb, tile, zb);
-    const int64_t base = zb * (int64_t)(kBlock * ZPT) + threadIdx.x;
+__device__ __forceinline__ void between_vjp_block(int64_t b, const CosmoRec *__restrict__ recs, int64_t n_cosmo,
+                                                  const T *__restrict__ z1, const T *__restrict__ z2, int64_t n_z,
+                                                  int64_t zstride, const T *__restrict__ cot, T *__restrict__ pacc,
+                                                  T *__restrict__ g1_out, T *__restrict__ g2_out,
+                                                  T *__restrict__ g1_part, T *__restrict__ g2_part,
+                                                  T *__restrict__ out, int ct, int64_t nzb, T *gl1, T *gl2) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t nwz = nzb * (kBlock / 64);
+    const int64_t tile = b / nzb, zb = b - tile * nzb;
+    const int64_t base = zb * (int64_t)(kBlock * ZPT) + threadIdx.x;
     const int64_t gw = zb * (kBlock / 64) + wave;
     const int64_t c0 = tile * ct;
     const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
+    if (PASS == 1) {
+        bool has = false;
+        for (int64_t c = c0; c < c1; ++c) has |= !(recs[c].valid && between_chain_only<T, KIND>(recs[c]));
+        if (!has) return;
+    }
     for (int k = 0; k < ZPT; ++k) gl1[k * kBlock + threadIdx.x] = gl2[k * kBlock + threadIdx.x] = T(0);
     bool any = false; // the same on every thread of the block
     for (int64_t c = c0; c < c1; ++c) {
@@ -684,6 +688,25 @@ __global__ __launch_bounds__(kBlock, (between_min_waves<T, KIND>())) void k_betw
                 *d = PASS == 0 ? v2 : *d + v2;
             }
         }
+    }
+}
+
+template <typename T, int KIND, int ZPT, int PASS>
+__global__ __launch_bounds__(kBlock, (between_min_waves<T, KIND>())) void k_between_vjp(const CosmoRec *__restrict__ recs, int64_t n_cosmo,
+                                                        const T *__restrict__ z1, const T *__restrict__ z2,
+                                                        int64_t n_z, int64_t zstride, const T *__restrict__ cot,
+                                                        T *__restrict__ pacc, T *__restrict__ g1_out,
+                                                        T *__restrict__ g2_out, T *__restrict__ g1_part,
+                                                        T *__restrict__ g2_part, T *__restrict__ out, int ct,
+                                                        int64_t nzb, int64_t nblocks) {
+    __shared__ T gl1[ZPT * kBlock], gl2[ZPT * kBlock];
+    if (PASS == 0) {
+        between_vjp_block<T, KIND, ZPT, 0>(blockIdx.x, recs, n_cosmo, z1, z2, n_z, zstride, cot, pacc, g1_out, g2_out,
+                                           g1_part, g2_part, out, ct, nzb, gl1, gl2);
+    } else {
+        for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x)
+            between_vjp_block<T, KIND, ZPT, 1>(b, recs, n_cosmo, z1, z2, n_z, zstride, cot, pacc, g1_out, g2_out,
+                                               g1_part, g2_part, out, ct, nzb, gl1, gl2);
     }
 }
 
@@ -1253,12 +1276,13 @@ int launch_between_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T 
     T *p1 = (part && g1) ? (T *)(ws + L.gzp) : nullptr;
     T *p2 = (part && g2) ? (T *)(ws + L.gzp) + (size_t)t.ntile * (size_t)n_z : nullptr;
     dim3 grid((unsigned)t.nblocks), block(kBlock);
+    dim3 grid1((unsigned)(t.nblocks < 2048 ? t.nblocks : 2048)); // the quadrature pass (grid-stride)
 #define COSMO_BVJP_Z(K, Z)                                                                                      \
     do {                                                                                                        \
         hipLaunchKernelGGL((k_between_vjp<T, K, Z, 0>), grid, block, 0, s, recs, n_cosmo, z1, z2, n_z, zstride, \
-                           cot, pacc, g1, g2, p1, p2, out, t.ct, t.nzb);                                        \
-        hipLaunchKernelGGL((k_between_vjp<T, K, Z, 1>), grid, block, 0, s, recs, n_cosmo, z1, z2, n_z, zstride, \
-                           cot, pacc, g1, g2, p1, p2, out, t.ct, t.nzb);                                        \
+                           cot, pacc, g1, g2, p1, p2, out, t.ct, t.nzb, t.nblocks);                             \
+        hipLaunchKernelGGL((k_between_vjp<T, K, Z, 1>), grid1, block, 0, s, recs, n_cosmo, z1, z2, n_z,         \
+                           zstride, cot, pacc, g1, g2, p1, p2, out, t.ct, t.nzb, t.nblocks);                    \
     } while (0)
 #define COSMO_BVJP(K)                                                                                           \
     if (zpt == 8) COSMO_BVJP_Z(K, 8);                                                                           \

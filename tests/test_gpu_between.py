@@ -311,6 +311,53 @@ def test_between_vjp_edge_cases():
 _ORACLE_CACHE = {}
 
 
+def _mixed_case(kind):
+    """Shared limits on 24 cosmologies that alternate between the large batch's (every lane
+    on the root chain) and the near-degenerate families (near-multiple roots, radiation down
+    to zero: the quadrature routes), 180000 pairs each -- enough work per cosmology for
+    tiles of two, so that both passes of the adjoint meet in one tile and add to the same
+    shared-limit sums.  Limits exactly representable in FP32."""
+    key = ("mixed", kind)
+    if key not in _ORACLE_CACHE:
+        rng = np.random.default_rng(43)
+        p5, _ = workloads.config5(n_cosmo=12, n_z=8)
+        p4, _, _ = workloads.config4(n_per_family=3, n_z=8)
+        params = np.empty((24, 4))
+        params[0::2], params[1::2] = p5, p4
+        n = 180000
+        if kind == "T":
+            z1, z2 = workloads.age_redshifts(n=n), np.full(n, np.inf)
+        else:
+            z1, z2 = workloads.lensing_pairs(n=n)
+        z1 = z1.astype(np.float32).astype(np.float64)
+        z2 = z2.astype(np.float32).astype(np.float64)
+        w = rng.standard_normal((24, n)).astype(np.float32).astype(np.float64)
+        _ORACLE_CACHE[key] = (params, z1, z2, w, ref_between_vjp(kind, params, z1, z2, w))
+    return _ORACLE_CACHE[key]
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", ["T", "DC"])
+def test_between_vjp_mixed_routes_in_one_tile(kind, dt):
+    """The two passes of the between-limit adjoint (root-chain cosmologies, then those
+    with a quadrature route) on shared limits, with tiles holding one cosmology of each:
+    grad_params, the shared grad_z1/grad_z2 sums and the value against the oracle."""
+    params, z1, z2, w, (rgp, sp, r1, r2, s1, s2) = _mixed_case(kind)
+    p = torch.tensor(params, device=DEV)
+    a = torch.tensor(z1, dtype=dt, device=DEV)
+    b = torch.tensor(z2, dtype=dt, device=DEV)
+    wt = torch.tensor(w, dtype=dt, device=DEV)
+    val, gp, g1, g2 = cosmo.cosmo_distance_between_vjp(kind, p, a, b, wt, want_value=True)
+    tol = GTOL[dt]
+    ep = (np.abs(gp.cpu().numpy() - rgp) / sp).max(0)
+    note(f"between-vjp mixed tiles {kind} {dt} grad_params", (ep / gptol(dt)).max(), 1.0)
+    assert np.all(ep <= gptol(dt)), (kind, dt, ep)
+    for got, ref, sc in ((g1, r1.sum(0), s1.sum(0)), (g2, r2.sum(0), s2.sum(0))):
+        e = np.abs(got.double().cpu().numpy() - ref) / np.maximum(sc, 1e-300 + 1e-12 * sc.max())
+        assert e.max() <= tol, (kind, dt, float(e.max()))
+    check(kind, dt, params, z1, z2, val, "value from the adjoint, mixed tiles")
+
+
 def _mid_case(kind, shared):
     """Limits exactly representable in FP32 (one oracle evaluation serves both paths):
     2 non-flat cosmologies x 8300 pairs -- past the row length at which the adjoint
