@@ -646,7 +646,7 @@ __device__ void rfjd_s(T x, T a, T b, T p, T &rf, T &rj, T &rdx, cx<T> &rdy, T &
     const T QF = spread3<T, PAIR>(AF0, x, a, b);
     const T QJ = tmax(spread3<T, PAIR>(AJ0, x, a, b), spread1<T, PAIR>(AJ0 - p));
     const T delta = PAIR ? (p - x) * ((p - a) * (p - a) + b * b) : (p - x) * (p - a) * (p - b);
-    T AF = AF0, AJ = AJ0, f = T(1), acc = T(0), accx = T(0), accz = T(0);
+    T AF = AF0, AJ = AJ0, f = T(1), acc = T(0), accz = T(0);
     cx<T> accy = mkc(T(0), T(0));
     for (int m = 0; m < kMaxDup && (spread_above<T, PAIR>(QF, f, Fp<T>::tau7, AF) ||
                                    spread_above<T, PAIR>(QJ, f, Fp<T>::tau5, AJ)); ++m) {
@@ -665,7 +665,6 @@ __device__ void rfjd_s(T x, T a, T b, T p, T &rf, T &rj, T &rdx, cx<T> &rdy, T &
             accy.re += f * Fp<T>::rcp(sy * (a + lam));
             accz += f * Fp<T>::rcp(sz * (b + lam));
         }
-        accx += f * Fp<T>::rcp(sx * (x + lam));
         T rdd = Fp<T>::rcp(d);
         acc += f * rc1_r(delta * rdd * rdd * (f * f * f)) * rdd;
         x = (x + lam) * T(0.25);
@@ -679,9 +678,13 @@ __device__ void rfjd_s(T x, T a, T b, T p, T &rf, T &rj, T &rdx, cx<T> &rdy, T &
     T tx, tz;
     cx<T> ty;
     rfd_tails<T, PAIR>(AF0, x0, a0, b0, AF, f, rf, tx, ty, tz);
-    rdx = T(3) * accx + tx;
     rdy = accy * T(3) + ty;
     rdz = T(3) * accz + tz;
+    // R_D(y, z, x) from the cyclic identity R_D(x,y,z) + R_D(y,z,x) + R_D(z,x,y) =
+    // 3/sqrt(xyz) (DLMF 19.21.7) instead of a third accumulation (on the time
+    // coordinate's triples the terms are of one size; tested against the oracle)
+    if (PAIR) rdx = T(3) * Fp<T>::rsqrt(x0 * (a0 * a0 + b0 * b0)) - T(2) * rdy.re;
+    else rdx = T(3) * Fp<T>::rsqrt(x0 * a0 * b0) - rdy.re - rdz;
     {
         const T rj_a = Fp<T>::rsqrt(AJ);
         T g = f * (rj_a * rj_a);

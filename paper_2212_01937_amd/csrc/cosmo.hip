@@ -621,8 +621,8 @@ template <typename T, int KIND> constexpr int between_min_waves() { return 1; }
 // included.  For limits shared by all cosmologies, pass 0 writes the tile sums of the z1-
 // and z2-gradients and pass 1 adds its own where its block had a cosmology (launched
 // after pass 0 on the same stream).  Pass 0 has one block per pair; pass 1, which usually
-// finds nothing to do, strides over the pairs with a smaller grid and leaves a tile
-// after reading its records.
+// finds nothing to do, has up to 128 blocks per tile (grid y), which test the tile's
+// records once and leave, or stride over its z blocks.
 template <typename T, int KIND, int ZPT, int PASS>
 __device__ __forceinline__ void between_vjp_block(int64_t b, const CosmoRec *__restrict__ recs, int64_t n_cosmo,
                                                   const T *__restrict__ z1, const T *__restrict__ z2, int64_t n_z,
@@ -637,11 +637,6 @@ __device__ __forceinline__ void between_vjp_block(int64_t b, const CosmoRec *__r
     const int64_t gw = zb * (kBlock / 64) + wave;
     const int64_t c0 = tile * ct;
     const int64_t c1 = c0 + ct < n_cosmo ? c0 + ct : n_cosmo;
-    if (PASS == 1) {
-        bool has = false;
-        for (int64_t c = c0; c < c1; ++c) has |= !(recs[c].valid && between_chain_only<T, KIND>(recs[c]));
-        if (!has) return;
-    }
     for (int k = 0; k < ZPT; ++k) gl1[k * kBlock + threadIdx.x] = gl2[k * kBlock + threadIdx.x] = T(0);
     bool any = false; // the same on every thread of the block
     for (int64_t c = c0; c < c1; ++c) {
@@ -698,15 +693,23 @@ __global__ __launch_bounds__(kBlock, (between_min_waves<T, KIND>())) void k_betw
                                                         T *__restrict__ pacc, T *__restrict__ g1_out,
                                                         T *__restrict__ g2_out, T *__restrict__ g1_part,
                                                         T *__restrict__ g2_part, T *__restrict__ out, int ct,
-                                                        int64_t nzb, int64_t nblocks) {
+                                                        int64_t nzb) {
     __shared__ T gl1[ZPT * kBlock], gl2[ZPT * kBlock];
     if (PASS == 0) {
         between_vjp_block<T, KIND, ZPT, 0>(blockIdx.x, recs, n_cosmo, z1, z2, n_z, zstride, cot, pacc, g1_out, g2_out,
                                            g1_part, g2_part, out, ct, nzb, gl1, gl2);
     } else {
-        for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x)
-            between_vjp_block<T, KIND, ZPT, 1>(b, recs, n_cosmo, z1, z2, n_z, zstride, cot, pacc, g1_out, g2_out,
-                                               g1_part, g2_part, out, ct, nzb, gl1, gl2);
+        // grid (z-block groups, tiles): the tile's records are tested once, one per lane
+        const int64_t tile = blockIdx.y;
+        bool other = false;
+        for (int64_t j = threadIdx.x; j < ct; j += kBlock) {
+            const int64_t c = tile * ct + j;
+            other |= c < n_cosmo && !(recs[c].valid && between_chain_only<T, KIND>(recs[c]));
+        }
+        if (!__syncthreads_or(other)) return;
+        for (int64_t zb = blockIdx.x; zb < nzb; zb += gridDim.x)
+            between_vjp_block<T, KIND, ZPT, 1>(tile * nzb + zb, recs, n_cosmo, z1, z2, n_z, zstride, cot, pacc,
+                                               g1_out, g2_out, g1_part, g2_part, out, ct, nzb, gl1, gl2);
     }
 }
 
@@ -1276,13 +1279,13 @@ int launch_between_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T 
     T *p1 = (part && g1) ? (T *)(ws + L.gzp) : nullptr;
     T *p2 = (part && g2) ? (T *)(ws + L.gzp) + (size_t)t.ntile * (size_t)n_z : nullptr;
     dim3 grid((unsigned)t.nblocks), block(kBlock);
-    dim3 grid1((unsigned)(t.nblocks < 2048 ? t.nblocks : 2048)); // the quadrature pass (grid-stride)
+    dim3 grid1((unsigned)(t.nzb < 128 ? t.nzb : 128), (unsigned)t.ntile); // the quadrature pass
 #define COSMO_BVJP_Z(K, Z)                                                                                      \
     do {                                                                                                        \
         hipLaunchKernelGGL((k_between_vjp<T, K, Z, 0>), grid, block, 0, s, recs, n_cosmo, z1, z2, n_z, zstride, \
-                           cot, pacc, g1, g2, p1, p2, out, t.ct, t.nzb, t.nblocks);                             \
+                           cot, pacc, g1, g2, p1, p2, out, t.ct, t.nzb);                                        \
         hipLaunchKernelGGL((k_between_vjp<T, K, Z, 1>), grid1, block, 0, s, recs, n_cosmo, z1, z2, n_z,         \
-                           zstride, cot, pacc, g1, g2, p1, p2, out, t.ct, t.nzb, t.nblocks);                    \
+                           zstride, cot, pacc, g1, g2, p1, p2, out, t.ct, t.nzb);                               \
     } while (0)
 #define COSMO_BVJP(K)                                                                                           \
     if (zpt == 8) COSMO_BVJP_Z(K, 8);                                                                           \
