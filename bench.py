@@ -311,11 +311,11 @@ def main():
             btw[f"{path}_DA_lens_value_and_grad_ms"] = float(np.median(ev))
             btw[f"{path}_DA_lens_value_and_grad_evals_per_s"] = evals / (np.median(ev) * 1e-3)
 
-            # the age t(z, inf) with its gradients (parameters by the Leibniz quadrature)
+            # the age t(z, inf) with its gradients (eq. 3.8's Carlson derivatives at both limits)
             def fag():
                 return cosmo.cosmo_distance_between_vjp("T", p, za, zinf, wb, want_value=True, workspace=ws)
             fag()
-            ev, _, _ = timed(fag, 2, stream, torch)
+            ev, _, _ = timed(fag, max(2, args.steps // 2), stream, torch)
             btw[f"{path}_T_age_value_and_grad_ms"] = float(np.median(ev))
             btw[f"{path}_T_age_value_and_grad_evals_per_s"] = evals / (np.median(ev) * 1e-3)
             del a, b, za, zinf, wb
