@@ -211,10 +211,10 @@ int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params,
  *  - The array holds COSMO_NOALLOC_SCRATCH_BYTES per GPU.  A call needs the record
  *    table (under 1 KB per cosmology); with grad_params, 44 B (FP32) or 88 B (FP64)
  *    per cosmology per 512 redshifts (per 64 redshifts when n_z < 8192); with a
- *    shared-z grad_z and more than one tile of cosmologies (tiles of up to 16),
+ *    shared-z grad_z and more than one tile of cosmologies (tiles of up to 8),
  *    one dtype element per redshift per tile.  It fits whenever
  *    cosmo_workspace_size(n_cosmo, n_z) <= COSMO_NOALLOC_SCRATCH_BYTES, and often
- *    beyond (64 cosmologies x 1e6 shared redshifts fit in either dtype).  Larger
+ *    beyond (1e6 shared redshifts: 64 cosmologies fit in FP32, 32 in FP64).  Larger
  *    problems return COSMO_E_SCRATCH, detected on the host before any HIP call.
  *  - The first call on a GPU resolves the array's device address there
  *    (hipGetSymbolAddress, with that GPU current); make that first call outside a

@@ -1035,15 +1035,15 @@ struct Tiling {
 };
 
 // zpt: redshifts per lane (1 for the forward kernels; the adjoint uses 8 on long
-// redshift rows).  Cosmology tiles of up to 16 are formed while the grid keeps
+// redshift rows).  Cosmology tiles of up to ct_max are formed while the grid keeps
 // about 8192 lane-blocks of work.
-Tiling tiling(int64_t n_cosmo, int64_t n_z, int zpt = 1) {
+Tiling tiling(int64_t n_cosmo, int64_t n_z, int zpt = 1, int ct_max = 16) {
     Tiling t;
     const int64_t span = (int64_t)kBlock * zpt;
     t.nzb = (n_z + span - 1) / span;
     if (t.nzb < 1) t.nzb = 1;
     int64_t want = (n_cosmo * t.nzb * zpt) / 8192;
-    t.ct = (int)(want < 1 ? 1 : (want > 16 ? 16 : want));
+    t.ct = (int)(want < 1 ? 1 : (want > ct_max ? ct_max : want));
     // at most 65535 tiles (the forward and Jacobian grids put them on the y axis)
     const int64_t ct_min = (n_cosmo + 65534) / 65535;
     if (t.ct < ct_min) t.ct = (int)ct_min;
@@ -1054,6 +1054,17 @@ Tiling tiling(int64_t n_cosmo, int64_t n_z, int zpt = 1) {
 
 int vjp_zpt(int64_t n_z) { return n_z >= 8192 ? 8 : 1; }
 
+// Tiles of the adjoints: up to kVjpTile cosmologies (the forward and Jacobian kernels
+// take up to 16).  On 256 cosmologies x 1e6 shared redshifts, tiles of 8 ran the fused
+// step 3% and the gradient-only call 5% faster than tiles of 16 (twice the blocks and
+// tile partials of the shared-z gradient), tiles of 24 and 32 slower.
+constexpr int kVjpTile = 8;
+constexpr int kBetweenVjpTile = 16;
+Tiling vjp_tiling(int64_t n_cosmo, int64_t n_z) { return tiling(n_cosmo, n_z, vjp_zpt(n_z), kVjpTile); }
+Tiling between_vjp_tiling(int64_t n_cosmo, int64_t n_z) {
+    return tiling(n_cosmo, n_z, vjp_zpt(n_z), kBetweenVjpTile);
+}
+
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct WsLayout {
@@ -1061,12 +1072,15 @@ struct WsLayout {
 };
 
 WsLayout ws_layout(int64_t n_cosmo, int64_t n_z) {
-    Tiling t = tiling(n_cosmo, n_z, vjp_zpt(n_z));
+    const Tiling t = vjp_tiling(n_cosmo, n_z), tb = between_vjp_tiling(n_cosmo, n_z);
     WsLayout w;
     w.recs = 0;
     w.pacc = align256(sizeof(CosmoRec) * (size_t)n_cosmo);
     w.gzp = w.pacc + align256(sizeof(double) * kAcc * (size_t)n_cosmo * (size_t)t.nzb * (kBlock / 64));
-    w.total = w.gzp + align256(sizeof(double) * 2 * (size_t)t.ntile * (size_t)n_z); // z1 and z2 planes (between adjoint)
+    // one tile-partial plane of the shared-z gradient (distance adjoint) or two (z1 and
+    // z2, between adjoint)
+    const size_t planes = (size_t)t.ntile > 2 * (size_t)tb.ntile ? (size_t)t.ntile : 2 * (size_t)tb.ntile;
+    w.total = w.gzp + align256(sizeof(double) * planes * (size_t)n_z);
     return w;
 }
 
@@ -1102,7 +1116,7 @@ int scratch_address(void **out) {
 // partial sums in the lane precision and only the tile-partial plane this call uses.
 template <typename T>
 WsLayout noalloc_layout(int64_t n_cosmo, int64_t n_z, int64_t zstride, bool want_params, bool want_z) {
-    Tiling t = tiling(n_cosmo, n_z, vjp_zpt(n_z));
+    Tiling t = vjp_tiling(n_cosmo, n_z);
     WsLayout w;
     w.recs = 0;
     w.pacc = align256(sizeof(CosmoRec) * (size_t)n_cosmo);
@@ -1226,7 +1240,7 @@ int launch_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int6
                const T *cot, const T *ivar, const double *wc, double *loglike, T *out, double *grad_params,
                T *grad_z, int32_t *info, const WsLayout &L, char *ws, hipStream_t s) {
     const int zpt = vjp_zpt(n_z);
-    Tiling t = tiling(n_cosmo, n_z, zpt);
+    Tiling t = vjp_tiling(n_cosmo, n_z);
     const bool like = ivar != nullptr;
     T *pacc = (grad_params || loglike) ? (T *)(ws + L.pacc) : nullptr;
     T *gzp = (grad_z && zstride == 0 && t.ntile > 1 && n_z > 0) ? (T *)(ws + L.gzp) : nullptr;
@@ -1273,7 +1287,7 @@ int launch_between_vjp(int kind, const CosmoRec *recs, int64_t n_cosmo, const T 
                        int64_t zstride, const T *cot, T *out, double *grad_params, T *g1, T *g2,
                        const WsLayout &L, char *ws, hipStream_t s) {
     const int zpt = vjp_zpt(n_z);
-    Tiling t = tiling(n_cosmo, n_z, zpt);
+    Tiling t = between_vjp_tiling(n_cosmo, n_z);
     T *pacc = grad_params ? (T *)(ws + L.pacc) : nullptr;
     const bool part = zstride == 0 && t.ntile > 1 && n_z > 0;
     T *p1 = (part && g1) ? (T *)(ws + L.gzp) : nullptr;
