@@ -1214,7 +1214,8 @@ int launch_between(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z1,
 template <typename T>
 int launch_jac(int kind, const CosmoRec *recs, int64_t n_cosmo, const T *z, int64_t n_z, int64_t zstride, T *out,
                T *jac, int32_t *info, hipStream_t s) {
-    Tiling t = tiling(n_cosmo, n_z);
+    // tiles of up to 24 cosmologies (1% faster than 16 on 256 x 1e6; the forward keeps 16)
+    Tiling t = tiling(n_cosmo, n_z, 1, 24);
     dim3 grid((unsigned)t.nzb, (unsigned)t.ntile), block(kBlock);
 #define COSMO_JAC(K) \
     hipLaunchKernelGGL((k_jac<T, K>), grid, block, 0, s, recs, n_cosmo, z, n_z, zstride, out, jac, info, t.ct, t.nzb)
