@@ -209,7 +209,7 @@ int cosmo_distance_vjp(cosmo_kind kind, cosmo_dtype dt, const double *params,
  * workspace.  It calls no hipMalloc, hipFree or other allocating routine; the
  * caller passes every input and output as in cosmo_distance_vjp.
  *  - The array holds COSMO_NOALLOC_SCRATCH_BYTES per GPU.  A call needs the record
- *    table (under 1 KB per cosmology); with grad_params, 44 B (FP32) or 88 B (FP64)
+ *    table (1.2 KB per cosmology); with grad_params, 44 B (FP32) or 88 B (FP64)
  *    per cosmology per 512 redshifts (per 64 redshifts when n_z < 8192); with a
  *    shared-z grad_z and more than one tile of cosmologies (tiles of up to 8),
  *    one dtype element per redshift per tile.  It fits whenever
