@@ -144,7 +144,8 @@ __device__ __forceinline__ void t_args_between(const LaneConst<Q> &k, Q z1, Q z2
     t_args_sides<Q, PAIR>(k, a, b, dz, o);
 }
 
-// ---------------------------------------------------------------- adjoint (D_C family)
+// ---------------------------------------------------------------- limits with reciprocals
+// (the adjoints' chain, and the FP32 time coordinate's FP64 arguments)
 // One limit with the reciprocals the chain needs (square roots as v rsqrt(v), as in
 // build_u's INV form): it2 = 1/t^2, i0 = 1/n0^2, i1 = 1/n1^2 (PAIR: the complex
 // 1/(x - rho_1)), i2 = 1/n2^2, and ie = 1/(t n0 |n1|^2) (PAIR) or 1/(t n0 n1 n2), so that
@@ -309,6 +310,7 @@ __device__ __forceinline__ T eval_between(const CosmoRec &r, T z1, T z2) {
 }
 
 
+// ---------------------------------------------------------------- adjoint (D_C family)
 // chi(z1, z2)/D_H and its partials in the root parameters (sigma, rho_0, rho_1 [re, im]
 // or rho_1, rho_2) at fixed beta, through dR_F/d(U_m^2) = -R_D(., ., U_m^2)/6 (eq. 2.10)
 // and the square roots of both limits (each U_m = T1_m + T2_m, T1 led by the upper

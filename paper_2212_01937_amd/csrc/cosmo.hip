@@ -613,6 +613,9 @@ __device__ __forceinline__ void between_vjp_cosmo(const CosmoRec &r, int64_t c, 
     }
 }
 
+// Occupancy of the between-limit adjoint: the compiler's allocation (the FP32 time
+// coordinate's root-chain pass takes 102 VGPRs, four waves; held to five waves it spills
+// vector registers to scratch).
 template <typename T, int KIND> constexpr int between_min_waves() { return 1; }
 
 // Two passes over the (cosmology tile, z block) pairs: PASS 0 takes the cosmologies whose
