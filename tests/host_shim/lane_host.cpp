@@ -19,6 +19,46 @@ extern "C" void host_eval(const double *prm, int kind, int dt, const double *z, 
     }
 }
 
+// The FP32 time coordinate's FP64 square roots: sqrt_nr from the FP32 root v rsqrt(v) for
+// n arguments; and one finite limit's FP64 sides (side_at_mixed) of cosmology prm at
+// float z[i]: out[12 i ..] = (t, n0, n1re, n1im, n1abs, n2) and the same from FP64
+// square roots of the record's constants.
+extern "C" void host_sqrt_nr(const double *x, long n, double *out) {
+    for (long i = 0; i < n; ++i) {
+        const float xf = (float)x[i], rt = Fp<float>::rsqrt(xf);
+        out[i] = sqrt_nr(x[i], xf * rt, rt);
+    }
+}
+extern "C" void host_side_mixed(const double *prm, const double *z, long n, double *out) {
+    CosmoRec r;
+    setup_cosmo(prm, r);
+    const LaneConst<double> &k = r.d;
+    for (long i = 0; i < n; ++i) {
+        double *o = out + 12 * i;
+        const float zf = (float)z[i];
+        const double zd = (double)zf;
+        if (r.pair) {
+            Side<double, true> d; SideG<float, true> g;
+            side_at_mixed<true>(r.d, r.f, zf, d, g);
+            o[0] = d.t; o[1] = d.n0; o[2] = d.n1re; o[3] = d.n1im; o[4] = d.n1abs; o[5] = d.n2;
+        } else {
+            Side<double, false> d; SideG<float, false> g;
+            side_at_mixed<false>(r.d, r.f, zf, d, g);
+            o[0] = d.t; o[1] = d.n0; o[2] = d.n1re; o[3] = d.n1im; o[4] = d.n1abs; o[5] = d.n2;
+        }
+        // FP64 references from the same record: correctly rounded square roots
+        o[6] = __builtin_sqrt(k.yt2 - k.sigma * zd);
+        o[7] = __builtin_sqrt(zd + k.w0);
+        if (r.pair) {
+            double ab;
+            const cx<double> n1 = csqrt(mkc(zd + k.w1re, k.w1im), ab);
+            o[8] = n1.re; o[9] = n1.im; o[10] = ab; o[11] = 0.0;
+        } else {
+            o[8] = __builtin_sqrt(zd + k.w1re); o[9] = 0.0; o[10] = 0.0; o[11] = __builtin_sqrt(zd + k.w2);
+        }
+    }
+}
+
 // R_C(x, y) and R_D(y, y, x) (rc_rd_r) for n pairs; out[2 i ..] = (rc, rd).  dt: 0 FP32
 // (the host stand-in for the wave vote is the lane's own test), 1 FP64.
 extern "C" void host_rc_rd(int dt, const double *x, const double *y, long n, double *out) {

@@ -146,6 +146,72 @@ def test_rc_with_x_derivative_matches_oracle(libs, model):
             assert np.max(np.abs(out[1::2] - rd) / rd) <= tol, (dt, model)
 
 
+@pytest.mark.parametrize("model", ["exact", "noisy"])
+def test_refined_square_roots_of_the_time_coordinate(libs, model):
+    """sqrt_nr (the FP32 root refined by one Newton step with an FP32 correction) against
+    the correctly rounded FP64 root: within 1e-13 relative over 1e-6..1e6, also with the
+    FP32 reciprocal square root off by an ulp ('noisy').  side_at_mixed's FP64 sides of one
+    limit (sqrt(1 - sigma x), sqrt(x - rho_n), a pair's complex root and |x - rho_1|)
+    against FP64 square roots of the same record's constants (pairs and three real roots;
+    1e-13, 5e-13 'noisy'),
+    and, on the well separated roots of the large-batch and non-flat cosmologies, against
+    their definitions from the oracle's 50-digit roots."""
+    lib = libs[model]
+    x = 10.0 ** np.random.default_rng(13).uniform(-6, 6, 5000)
+    out = np.zeros_like(x)
+    lib.host_sqrt_nr(x.ctypes.data_as(ctypes.c_void_p), ctypes.c_long(x.size), out.ctypes.data_as(ctypes.c_void_p))
+    assert np.max(np.abs(out - np.sqrt(x)) / np.sqrt(x)) < 1e-13
+    z = np.concatenate([np.linspace(0.0, 20.0, 400), 10.0 ** np.linspace(-5, 3, 400)]).astype(np.float32).astype(np.float64)
+    xx = 1.0 + z
+    p5, _ = workloads.config5(n_cosmo=4, n_z=8)
+    p2, _ = workloads.config2(n_cosmo=4, n_z=8)
+    p4, _, _ = workloads.config4(n_per_family=8, n_z=8)  # families C and D: three real roots
+    for which, params in (("separated", np.concatenate([p5, p2])), ("record only", p4[16:32:3])):
+        for prm in params:
+            o = np.zeros(12 * z.size)
+            lib.host_side_mixed(np.ascontiguousarray(prm).ctypes.data_as(ctypes.c_void_p),
+                                z.ctypes.data_as(ctypes.c_void_p), ctypes.c_long(z.size),
+                                o.ctypes.data_as(ctypes.c_void_p))
+            o = o.reshape(-1, 12)
+            got, rec = o[:, :6], o[:, 6:]
+            scale = np.maximum(np.abs(rec), 1e-300)
+            used = np.abs(rec) > 0
+            # one Newton step from a root within ~1 ulp of FP32: ~1e-14, up to ~2e-13 where
+            # the FP32 estimates are themselves 1 ulp off ('noisy')
+            assert np.max((np.abs(got - rec) / scale)[used]) < (1e-13 if model == "exact" else 5e-13), (which, prm)
+            if which == "record only":
+                continue
+            sigma, rho = oracle_roots(prm)
+            t = np.sqrt(1.0 - sigma * xx)
+            assert np.max(np.abs(got[:, 0] - t) / t) < 1e-12
+            n0 = np.sqrt(xx - rho[0].real)
+            assert np.max(np.abs(got[:, 1] - n0) / n0) < 1e-12
+            n1 = got[:, 2] + 1j * got[:, 3]
+            ref = np.sqrt((xx - rho[1]).astype(complex))
+            ref = np.where(np.sign(ref.imag) == np.sign(n1.imag), ref, np.conj(ref))
+            assert np.max(np.abs(n1 - ref) / np.abs(ref)) < 1e-12
+            assert np.max(np.abs(got[:, 4] - np.abs(xx - rho[1])) / np.abs(xx - rho[1])) < 1e-12
+
+
+def oracle_roots(prm):
+    """sigma = 1/x_l (x_l the radiation root of P(x) = Or x^4 + Om x^3 + Ok x^2 + OL, the
+    real root of largest modulus; 0 without radiation) and the roots rho_n of the cubic
+    factor (a real root, then a pair with positive imaginary part first), from the
+    oracle's 50-digit roots."""
+    x = oracle.roots(prm[None, :])[0] + 1.0
+    x = x[np.isfinite(x)]
+    order = np.argsort(-np.abs(x))
+    if prm[3] > 0:
+        sigma, rest = 1.0 / x[order[0]].real, list(x[order[1:]])
+    else:
+        sigma, rest = 0.0, list(x)
+    cplx = [v for v in rest if abs(v.imag) > 1e-12 * max(1.0, abs(v))]
+    assert len(cplx) == 2, "a root pair is expected here"
+    r0 = [v for v in rest if abs(v.imag) <= 1e-12 * max(1.0, abs(v))][0]
+    r1 = max(cplx, key=lambda v: v.imag)
+    return sigma, [complex(r0.real, 0.0), r1, r1.conjugate()]
+
+
 KIND_BTW = {"DC": 0, "DM": 1, "T": 4, "DA": 6}
 
 
