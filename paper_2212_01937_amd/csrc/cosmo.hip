@@ -498,13 +498,13 @@ __device__ __forceinline__ void vjp_cosmo(const CosmoRec &r, int64_t c, const T 
     }
 }
 
-// Occupancy: the comoving-distance-family adjoint is held to 64 VGPRs, eight waves per
-// SIMD, on the FP32 path (the root-chain loop fits; measured 3-6% faster on the headline
-// workload than six waves at 80 VGPRs) and to 128, four waves, on the FP64 path (its
-// coefficients in scalar registers, see kc); T, X and the volume keep the compiler's
-// allocation.
+// Occupancy: the comoving-distance-family adjoint is held to seven waves per SIMD (72
+// VGPRs) on the FP32 path (on the headline workload as fast as eight waves at 64 VGPRs
+// with the value output and 2-3% faster without it, with fewer spills; six waves at 80
+// VGPRs were 3-6% slower) and to 128 VGPRs, four waves, on the FP64 path (its coefficients
+// in scalar registers, see kc); T, X and the volume keep the compiler's allocation.
 template <typename T, int KIND> constexpr int adjoint_min_waves() {
-    return (KIND == COSMO_T || KIND == COSMO_X || KIND == COSMO_VC) ? 1 : (sizeof(T) == 4 ? 8 : 4);
+    return (KIND == COSMO_T || KIND == COSMO_X || KIND == COSMO_VC) ? 1 : (sizeof(T) == 4 ? 7 : 4);
 }
 
 template <typename T, int KIND, int ZPT, bool LIKE>
@@ -718,12 +718,13 @@ __global__ __launch_bounds__(kBlock, (between_min_waves<T, KIND>())) void k_betw
 
 // Materialised Jacobian: per lane the observable and d out / d(H0, Om0, OL0, Or0, z),
 // written as five planes jac[q][c][i]; the root-space partials are contracted with the
-// root Jacobian per lane, in FP64.  Grid as k_forward.
-// Occupancy of the materialised Jacobian: the FP32 comoving-distance family at 64 VGPRs
-// (eight waves; the lane fits without spilling); the others keep the compiler's
-// allocation.
+// root Jacobian per lane (jac_contract: FP32 lanes in FP32 with a cancellation check).
+// Grid as k_forward, on tiles of up to 24 cosmologies.
+// Occupancy of the materialised Jacobian: the FP32 comoving-distance family held to seven
+// waves (65 VGPRs, no spills; at eight, 64 VGPRs, two scalar registers spill and it ran no
+// faster); the others keep the compiler's allocation.
 template <typename T, int KIND> constexpr int jac_min_waves() {
-    return (sizeof(T) == 4 && KIND != COSMO_T && KIND != COSMO_X) ? 8 : 1;
+    return (sizeof(T) == 4 && KIND != COSMO_T && KIND != COSMO_X) ? 7 : 1;
 }
 
 // The lane's partials contracted with the root Jacobian (app. A) per parameter, with the
