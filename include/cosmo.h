@@ -148,11 +148,14 @@ int cosmo_distance_between(cosmo_kind kind, cosmo_dtype dt, const double *params
 
 /* cosmo_distance_between_vjp -- adjoint of cosmo_distance_between for COSMO_DC,
  * COSMO_DM, COSMO_DA and COSMO_T (other kinds: COSMO_E_KIND).  The distance kinds through
- * the Carlson derivatives of eq. 3.7 (eq. 2.10) with both limits' square roots per
- * element and the root Jacobian (app. A); T (value by eq. 3.8) with parameter
- * derivatives by the Leibniz rule (eq. 2.4 differentiated under the integral), by
- * Gauss-Legendre quadrature in s = (1+z)^(-1/2), which is finite for z2 = inf; limits
- * by the fundamental theorem of calculus.  cot: [n_cosmo][n_z] of dtype.
+ * the Carlson derivatives of eq. 3.7 (eq. 2.10) and T through those of eq. 3.8 (R_F,
+ * R_J and R_C partials, eqs. 2.10-2.11), with both limits' square roots per element and
+ * the root Jacobian (app. A).  Near-multiple-root cosmologies, and for T with z2 = inf
+ * a radiation root too small for the chain (|sigma| below 1e-4 FP32 / 1e-9 FP64, or no
+ * radiation), take the parameter derivatives by the Leibniz rule (eq. 2.4
+ * differentiated under the integral; for T by Gauss-Legendre quadrature in
+ * s = (1+z)^(-1/2), finite for z2 = inf).  Limits by the fundamental theorem of
+ * calculus.  cot: [n_cosmo][n_z] of dtype.
  * out        : nullable; the observable from the same pass.
  * grad_params: [n_cosmo][4] FP64, sum over elements of cot * d out/d(H0, Om0, OL0,
  *              Or0); nullable.  For the distance kinds NaN for a cosmology with an
